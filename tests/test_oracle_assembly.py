@@ -1,0 +1,102 @@
+"""Pins of the oracle's assembly (weak form of Section 2.1): K against central differences
+of f_int, balance of forces and moments, rigid-body invariances, symmetry, a patch test,
+and the body-force term."""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+from tests.helpers import node_xyz, setup, tiny_workload
+
+
+def _problem(kind, jit, sy, amp=2e-3, Fn_std=0.02):
+    w = tiny_workload(kind, E=1e4, nu=0.3, sy=sy, Fn_std=Fn_std)
+    m, ps = setup(w, jitter=jit)
+    s = W.make_state(w, ps)
+    u = W.make_u(w, m.nodes(), amp=amp)
+    return w, m, ps, s, u
+
+
+def _K(m, K):
+    rp, col = m.csr()
+    n = 3 * m.counts()["n_node"]
+    return sp.csr_matrix((K, col, rp), shape=(n, n))
+
+
+CASES = [("sphere", None, math.inf), ("sphere", 0, math.inf), ("cone", 1, 2.0), ("box", 2, 2.0), ("sphere", 3, 40.0)]
+
+
+@pytest.mark.parametrize("kind,jit,sy", CASES)
+def test_tangent_is_jacobian_of_internal_force(kind, jit, sy):
+    w, m, ps, s, u = _problem(kind, jit, sy)
+    out = m.assemble(s, u)
+    if math.isfinite(sy) and sy < 10:
+        assert out["plastic"].mean() > 0.9
+    K = _K(m, out["K"])
+    rng = np.random.default_rng(1)
+    for _ in range(3):
+        d = rng.normal(size=u.size)
+        h = 1e-7
+        fp = m.assemble(s, u + h * d, want_K=False)["f_int"]
+        fm = m.assemble(s, u - h * d, want_K=False)["f_int"]
+        fd = (fp - fm) / (2 * h)
+        kd = K @ d
+        assert np.abs(fd - kd).max() < 1e-6 * np.abs(kd).max()
+
+
+@pytest.mark.parametrize("kind,jit,sy", CASES)
+def test_balance_invariances_symmetry(kind, jit, sy):
+    w, m, ps, s, u = _problem(kind, jit, sy)
+    out = m.assemble(s, u)
+    f = out["f_int"].reshape(-1, 3)
+    K = _K(m, out["K"])
+    scale = np.abs(f).max()
+    assert np.abs(f.sum(axis=0)).max() < 1e-12 * np.abs(f).sum()           # sum of forces
+    xc = node_xyz(w, m.nodes()) + u.reshape(-1, 3)
+    mom = np.cross(xc, f).sum(axis=0)
+    assert np.abs(mom).max() < 1e-12 * np.abs(f).sum()                      # moment balance
+    Kmax = np.abs(out["K"]).max()
+    for c in range(3):
+        t = np.zeros_like(u).reshape(-1, 3)
+        t[:, c] = 1.0
+        assert np.abs(K @ t.ravel()).max() < 1e-11 * Kmax                   # rigid translation
+    Wm = np.array([[0, -0.3, 0.2], [0.3, 0, -0.7], [-0.2, 0.7, 0]])
+    rotv = (xc @ Wm.T).ravel()
+    assert np.abs(K @ rotv - (f @ Wm.T).ravel()).max() < 1e-10 * scale      # infinitesimal rotation
+    assert abs(K - K.T).max() < 1e-12 * Kmax                                # symmetric
+
+
+def test_patch_test_interior_nodes_unloaded():
+    """Affine displacement on the fully populated lower half of the C0 mesh gives a uniform
+    stress, and interior nodes receive no net internal force."""
+    w = W.get("c0")
+    m, ps = setup(w)
+    s = W.make_state(w, ps)
+    nd = m.nodes()
+    X = node_xyz(w, nd)
+    A = np.array([[1e-3, 2e-4, -3e-4], [5e-4, -2e-3, 1e-4], [-1e-4, 3e-4, 4e-3]])
+    u = (X @ A.T).ravel()
+    out = m.assemble(s, u, want_K=False)
+    sig = out["sigma"]
+    assert np.abs(sig - sig[:, :1]).max() < 1e-10 * np.abs(sig).max()
+    f = out["f_int"].reshape(-1, 3)
+    interior = (nd[:, 0] > 0) & (nd[:, 0] < 8) & (nd[:, 1] > 0) & (nd[:, 1] < 8) & (nd[:, 2] > 0) & (nd[:, 2] < 4)
+    assert interior.sum() == 7 * 7 * 3
+    assert np.abs(f[interior]).max() < 1e-12 * np.abs(f).max()
+
+
+@pytest.mark.parametrize("kind,jit", [("sphere", None), ("cone", 1)])
+def test_external_force_total(kind, jit):
+    from oracle.oracle import residual
+    w, m, ps, s, u = _problem(kind, jit, math.inf)
+    fe = m.external_force(s).reshape(-1, 3)
+    g = np.array([0.0, 0.0, -9.81])
+    assert np.abs(fe.sum(axis=0) - g * s["mass"].sum()).max() < 1e-13 * np.abs(g).max() * s["mass"].sum()
+    fi = m.assemble(s, u, want_K=False)["f_int"]
+    d = W.dirichlet_dofs(m.nodes())
+    r, rn = residual(fi, fe.ravel(), d)
+    ref = np.where(d == 1, 0.0, fi - fe.ravel())
+    assert np.array_equal(r, ref)
+    assert abs(rn - np.sqrt(np.sum(ref * ref))) < 1e-15 * rn

@@ -1,0 +1,131 @@
+"""Workload definitions (mesh criterion, point layout, material, seeds).
+
+The refinement criterion follows the paper's adaptive strategy (Section 5, Steps 1-3): a
+rigid body, a distance band dx_region around it, a base level and a maximum level. The
+shapes below are synthetic stand-ins for the paper's experiments (Section 6.4 cone
+penetration, Section 6.5 plough/anchor-like moving tool); no experimental data is used.
+
+Body kinds and their 8 parameters:
+  0 none
+  1 sphere       [cx, cy, cz, R]
+  2 cone+shaft   [axis_x, axis_y, z_apex, R_shaft, tan(half apex angle), z_top]
+  3 box          [x0, x1, y0, y1, z0, z1]
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Callable, Optional
+
+BODY_NONE, BODY_SPHERE, BODY_CONE, BODY_BOX = 0, 1, 2, 3
+GRAVITY = (0.0, 0.0, -9.81)
+
+
+@dataclass
+class Workload:
+    name: str
+    lo: tuple
+    base: tuple
+    h0: float
+    lvl_base: int
+    lvl_max: int
+    body_kind: int
+    body: tuple
+    dx_region: float
+    # points per axis in a leaf of the given level
+    ppa: Callable[[int], int]
+    E: float
+    nu: float
+    sy: float
+    Fn_std: float          # std of the I + N(0, s^2) perturbation of F_n (0: F_n = I)
+    seed_state: int
+    seed_u: int
+    seed_lambda: int
+    keep: Optional[Callable] = None   # extra filter on point centres (x, y, z arrays) -> bool mask
+    drop_inside_body: bool = True
+    note: str = ""
+    extra: dict = field(default_factory=dict)
+
+    def crit(self) -> dict:
+        body = list(self.body) + [0.0] * (8 - len(self.body))
+        return dict(lo=tuple(float(v) for v in self.lo), base=tuple(int(v) for v in self.base),
+                    h0=float(self.h0), lvl_base=int(self.lvl_base), lvl_max=int(self.lvl_max),
+                    body_kind=int(self.body_kind), body=tuple(float(v) for v in body),
+                    dx_region=float(self.dx_region))
+
+    @property
+    def h_min(self) -> float:
+        return self.h0 * 2.0 ** (-(self.lvl_max - self.lvl_base))
+
+    def lattice_dims(self):
+        s = 1 << (self.lvl_max - self.lvl_base)
+        return tuple(int(b) * s for b in self.base)
+
+
+def _two(_lvl):
+    return 2
+
+
+C0 = Workload(
+    name="c0_uniform_elastic",
+    lo=(0.0, 0.0, 0.0), base=(8, 8, 8), h0=0.125, lvl_base=3, lvl_max=3,
+    body_kind=BODY_NONE, body=(), dx_region=0.0, ppa=_two,
+    E=1e4, nu=0.3, sy=math.inf, Fn_std=0.0, seed_state=0, seed_u=0, seed_lambda=3,
+    keep=lambda x, y, z: z < 0.5, drop_inside_body=False,
+    note="unit cube, 8^3 level-3 cells, 2x2x2 points in the lower half, Hencky elastic",
+)
+
+C1 = Workload(
+    name="c1_sphere_vm",
+    lo=(0.0, 0.0, 0.0), base=(16, 16, 16), h0=1.0 / 16, lvl_base=4, lvl_max=7,
+    body_kind=BODY_SPHERE, body=(0.5, 0.5, 0.6, 0.1), dx_region=0.05, ppa=_two,
+    E=1e5, nu=0.3, sy=50.0, Fn_std=0.02, seed_state=1, seed_u=1, seed_lambda=3,
+    keep=lambda x, y, z: z < 0.6,
+    note="2:1-balanced octree refined to level 7 around a sphere; soil below z=0.6",
+)
+
+# same mesh and points as C1 with a yield stress near the 70th percentile of the trial
+# von Mises stress, so that only part of the points yield
+C1B = Workload(**{**C1.__dict__, "name": "c1b_sphere_vm_partial", "sy": 1.3e4,
+                  "note": "C1 with sigma_y = 1.3e4 (partial yielding)"})
+
+_TAN30 = math.tan(math.radians(30.0))
+
+
+def _cpt_ppa(lvl):
+    return 3 if lvl >= 8 else 2
+
+
+C2 = Workload(
+    name="c2_cpt_vm",
+    lo=(0.0, 0.0, 0.0), base=(16, 16, 32), h0=1.0 / 16, lvl_base=4, lvl_max=8,
+    body_kind=BODY_CONE, body=(0.5, 0.5, 1.0, 0.02, _TAN30, 2.0), dx_region=0.04, ppa=_cpt_ppa,
+    E=2e5, nu=0.3, sy=100.0, Fn_std=0.05, seed_state=2, seed_u=2, seed_lambda=3,
+    note="cone-penetrometer-shaped workload: 60-degree cone tip r=0.02 at depth 1.0, shaft to the top",
+)
+
+C3 = Workload(**{**C2.__dict__, "name": "c3_cpt_adjoint",
+                 "note": "adjoint on the C2 mesh/points, lambda ~ N(0,1)"})
+
+
+def _c4_ppa(lvl):
+    return 2
+
+
+C4 = Workload(
+    name="c4_plough_trail",
+    lo=(0.0, 0.0, 0.0), base=(32, 16, 12), h0=0.125, lvl_base=5, lvl_max=9,
+    body_kind=BODY_BOX, body=(3.20, 3.50, 0.95, 1.05, 1.3, 1.5), dx_region=0.05, ppa=_c4_ppa,
+    E=5e4, nu=0.3, sy=20.0, Fn_std=0.02, seed_state=4, seed_u=4000, seed_lambda=4,
+    note="moving box tool; refined-point trail (never derefined) along the swept path",
+    extra=dict(trail_x=(0.2, 3.2), trail_band=0.075, trail_ppa=4),
+)
+
+CONFIGS = {w.name: w for w in (C0, C1, C1B, C2, C3, C4)}
+ALIASES = {"c0": C0, "c1": C1, "c1b": C1B, "c2": C2, "c3": C3, "c4": C4}
+
+
+def get(name: str) -> Workload:
+    if name in ALIASES:
+        return ALIASES[name]
+    return CONFIGS[name]

@@ -1,0 +1,195 @@
+/*
+ * mpm_gimp.h — C ABI of the MI355X (gfx950) octree GIMP material point assembly library.
+ *
+ * The library builds a 2:1-balanced octree around a rigid body, resolves hanging nodes by
+ * constraints, orders material points by Morton key, and assembles — per Newton iteration —
+ * the internal force vector f_int and the tangent K (fixed-pattern CSR) of the implicit
+ * updated-Lagrangian GIMP material point method, plus the adjoint of f_int with respect to
+ * the per-point material parameters. Paper references are to "An implicit octree-based
+ * adaptive Material Point Method" (Bird, Coombs, Augarde, Pretti, O'Hare).
+ *
+ * Conventions
+ *   - Every call returns an int32 status: MPM_OK (0) or a negative MPM_E* code. On error no
+ *     output is guaranteed; mpm_last_error() gives a message and mpm_last_error_index() the
+ *     first offending point (sorted position) or node, or -1.
+ *   - Per-point arrays are structure-of-arrays, component-major: a[c * n + p].
+ *   - Symmetric 3x3 tensors are stored as 6 components (xx, yy, zz, xy, yz, xz); general 3x3
+ *     tensors as 9 components, row-major (xx, xy, xz, yx, ...).
+ *   - DOF numbering: dof = 3 * node + c (c = 0,1,2 for x,y,z) over independent nodes in
+ *     ascending Morton key of their integer lattice coordinates.
+ *   - "device" pointers are HIP device memory (e.g. torch tensors on the GPU); they stay
+ *     owned by the caller unless stated. All device work is ordered on the caller's
+ *     hipStream_t `stream` (NULL = default stream). A mesh handle must not be used
+ *     concurrently from two streams.
+ *   - No exception crosses this interface. The library is not re-entrant for one handle.
+ */
+#ifndef MPM_GIMP_H
+#define MPM_GIMP_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define MPM_OK 0
+#define MPM_EARG -1        /* bad argument (null pointer, size mismatch, bad precision ...) */
+#define MPM_EDET -2        /* det(dF) <= 0 or a non-positive eigenvalue of the trial b */
+#define MPM_ESTENCIL -3    /* point domain needs more than one leaf boundary per axis, or
+                              lattice/leaf counts exceed the key widths */
+#define MPM_EOUTSIDE -4    /* point domain not inside the mesh box */
+#define MPM_ETREE -5       /* octree inconsistency (unbalanced, constraint chain) */
+#define MPM_EHIP -6        /* HIP runtime error */
+#define MPM_ENONFINITE -7  /* non-finite input */
+
+/* arithmetic of mpm_assemble / mpm_assemble_adjoint */
+#define MPM_F64 0          /* everything in FP64 */
+#define MPM_F32K 1         /* basis, stress, tangent and K values in FP32; f_int, residual and
+                              its norm accumulated in FP64 (adjoint: FP32 point arithmetic,
+                              FP64 outputs) */
+
+/* body kinds for the refinement criterion */
+#define MPM_BODY_NONE 0    /* no refinement */
+#define MPM_BODY_SPHERE 1  /* body = {cx, cy, cz, R} */
+#define MPM_BODY_CONE 2    /* cone tip + cylindrical shaft on a vertical axis:
+                              body = {axis_x, axis_y, z_apex, R, tan(half apex angle), z_top} */
+#define MPM_BODY_BOX 3     /* axis-aligned box: body = {x0, x1, y0, y1, z0, z1} */
+
+/* Refinement criterion (Section 5, Steps 1-3): leaves coarser than lvl_max that meet the
+ * closed body (Step 1) or have a vertex within dx_region of it (Step 2) are split (Step 3);
+ * rounds repeat until nothing is marked, each followed by 2:1 balance across faces and
+ * edges (at most one hanging node per edge or face). The mesh box is lo + [0, base*h0];
+ * base cells have level lvl_base; a level-l leaf has side h0 * 2^(lvl_base - l).
+ * Ties of the distance predicates are inclusive up to a relative 1e-12 slack. */
+typedef struct {
+  double lo[3];
+  int32_t base[3];
+  double h0;
+  int32_t lvl_base, lvl_max;
+  int32_t body_kind;
+  double body[8];
+  double dx_region;
+} mpm_refine_t;
+
+typedef struct mpm_mesh mpm_mesh_t;
+
+typedef struct {
+  int64_t n_leaf;        /* leaves (elements) */
+  int64_t n_node;        /* independent nodes */
+  int64_t n_hang;        /* hanging (constrained) nodes */
+  int64_t n_dof;         /* 3 * n_node */
+  int64_t nnz;           /* CSR entries */
+  int64_t n_point;       /* material points */
+  int64_t n_straddle;    /* points whose domain overlaps more than one leaf */
+  int64_t n_active_rows; /* DOF rows with at least one entry */
+  int32_t max_support;   /* largest point support (nodes) */
+  int32_t lattice[3];    /* finest-lattice cells per axis */
+  double h_min;          /* finest cell size */
+} mpm_mesh_info_t;
+
+/* Library-owned device arrays, valid until mpm_mesh_free (read only). */
+typedef struct {
+  const int32_t* leaf;          /* [n_leaf][4] anchor (finest-lattice units) x,y,z, level;
+                                   ascending Morton key of the anchor */
+  const int32_t* node_ijk;      /* [n_node][3] lattice coordinates of independent nodes */
+  const int32_t* hang_ijk;      /* [n_hang][3] hanging nodes, ascending Morton key */
+  const int32_t* hang_support;  /* [n_hang][4] independent node ids of S(n), -1 padded */
+  const double* hang_weight;    /* [n_hang][4] phi_{i K_n}(x_n): 1/2 (edge) or 1/4 (face) */
+  const int32_t* hang_owner;    /* [n_hang] K_n (coarsest element the node hangs on; ties:
+                                   lowest Morton rank) */
+  const int32_t* cell_nodes;    /* [n_leaf][8] I(K): slot k = vertex k if independent, else
+                                   the parent corner that replaces it */
+  const double* cell_cmat;      /* [n_leaf][8][8] C_K[vertex][slot]: phi~_slot = sum_vertex
+                                   C_K[vertex][slot] phi_vertex (Section 3.1, hanging node basis) */
+  const int64_t* perm;          /* [n_point] sorted position -> original index */
+  const int32_t* point_leaf;    /* [n_point] sorted position -> leaf containing the centre */
+  const uint8_t* point_nleaf;   /* [n_point] sorted position -> leaves overlapped */
+  const int64_t* row_ptr;       /* [n_dof + 1] */
+  const int32_t* col;           /* [nnz], ascending within each row */
+} mpm_mesh_arrays_t;
+
+/* Material point state, SoA device arrays in SORTED point order (see mpm_permute).
+ * Updated-Lagrangian: the step starts from F_n (J_n = det F_n) and the elastic left
+ * Cauchy-Green tensor b_n; V_n is the point volume at the start of the step and also
+ * (generated configs) 8 l1 l2 l3 of the GIMP domain. Elastic points: sy = +inf. */
+typedef struct {
+  const double* x;    /* [3][n] domain centres */
+  const double* l;    /* [3][n] domain half side lengths */
+  const double* vol;  /* [n] V_n */
+  const double* mass; /* [n] m_p */
+  const double* Jn;   /* [n] det F_n */
+  const double* bn;   /* [6][n] elastic left Cauchy-Green b_n */
+  const double* Fn;   /* [9][n] F_n, only read when F_new is requested (may be NULL) */
+  const double* E;    /* [n] Young's modulus */
+  const double* nu;   /* [n] Poisson's ratio */
+  const double* sy;   /* [n] uniaxial yield stress (von Mises, perfect plasticity) */
+  double g[3];        /* body acceleration */
+} mpm_state_t;
+
+/* Build the octree from the criterion, enumerate nodes, hanging nodes and constraints
+ * (Section 3.1), sort the points by (leaf containing the centre, Morton code at h_min/16,
+ * original index), find the leaves each GIMP domain overlaps with positive volume
+ * (Section 3.2; overlaps thinner than 1e-12 of the domain side do not count), and build the
+ * CSR pattern: a node pair is coupled iff some point's support holds both; each coupled
+ * pair is a dense 3x3 block; rows of unsupported nodes are empty.
+ *   x, l: [3][n] host OR device arrays (detected), caller-owned; n may be 0 (mesh only).
+ *   *out_mesh: new library-owned handle (free with mpm_mesh_free).
+ * Host work: refinement, balance, numbering, CSR pattern. Device work: Morton keys,
+ * radix sort, point-to-leaf search and overlap classification. */
+int32_t octree_build(const mpm_refine_t* crit, const double* x, const double* l, int64_t n, void* stream,
+                     mpm_mesh_t** out_mesh);
+int32_t mpm_mesh_info(const mpm_mesh_t* mesh, mpm_mesh_info_t* out);
+int32_t mpm_mesh_arrays(const mpm_mesh_t* mesh, mpm_mesh_arrays_t* out);
+void mpm_mesh_free(mpm_mesh_t* mesh);
+
+/* Re-order points of an existing mesh (device only): Morton keys, radix sort and leaf
+ * search for n device points x [3][n] (must equal the mesh's point count). Writes perm_out
+ * [n] (sorted position -> original index) and leaf_out [n] (sorted position -> leaf);
+ * the mesh's own perm is not changed. Timed as the point-to-cell step of a re-sort. */
+int32_t mpm_point_sort(const mpm_mesh_t* mesh, const double* x, int64_t n, int64_t* perm_out, int32_t* leaf_out,
+                       void* stream);
+
+/* dst[c][p] = src[c][perm[p]] for c < ncomp (device, double): brings original-order state
+ * into sorted order. perm = the mesh's perm when NULL. */
+int32_t mpm_permute(const mpm_mesh_t* mesh, const int64_t* perm, const double* src, double* dst, int32_t ncomp,
+                    void* stream);
+
+/* Body force of the weak form (Section 2.1, eq. MPMweak): f_ext[v] = sum_p S_vp m_p g,
+ * FP64 device output [n_dof] (overwritten). */
+int32_t mpm_external_force(const mpm_mesh_t* mesh, const mpm_state_t* s, double* f_ext, void* stream);
+
+/* One Newton-iteration assembly (Section 2.1 weak form, discrete GIMP basis of Section 3.2
+ * eq. GIMP numerical, hanging node basis of Section 3.1, Hencky / von Mises of Section 2.2):
+ * per point, with u the nodal displacement of the step (device [n_dof]):
+ *   S_vp, grad S_vp (one-point rule per domain/leaf overlap); H = sum_v u_v (x) grad S_v;
+ *   dF = I + H; b_tr = dF b_n dF^T; principal logarithmic strains; radial return onto
+ *   sqrt(3 J2) = sy; tau; sigma = tau / (det dF J_n); consistent tangent.
+ *   f_int[v] += V sigma grad_x S_v,  K[(a,i),(b,k)] += V grad_x S_a . a_i.k. . grad_x S_b,
+ *   V = det(dF) V_n, grad_x S = dF^-T grad S. K is the exact Jacobian d f_int / d u.
+ * Outputs (device, caller-owned, overwritten):
+ *   f_int [n_dof] FP64; K_vals [nnz] FP64 (MPM_F64) or FP32 (MPM_F32K), may be NULL;
+ *   sigma6 [6][n] FP64 Cauchy stress, may be NULL;
+ *   r [n_dof] = f_int - f_ext with DOFs where dirichlet[dof] != 0 zeroed (f_ext, dirichlet
+ *   may be NULL = zero / none), and rnorm (device, 1 double) = ||r||_2 in FP64; both may be
+ *   NULL; F_new [9][n] = dF F_n and be_new [6][n] updated b_e, may be NULL (commit state).
+ * Synchronises `stream` once at the end to read the device error flag. */
+int32_t mpm_assemble(const mpm_mesh_t* mesh, const mpm_state_t* s, const double* u, int32_t precision,
+                     const double* f_ext, const uint8_t* dirichlet, double* f_int, void* K_vals, double* sigma6,
+                     double* r, double* rnorm, double* F_new, double* be_new, void* stream);
+
+/* Adjoint of the assembly for L = lambda . f_int(u) (lambda: device [n_dof]): per point
+ * dL/dE, dL/dnu, dL/dsy, dL/dV_n (device [n] FP64 each, caller-owned). Gather only (no
+ * atomics); the return map is recomputed, nothing is stored by the forward pass. */
+int32_t mpm_assemble_adjoint(const mpm_mesh_t* mesh, const mpm_state_t* s, const double* u, const double* lambda,
+                             int32_t precision, double* dL_dE, double* dL_dnu, double* dL_dsy, double* dL_dV,
+                             void* stream);
+
+/* last error of the calling thread */
+int32_t mpm_last_error(char* buf, size_t n);
+int64_t mpm_last_error_index(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,728 @@
+// Assembly kernels: fused per-point GIMP basis -> kinematics -> Hencky/von Mises return ->
+// consistent tangent -> per-leaf segmented reduction in LDS -> atomics into f_int and the
+// CSR values; a general kernel for domains overlapping several leaves; body force;
+// residual and its FP64 norm; the adjoint gather.
+#include <algorithm>
+#include <cstring>
+
+#include "point_math.h"
+
+namespace mpm {
+
+int32_t read_error(mpm_mesh* m, hipStream_t st, const char* what);
+LeafGeo make_geo(const mpm_mesh* m);
+
+struct AsmArgs {
+  LeafGeo G;
+  const int32_t* cell_nodes;
+  const int32_t* cell_code;
+  const int32_t* pleaf;
+  const uint8_t* pnleaf;
+  const int64_t* slot;
+  const int32_t* stride;
+  const int64_t* row_ptr;
+  const int32_t* col;
+  const int64_t* strad;
+  const int32_t* strad_leaf;
+  int64_t n, n_strad;
+  mpm_state_t s;
+  const double* u;
+  const double* lam;  // adjoint
+  double* f;
+  void* K;
+  double* sigma;
+  double* Fnew;
+  double* be;
+  double *dE, *dnu, *dsy, *dV;
+  DevErr* err;
+};
+
+__device__ __forceinline__ void raise(DevErr* err, int code, int64_t idx) {
+  if (atomicCAS(&err->code, 0, code) == 0) err->index = (unsigned long long)idx;
+}
+
+// upper-triangle slot blocks in (b outer, a <= b inner) order
+__constant__ int8_t c_blk_a[36] = {0, 0, 1, 0, 1, 2, 0, 1, 2, 3, 0, 1, 2, 3, 4, 0, 1, 2,
+                                   3, 4, 5, 0, 1, 2, 3, 4, 5, 6, 0, 1, 2, 3, 4, 5, 6, 7};
+__constant__ int8_t c_blk_b[36] = {0, 1, 1, 2, 2, 2, 3, 3, 3, 3, 4, 4, 4, 4, 4, 5, 5, 5,
+                                   5, 5, 5, 6, 6, 6, 6, 6, 6, 6, 7, 7, 7, 7, 7, 7, 7, 7};
+
+template <typename T>
+__device__ __forceinline__ void atomic_add_val(T* p, T v) {
+  atomicAdd(p, v);
+}
+
+// Basis of a point over one leaf overlap box, accumulated into the 8 slots of that leaf.
+template <typename T>
+__device__ __forceinline__ void leaf_overlap_basis(const LeafGeo& G, int64_t e, int32_t code, const double x[3],
+                                                   const double l[3], T S[8], T dS[8][3]) {
+  double lo[3], hi[3], h;
+  leaf_bounds(G, e, lo, hi, &h);
+  double ctr[3], wgt = 1.0;
+  for (int a = 0; a < 3; ++a) {
+    const double a0 = x[a] - l[a] > lo[a] ? x[a] - l[a] : lo[a];
+    const double a1 = x[a] + l[a] < hi[a] ? x[a] + l[a] : hi[a];
+    ctr[a] = 0.5 * (a0 + a1);
+    wgt *= (a1 - a0) / (2.0 * l[a]);
+  }
+  T xi[3];
+  for (int a = 0; a < 3; ++a) xi[a] = T((ctr[a] - lo[a]) / h);
+  slot_basis<T>(xi, T(1.0 / h), code, T(wgt), S, dS);
+}
+
+template <typename T>
+__device__ __forceinline__ void load_B(const mpm_state_t& s, int64_t n, int64_t i, T B[3][3]) {
+  const double b0 = s.bn[i], b1 = s.bn[n + i], b2 = s.bn[2 * n + i];
+  const double b3 = s.bn[3 * n + i], b4 = s.bn[4 * n + i], b5 = s.bn[5 * n + i];
+  B[0][0] = T(b0 - 1.0);
+  B[1][1] = T(b1 - 1.0);
+  B[2][2] = T(b2 - 1.0);
+  B[0][1] = B[1][0] = T(b3);
+  B[1][2] = B[2][1] = T(b4);
+  B[0][2] = B[2][0] = T(b5);
+}
+
+// write sigma and (optionally) the committed state of one point
+template <typename T>
+__device__ __forceinline__ void write_point(const AsmArgs& A, int64_t i, const PointMat<T>& P, const T F[3][3],
+                                            double J) {
+  const int64_t n = A.n;
+  if (A.sigma) {
+    const double iJ = 1.0 / J;
+    A.sigma[i] = double(P.tau[0][0]) * iJ;
+    A.sigma[n + i] = double(P.tau[1][1]) * iJ;
+    A.sigma[2 * n + i] = double(P.tau[2][2]) * iJ;
+    A.sigma[3 * n + i] = double(P.tau[0][1]) * iJ;
+    A.sigma[4 * n + i] = double(P.tau[1][2]) * iJ;
+    A.sigma[5 * n + i] = double(P.tau[0][2]) * iJ;
+  }
+  if (A.be) {
+    T ee[3];
+    for (int a = 0; a < 3; ++a)
+      ee[a] = t_exp<T>(T(2) * (P.eps[a] - (T(1) - P.r) * (P.tp[a] - (P.tp[0] + P.tp[1] + P.tp[2]) / T(3)) /
+                                              (T(2) * P.G * P.r)));
+    const int ii[6] = {0, 1, 2, 0, 1, 0}, jj[6] = {0, 1, 2, 1, 2, 2};
+    for (int c = 0; c < 6; ++c) {
+      T v = 0;
+      for (int a = 0; a < 3; ++a) v += ee[a] * P.N[ii[c]][a] * P.N[jj[c]][a];
+      A.be[c * n + i] = double(v);
+    }
+  }
+  if (A.Fnew && A.s.Fn) {
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        double v = 0;
+        for (int m = 0; m < 3; ++m) v += double(F[r][m]) * A.s.Fn[(3 * m + c) * n + i];
+        A.Fnew[(3 * r + c) * n + i] = v;
+      }
+  }
+}
+
+// ------------------------------------------------------------------ fast path
+// One 64-lane workgroup = one wavefront = 64 consecutive sorted points. Points whose domain
+// lies in one leaf share that leaf's 8-node stencil; each lane computes its point's force
+// (24 values) and upper-triangle stiffness blocks (36 x 9); the values are reduced per leaf
+// segment through LDS (36 values per round) and the segment sums go to global memory with
+// atomics (K mirrored into the lower triangle).
+constexpr int kRound = 36;
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_assemble_fast(AsmArgs A) {
+  __shared__ __align__(16) unsigned char red_raw[(kRound * 64 * sizeof(T) > 24 * 64 * 8) ? kRound * 64 * sizeof(T)
+                                                                                          : 24 * 64 * 8];
+  __shared__ int32_t seg_start[65];
+  __shared__ int32_t seg_leaf[64];
+  __shared__ int32_t seg_act[64];
+  __shared__ int32_t seg_cnt;
+  T(*red)[64] = reinterpret_cast<T(*)[64]>(red_raw);
+  double(*redd)[64] = reinterpret_cast<double(*)[64]>(red_raw);
+
+  const int lane = threadIdx.x;
+  const int64_t i = int64_t(blockIdx.x) * 64 + lane;
+  const int64_t n = A.n;
+  const bool inr = i < n;
+  const int32_t leaf = inr ? A.pleaf[i] : -1;
+  bool act = inr && A.pnleaf[i] == 1;
+
+  // segments = runs of equal leaf
+  const int32_t prev = __shfl_up(leaf, 1);
+  const bool head = inr && (lane == 0 || prev != leaf);
+  const uint64_t heads = __ballot(head);
+  const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+  const int my_seg = __popcll(heads & le) - 1;
+  if (lane < 64) seg_act[lane] = 0;
+  if (lane == 0) seg_cnt = __popcll(heads);
+  __syncthreads();
+  if (head) {
+    seg_start[my_seg] = lane;
+    seg_leaf[my_seg] = leaf;
+  }
+  if (lane == 0) {
+    const int64_t rem = n - int64_t(blockIdx.x) * 64;
+    seg_start[__popcll(heads)] = int32_t(rem < 64 ? rem : 64);
+  }
+
+  // ---------------- per-point arithmetic
+  T S[8], dS[8][3], g[8][3];
+  PointMat<T> P;
+  T c = 0;
+  T F[3][3];
+  int32_t nodes[8];
+  if (act) {
+    const int32_t code = A.cell_code[leaf];
+    for (int v = 0; v < 8; ++v) nodes[v] = A.cell_nodes[8 * int64_t(leaf) + v];
+    double x[3], l[3];
+    for (int a = 0; a < 3; ++a) {
+      x[a] = A.s.x[a * n + i];
+      l[a] = A.s.l[a * n + i];
+    }
+    leaf_overlap_basis<T>(A.G, leaf, code, x, l, S, dS);
+    T H[3][3];
+    for (int r = 0; r < 3; ++r)
+      for (int q = 0; q < 3; ++q) H[r][q] = 0;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const double* uv = A.u + 3 * int64_t(nodes[v]);
+      const T u0 = T(uv[0]), u1 = T(uv[1]), u2 = T(uv[2]);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        H[0][q] += u0 * dS[v][q];
+        H[1][q] += u1 * dS[v][q];
+        H[2][q] += u2 * dS[v][q];
+      }
+    }
+    for (int r = 0; r < 3; ++r)
+      for (int q = 0; q < 3; ++q) F[r][q] = H[r][q] + (r == q ? T(1) : T(0));
+    T Fi[3][3];
+    const T Jd = inv3(F, Fi);
+    const double Jn = A.s.Jn[i];
+    if (!isfinite(double(Jd)) || !isfinite(Jn)) {
+      raise(A.err, MPM_ENONFINITE, i);
+      act = false;
+    } else if (!(Jd > T(0))) {
+      raise(A.err, MPM_EDET, i);
+      act = false;
+    }
+    if (act) {
+#pragma unroll
+      for (int v = 0; v < 8; ++v)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) g[v][q] = Fi[0][q] * dS[v][0] + Fi[1][q] * dS[v][1] + Fi[2][q] * dS[v][2];
+      T B[3][3];
+      load_B<T>(A.s, n, i, B);
+      const int st = material<T>(H, B, A.s.E[i], A.s.nu[i], A.s.sy[i], P);
+      if (st) {
+        raise(A.err, st, i);
+        act = false;
+      } else {
+        c = T(A.s.vol[i] / Jn);
+        write_point<T>(A, i, P, F, double(Jd) * Jn);
+      }
+    }
+  }
+  if (act) seg_act[my_seg] = 1;
+  if (!act) {
+    c = 0;
+    for (int v = 0; v < 8; ++v) {
+      nodes[v] = 0;
+      for (int q = 0; q < 3; ++q) g[v][q] = 0;
+    }
+    for (int r = 0; r < 3; ++r)
+      for (int q = 0; q < 3; ++q) {
+        P.tau[r][q] = 0;
+        P.N[r][q] = r == q ? T(1) : T(0);
+        P.D[r][q] = 0;
+      }
+    P.Geff = 0;
+    P.th01 = P.th02 = P.th12 = 0;
+    for (int a = 0; a < 3; ++a) P.x[a] = 1;
+  }
+  const int nseg = seg_cnt;
+
+  // ---------------- force: f_v = c tau g_v (FP64 accumulation)
+#pragma unroll
+  for (int v = 0; v < 8; ++v)
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+      redd[3 * v + r][lane] = double(c) * double(P.tau[r][0] * g[v][0] + P.tau[r][1] * g[v][1] + P.tau[r][2] * g[v][2]);
+  __syncthreads();
+  for (int pp = lane; pp < nseg * 24; pp += 64) {
+    const int sg = pp / 24, v = pp % 24;
+    if (!seg_act[sg]) continue;
+    double sum = 0;
+    for (int ln = seg_start[sg]; ln < seg_start[sg + 1]; ++ln) sum += redd[v][ln];
+    const int32_t node = A.cell_nodes[8 * int64_t(seg_leaf[sg]) + v / 3];
+    atomicAdd(A.f + 3 * int64_t(node) + (v % 3), sum);
+  }
+  __syncthreads();
+  if (!A.K) return;
+
+  // ---------------- stiffness: K_(a,i)(b,k) = c [ (dtau(b,k) g_a)_i - (tau g_b)_i g_a,k ]
+  T* Kout = reinterpret_cast<T*>(A.K);
+  int blk = 0;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    T gt[3], tg[3];
+#pragma unroll
+    for (int al = 0; al < 3; ++al) gt[al] = P.N[0][al] * g[b][0] + P.N[1][al] * g[b][1] + P.N[2][al] * g[b][2];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) tg[r] = P.tau[r][0] * g[b][0] + P.tau[r][1] * g[b][1] + P.tau[r][2] * g[b][2];
+    T dt[3][3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dtau_rank1<T>(P, k, gt, dt[k]);
+#pragma unroll
+    for (int a = 0; a <= b; ++a) {
+      const int slotv = (blk % 4) * 9;
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const T m = dt[k][r][0] * g[a][0] + dt[k][r][1] * g[a][1] + dt[k][r][2] * g[a][2] - tg[r] * g[a][k];
+          red[slotv + 3 * r + k][lane] = c * m;
+        }
+      if (blk % 4 == 3) {
+        __syncthreads();
+        const int rnd = blk / 4;
+        for (int pp = lane; pp < nseg * kRound; pp += 64) {
+          const int sg = pp / kRound, v = pp % kRound;
+          if (!seg_act[sg]) continue;
+          T sum = 0;
+          for (int ln = seg_start[sg]; ln < seg_start[sg + 1]; ++ln) sum += red[v][ln];
+          const int bi = rnd * 4 + v / 9;
+          const int ba = c_blk_a[bi], bb = c_blk_b[bi];
+          const int r = (v % 9) / 3, k = v % 3;
+          const int64_t e = seg_leaf[sg];
+          const int64_t o1 = A.slot[64 * e + 8 * ba + bb] + int64_t(r) * A.stride[8 * e + ba] + k;
+          atomic_add_val<T>(Kout + o1, sum);
+          if (ba != bb) {
+            const int64_t o2 = A.slot[64 * e + 8 * bb + ba] + int64_t(k) * A.stride[8 * e + bb] + r;
+            atomic_add_val<T>(Kout + o2, sum);
+          }
+        }
+        __syncthreads();
+      }
+      ++blk;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ general path
+// Points whose domain overlaps several leaves: one lane per point, support merged over the
+// leaves (up to 64 nodes), direct atomics; CSR positions found by binary search in the row.
+constexpr int kMaxSup = kMaxPointLeaves * 8;
+
+__device__ __forceinline__ int64_t csr_pos(const int64_t* row_ptr, const int32_t* col, int64_t row, int32_t cv) {
+  int64_t lo = row_ptr[row], hi = row_ptr[row + 1] - 1;
+  while (lo <= hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    const int32_t v = col[mid];
+    if (v == cv) return mid;
+    if (v < cv) lo = mid + 1;
+    else hi = mid - 1;
+  }
+  return -1;
+}
+
+template <typename T>
+__device__ int general_basis(const AsmArgs& A, int64_t t, const double x[3], const double l[3], int32_t* nd, T* S,
+                             T (*dS)[3]) {
+  int ns = 0;
+  for (int q = 0; q < kMaxPointLeaves; ++q) {
+    const int32_t e = A.strad_leaf[t * kMaxPointLeaves + q];
+    if (e < 0) break;
+    T s8[8], d8[8][3];
+    leaf_overlap_basis<T>(A.G, e, A.cell_code[e], x, l, s8, d8);
+    for (int v = 0; v < 8; ++v) {
+      const int32_t id = A.cell_nodes[8 * int64_t(e) + v];
+      int pos = -1;
+      for (int z = 0; z < ns; ++z)
+        if (nd[z] == id) pos = z;
+      if (pos < 0) {
+        pos = ns++;
+        nd[pos] = id;
+        S[pos] = 0;
+        dS[pos][0] = dS[pos][1] = dS[pos][2] = 0;
+      }
+      S[pos] += s8[v];
+      dS[pos][0] += d8[v][0];
+      dS[pos][1] += d8[v][1];
+      dS[pos][2] += d8[v][2];
+    }
+  }
+  return ns;
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_assemble_general(AsmArgs A) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= A.n_strad) return;
+  const int64_t i = A.strad[t], n = A.n;
+  double x[3], l[3];
+  for (int a = 0; a < 3; ++a) {
+    x[a] = A.s.x[a * n + i];
+    l[a] = A.s.l[a * n + i];
+  }
+  int32_t nd[kMaxSup];
+  T S[kMaxSup], dS[kMaxSup][3];
+  const int ns = general_basis<T>(A, t, x, l, nd, S, dS);
+  T H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int v = 0; v < ns; ++v) {
+    const double* uv = A.u + 3 * int64_t(nd[v]);
+    for (int r = 0; r < 3; ++r)
+      for (int q = 0; q < 3; ++q) H[r][q] += T(uv[r]) * dS[v][q];
+  }
+  T F[3][3], Fi[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int q = 0; q < 3; ++q) F[r][q] = H[r][q] + (r == q ? T(1) : T(0));
+  const T Jd = inv3(F, Fi);
+  const double Jn = A.s.Jn[i];
+  if (!isfinite(double(Jd)) || !isfinite(Jn)) {
+    raise(A.err, MPM_ENONFINITE, i);
+    return;
+  }
+  if (!(Jd > T(0))) {
+    raise(A.err, MPM_EDET, i);
+    return;
+  }
+  T B[3][3];
+  load_B<T>(A.s, n, i, B);
+  PointMat<T> P;
+  const int st = material<T>(H, B, A.s.E[i], A.s.nu[i], A.s.sy[i], P);
+  if (st) {
+    raise(A.err, st, i);
+    return;
+  }
+  write_point<T>(A, i, P, F, double(Jd) * Jn);
+  const T c = T(A.s.vol[i] / Jn);
+  T g[kMaxSup][3];
+  for (int v = 0; v < ns; ++v)
+    for (int q = 0; q < 3; ++q) g[v][q] = Fi[0][q] * dS[v][0] + Fi[1][q] * dS[v][1] + Fi[2][q] * dS[v][2];
+  for (int v = 0; v < ns; ++v)
+    for (int r = 0; r < 3; ++r)
+      atomicAdd(A.f + 3 * int64_t(nd[v]) + r,
+                double(c) * double(P.tau[r][0] * g[v][0] + P.tau[r][1] * g[v][1] + P.tau[r][2] * g[v][2]));
+  if (!A.K) return;
+  T* Kout = reinterpret_cast<T*>(A.K);
+  for (int b = 0; b < ns; ++b) {
+    T gt[3], tg[3];
+    for (int al = 0; al < 3; ++al) gt[al] = P.N[0][al] * g[b][0] + P.N[1][al] * g[b][1] + P.N[2][al] * g[b][2];
+    for (int r = 0; r < 3; ++r) tg[r] = P.tau[r][0] * g[b][0] + P.tau[r][1] * g[b][1] + P.tau[r][2] * g[b][2];
+    T dt[3][3][3];
+    for (int k = 0; k < 3; ++k) dtau_rank1<T>(P, k, gt, dt[k]);
+    for (int a = 0; a < ns; ++a) {
+      for (int r = 0; r < 3; ++r) {
+        const int64_t row = 3 * int64_t(nd[a]) + r;
+        const int64_t p0 = csr_pos(A.row_ptr, A.col, row, 3 * nd[b]);
+        if (p0 < 0) {
+          raise(A.err, MPM_ESTENCIL, i);
+          return;
+        }
+        for (int k = 0; k < 3; ++k) {
+          const T m = dt[k][r][0] * g[a][0] + dt[k][r][1] * g[a][1] + dt[k][r][2] * g[a][2] - tg[r] * g[a][k];
+          atomic_add_val<T>(Kout + p0 + k, c * m);
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ body force
+__global__ void k_external_force(AsmArgs A) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t n = A.n;
+  if (i >= n || A.pnleaf[i] != 1) return;
+  const int32_t e = A.pleaf[i];
+  double x[3], l[3];
+  for (int a = 0; a < 3; ++a) {
+    x[a] = A.s.x[a * n + i];
+    l[a] = A.s.l[a * n + i];
+  }
+  double S[8], dS[8][3];
+  leaf_overlap_basis<double>(A.G, e, A.cell_code[e], x, l, S, dS);
+  const double m = A.s.mass[i];
+  for (int v = 0; v < 8; ++v) {
+    const int64_t nd = A.cell_nodes[8 * int64_t(e) + v];
+    for (int r = 0; r < 3; ++r) atomicAdd(A.f + 3 * nd + r, S[v] * m * A.s.g[r]);
+  }
+}
+
+__global__ void k_external_force_general(AsmArgs A) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= A.n_strad) return;
+  const int64_t i = A.strad[t], n = A.n;
+  double x[3], l[3];
+  for (int a = 0; a < 3; ++a) {
+    x[a] = A.s.x[a * n + i];
+    l[a] = A.s.l[a * n + i];
+  }
+  int32_t nd[kMaxSup];
+  double S[kMaxSup], dS[kMaxSup][3];
+  const int ns = general_basis<double>(A, t, x, l, nd, S, dS);
+  const double m = A.s.mass[i];
+  for (int v = 0; v < ns; ++v)
+    for (int r = 0; r < 3; ++r) atomicAdd(A.f + 3 * int64_t(nd[v]) + r, S[v] * m * A.s.g[r]);
+}
+
+// ------------------------------------------------------------------ residual
+constexpr int kResBlocks = 1024;
+__global__ __launch_bounds__(256) void k_residual(const double* __restrict__ f, const double* __restrict__ fe,
+                                                  const uint8_t* __restrict__ dir, double* __restrict__ r, int64_t nd,
+                                                  double* __restrict__ partial) {
+  __shared__ double s[256];
+  double acc = 0;
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < nd; k += int64_t(gridDim.x) * 256) {
+    double v = f[k] - (fe ? fe[k] : 0.0);
+    if (dir && dir[k]) v = 0.0;
+    if (r) r[k] = v;
+    acc += v * v;
+  }
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(256) void k_norm_final(const double* __restrict__ partial, int np, double* out) {
+  __shared__ double s[256];
+  double acc = 0;
+  for (int k = threadIdx.x; k < np; k += 256) acc += partial[k];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sqrt(s[0]);
+}
+
+// ------------------------------------------------------------------ adjoint
+// L = lambda . f_int: per point L_p = c tau : G with c = V_n/J_n, G = sum_v lambda_v (x) grad_x S_v.
+// dL/dV_n = tau:G / J_n; dL/dtheta = c sum_a (d tau_a / d theta) (n_a . G n_a).
+template <typename T>
+__global__ __launch_bounds__(64) void k_adjoint(AsmArgs A) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t n = A.n;
+  if (i >= n) return;
+  double x[3], l[3];
+  for (int a = 0; a < 3; ++a) {
+    x[a] = A.s.x[a * n + i];
+    l[a] = A.s.l[a * n + i];
+  }
+  int32_t nd[kMaxSup];
+  T S[kMaxSup], dS[kMaxSup][3];
+  int ns;
+  if (A.pnleaf[i] == 1) {
+    const int32_t e = A.pleaf[i];
+    T s8[8], d8[8][3];
+    leaf_overlap_basis<T>(A.G, e, A.cell_code[e], x, l, s8, d8);
+    for (int v = 0; v < 8; ++v) {
+      nd[v] = A.cell_nodes[8 * int64_t(e) + v];
+      S[v] = s8[v];
+      for (int q = 0; q < 3; ++q) dS[v][q] = d8[v][q];
+    }
+    ns = 8;
+  } else {
+    // locate this point in the straddle list (sorted ascending)
+    int64_t lo = 0, hi = A.n_strad - 1, t = -1;
+    while (lo <= hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (A.strad[mid] == i) {
+        t = mid;
+        break;
+      }
+      if (A.strad[mid] < i) lo = mid + 1;
+      else hi = mid - 1;
+    }
+    if (t < 0) {
+      raise(A.err, MPM_ETREE, i);
+      return;
+    }
+    ns = general_basis<T>(A, t, x, l, nd, S, dS);
+  }
+  T H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int v = 0; v < ns; ++v) {
+    const double* uv = A.u + 3 * int64_t(nd[v]);
+    for (int r = 0; r < 3; ++r)
+      for (int q = 0; q < 3; ++q) H[r][q] += T(uv[r]) * dS[v][q];
+  }
+  T F[3][3], Fi[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int q = 0; q < 3; ++q) F[r][q] = H[r][q] + (r == q ? T(1) : T(0));
+  const T Jd = inv3(F, Fi);
+  const double Jn = A.s.Jn[i];
+  if (!isfinite(double(Jd)) || !isfinite(Jn)) {
+    raise(A.err, MPM_ENONFINITE, i);
+    return;
+  }
+  if (!(Jd > T(0))) {
+    raise(A.err, MPM_EDET, i);
+    return;
+  }
+  T B[3][3];
+  load_B<T>(A.s, n, i, B);
+  PointMat<T> P;
+  const double Ed = A.s.E[i], nud = A.s.nu[i], syd = A.s.sy[i];
+  const int st = material<T>(H, B, Ed, nud, syd, P);
+  if (st) {
+    raise(A.err, st, i);
+    return;
+  }
+  T Gm[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int v = 0; v < ns; ++v) {
+    T gv[3];
+    for (int q = 0; q < 3; ++q) gv[q] = Fi[0][q] * dS[v][0] + Fi[1][q] * dS[v][1] + Fi[2][q] * dS[v][2];
+    const double* lv = A.lam + 3 * int64_t(nd[v]);
+    for (int r = 0; r < 3; ++r)
+      for (int q = 0; q < 3; ++q) Gm[r][q] += T(lv[r]) * gv[q];
+  }
+  double Ga[3], tauG = 0;
+  for (int a = 0; a < 3; ++a) {
+    T v = 0;
+    for (int r = 0; r < 3; ++r)
+      for (int q = 0; q < 3; ++q) v += P.N[r][a] * Gm[r][q] * P.N[q][a];
+    Ga[a] = double(v);
+    tauG += double(P.tp[a]) * Ga[a];
+  }
+  const double cc = A.s.vol[i] / Jn;
+  double tr = 0;
+  for (int a = 0; a < 3; ++a) tr += double(P.eps[a]);
+  double dE = 0, dnu = 0, dsy = 0;
+  if (P.plastic) {
+    const double dKdE = 1.0 / (3.0 * (1.0 - 2.0 * nud));
+    const double dKdnu = 2.0 * Ed / (3.0 * (1.0 - 2.0 * nud) * (1.0 - 2.0 * nud));
+    const double sq = sqrt(2.0 / 3.0);
+    for (int a = 0; a < 3; ++a) {
+      dE += tr * dKdE * Ga[a];
+      dnu += tr * dKdnu * Ga[a];
+      dsy += sq * double(P.s_hat[a]) * Ga[a];
+    }
+  } else {
+    const double opn = 1.0 + nud, omn = 1.0 - 2.0 * nud;
+    const double dlam = Ed * (1.0 + 2.0 * nud * nud) / (opn * opn * omn * omn);
+    const double dG = -Ed / (2.0 * opn * opn);
+    for (int a = 0; a < 3; ++a) {
+      dE += double(P.tp[a]) / Ed * Ga[a];
+      dnu += (dlam * tr + 2.0 * dG * double(P.eps[a])) * Ga[a];
+    }
+  }
+  A.dE[i] = cc * dE;
+  A.dnu[i] = cc * dnu;
+  A.dsy[i] = cc * dsy;
+  A.dV[i] = tauG / Jn;
+}
+
+static AsmArgs make_args(const mpm_mesh* m, const mpm_state_t* s) {
+  AsmArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.G = make_geo(m);
+  A.cell_nodes = m->d_cell_nodes;
+  A.cell_code = m->d_cell_code;
+  A.pleaf = m->d_pleaf;
+  A.pnleaf = m->d_pnleaf;
+  A.slot = m->d_slot;
+  A.stride = m->d_stride;
+  A.row_ptr = m->d_row_ptr;
+  A.col = m->d_col;
+  A.strad = m->d_strad;
+  A.strad_leaf = m->d_strad_leaf;
+  A.n = m->n_point;
+  A.n_strad = m->n_straddle;
+  A.s = *s;
+  A.err = m->d_err;
+  return A;
+}
+
+static bool state_ok(const mpm_state_t* s) {
+  return s && s->x && s->l && s->vol && s->Jn && s->bn && s->E && s->nu && s->sy;
+}
+
+}  // namespace mpm
+
+using namespace mpm;
+
+extern "C" int32_t mpm_external_force(const mpm_mesh_t* m, const mpm_state_t* s, double* f_ext, void* stream) {
+  if (!m || !s || !f_ext || !s->x || !s->l || !s->mass) {
+    set_error(MPM_EARG, "mpm_external_force: null argument");
+    return MPM_EARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  AsmArgs A = make_args(m, s);
+  A.f = f_ext;
+  MPM_HIP(hipMemsetAsync(f_ext, 0, size_t(3 * m->n_node) * 8, st));
+  if (m->n_point) hipLaunchKernelGGL(k_external_force, dim3((m->n_point + 255) / 256), dim3(256), 0, st, A);
+  if (m->n_straddle)
+    hipLaunchKernelGGL(k_external_force_general, dim3((m->n_straddle + 63) / 64), dim3(64), 0, st, A);
+  MPM_HIP(hipGetLastError());
+  return read_error(const_cast<mpm_mesh*>(m), st, "mpm_external_force");
+}
+
+extern "C" int32_t mpm_assemble(const mpm_mesh_t* m, const mpm_state_t* s, const double* u, int32_t precision,
+                                const double* f_ext, const uint8_t* dirichlet, double* f_int, void* K_vals,
+                                double* sigma6, double* r, double* rnorm, double* F_new, double* be_new,
+                                void* stream) {
+  if (!m || !state_ok(s) || !u || !f_int || (precision != MPM_F64 && precision != MPM_F32K) ||
+      (F_new && !s->Fn)) {
+    set_error(MPM_EARG, "mpm_assemble: null argument, bad precision or F_new without F_n");
+    return MPM_EARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  AsmArgs A = make_args(m, s);
+  A.u = u;
+  A.f = f_int;
+  A.K = K_vals;
+  A.sigma = sigma6;
+  A.Fnew = F_new;
+  A.be = be_new;
+  const size_t kbytes = size_t(m->nnz) * (precision == MPM_F64 ? 8 : 4);
+  MPM_HIP(hipMemsetAsync(f_int, 0, size_t(3 * m->n_node) * 8, st));
+  if (K_vals && kbytes) MPM_HIP(hipMemsetAsync(K_vals, 0, kbytes, st));
+  const int64_t n = m->n_point;
+  if (n) {
+    const dim3 grid(unsigned((n + 63) / 64));
+    if (precision == MPM_F64) hipLaunchKernelGGL(k_assemble_fast<double>, grid, dim3(64), 0, st, A);
+    else hipLaunchKernelGGL(k_assemble_fast<float>, grid, dim3(64), 0, st, A);
+  }
+  if (m->n_straddle) {
+    const dim3 grid(unsigned((m->n_straddle + 63) / 64));
+    if (precision == MPM_F64) hipLaunchKernelGGL(k_assemble_general<double>, grid, dim3(64), 0, st, A);
+    else hipLaunchKernelGGL(k_assemble_general<float>, grid, dim3(64), 0, st, A);
+  }
+  if (r || rnorm) {
+    const int64_t nd = 3 * m->n_node;
+    int nb = int(std::min<int64_t>(kResBlocks, (nd + 255) / 256));
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_residual, dim3(nb), dim3(256), 0, st, f_int, f_ext, dirichlet, r, nd, m->d_partial);
+    if (rnorm) hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(256), 0, st, m->d_partial, nb, rnorm);
+  }
+  MPM_HIP(hipGetLastError());
+  return read_error(const_cast<mpm_mesh*>(m), st, "mpm_assemble");
+}
+
+extern "C" int32_t mpm_assemble_adjoint(const mpm_mesh_t* m, const mpm_state_t* s, const double* u,
+                                        const double* lambda, int32_t precision, double* dE, double* dnu,
+                                        double* dsy, double* dV, void* stream) {
+  if (!m || !state_ok(s) || !u || !lambda || !dE || !dnu || !dsy || !dV ||
+      (precision != MPM_F64 && precision != MPM_F32K)) {
+    set_error(MPM_EARG, "mpm_assemble_adjoint: null argument or bad precision");
+    return MPM_EARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  AsmArgs A = make_args(m, s);
+  A.u = u;
+  A.lam = lambda;
+  A.dE = dE;
+  A.dnu = dnu;
+  A.dsy = dsy;
+  A.dV = dV;
+  const int64_t n = m->n_point;
+  if (n) {
+    const dim3 grid(unsigned((n + 63) / 64));
+    if (precision == MPM_F64) hipLaunchKernelGGL(k_adjoint<double>, grid, dim3(64), 0, st, A);
+    else hipLaunchKernelGGL(k_adjoint<float>, grid, dim3(64), 0, st, A);
+  }
+  MPM_HIP(hipGetLastError());
+  return read_error(const_cast<mpm_mesh*>(m), st, "mpm_assemble_adjoint");
+}

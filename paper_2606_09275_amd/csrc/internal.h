@@ -1,0 +1,98 @@
+// Internal definitions of the gfx950 octree GIMP assembly library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mpm_gimp.h"
+
+namespace mpm {
+
+// ------------------------------------------------------------------ errors
+void set_error(int32_t code, const std::string& msg, int64_t index = -1);
+int32_t hip_fail(hipError_t e, const char* what);
+
+#define MPM_HIP(call)                                       \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) return ::mpm::hip_fail(e_, #call); \
+  } while (0)
+
+// device error word: [0] first error code (0 none), [1..2] first offending index (int64)
+struct DevErr {
+  int32_t code;
+  int32_t pad;
+  unsigned long long index;
+};
+
+// ------------------------------------------------------------------ Morton keys
+// bits b of x, y, z go to bits 3b, 3b+1, 3b+2 (21 bits per axis)
+__host__ __device__ inline uint64_t spread3(uint64_t v) {
+  v &= 0x1fffffull;
+  v = (v | (v << 32)) & 0x1f00000000ffffull;
+  v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+  v = (v | (v << 8)) & 0x100f00f00f00f00full;
+  v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+  v = (v | (v << 2)) & 0x1249249249249249ull;
+  return v;
+}
+__host__ __device__ inline uint64_t morton(uint64_t x, uint64_t y, uint64_t z) {
+  return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+
+constexpr int kSubBits = 42;       // bits of the within-leaf sub-key in a point sort key
+constexpr int kSubRes = 16;        // sub-key resolution: h_min / 16
+constexpr int kMaxPointLeaves = 8; // leaves a point domain may overlap (one boundary per axis)
+
+// per-leaf constraint code: bits 0..7 hanging vertices, bits 8..10 child index in the parent
+__host__ __device__ inline int code_hmask(int32_t code) { return code & 0xff; }
+__host__ __device__ inline int code_child(int32_t code) { return (code >> 8) & 7; }
+
+// ------------------------------------------------------------------ mesh handle
+struct HostTree {
+  std::vector<int32_t> leaf;       // n_leaf x 4, Morton order
+  std::vector<uint64_t> leaf_key;  // Morton key of anchors
+  std::vector<int32_t> node_ijk;   // independent nodes x 3
+  std::vector<int32_t> hang_ijk, hang_sup, hang_owner;
+  std::vector<double> hang_w;
+  std::vector<int32_t> cell_nodes; // n_leaf x 8
+  std::vector<int32_t> cell_code;  // n_leaf
+  std::vector<double> cell_cmat;   // n_leaf x 8 x 8: C_K[vertex][slot]
+};
+
+}  // namespace mpm
+
+struct mpm_mesh {
+  mpm_refine_t crit;
+  int nx, ny, nz;
+  double hmin;
+  int64_t n_leaf = 0, n_node = 0, n_hang = 0, n_point = 0, nnz = 0, n_straddle = 0, n_active_rows = 0;
+  int32_t max_support = 0;
+  int leaf_bits = 1;            // bits needed for a leaf rank
+  // device arrays (owned)
+  int32_t* d_leaf = nullptr;        // n_leaf x 4
+  uint64_t* d_leaf_key = nullptr;   // n_leaf
+  int32_t* d_cell_nodes = nullptr;  // n_leaf x 8
+  int32_t* d_cell_code = nullptr;   // n_leaf
+  double* d_cell_cmat = nullptr;    // n_leaf x 64
+  int32_t* d_node_ijk = nullptr;
+  int32_t* d_hang_ijk = nullptr;
+  int32_t* d_hang_sup = nullptr;
+  double* d_hang_w = nullptr;
+  int32_t* d_hang_owner = nullptr;
+  int64_t* d_perm = nullptr;        // n_point
+  int32_t* d_pleaf = nullptr;       // n_point (sorted)
+  uint8_t* d_pnleaf = nullptr;      // n_point (sorted)
+  int64_t* d_row_ptr = nullptr;
+  int32_t* d_col = nullptr;
+  int64_t* d_slot = nullptr;        // n_leaf x 64: CSR offset of block (a,b) (row 3 n_a, block col n_b)
+  int32_t* d_stride = nullptr;      // n_leaf x 8: row length of node a
+  int64_t* d_strad = nullptr;       // n_straddle sorted positions
+  int32_t* d_strad_leaf = nullptr;  // n_straddle x 8 overlapped leaves (-1 pad)
+  mpm::DevErr* d_err = nullptr;
+  double* d_partial = nullptr;      // residual partial sums
+  void* d_scratch = nullptr;        // radix sort scratch
+  size_t scratch_bytes = 0;
+};

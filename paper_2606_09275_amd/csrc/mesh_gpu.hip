@@ -1,0 +1,618 @@
+// Mesh construction entry points: octree (host), point keys + LSD radix sort + leaf search
+// and overlap classification (device), CSR pattern and per-element slot map (host).
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+
+#include "geom.h"
+
+namespace mpm {
+
+// ------------------------------------------------------------------ errors
+namespace {
+thread_local std::string g_msg;
+thread_local int64_t g_index = -1;
+}  // namespace
+
+void set_error(int32_t code, const std::string& msg, int64_t index) {
+  g_msg = "[" + std::to_string(code) + "] " + msg;
+  g_index = index;
+}
+int32_t hip_fail(hipError_t e, const char* what) {
+  set_error(MPM_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  return MPM_EHIP;
+}
+
+int32_t build_tree(const mpm_refine_t& c, HostTree& T, int lat_out[3], double* hmin_out);
+
+// ------------------------------------------------------------------ point keys
+__global__ void k_point_keys(const double* __restrict__ x, int64_t n, LeafGeo G, uint64_t* __restrict__ keys,
+                             int64_t* __restrict__ idx, DevErr* err) {
+#pragma clang fp contract(off)
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const double hsub = G.hmin / double(kSubRes);
+  uint64_t sc[3];
+  double xp[3];
+  bool bad = false, big = false;
+  for (int a = 0; a < 3; ++a) {
+    xp[a] = x[a * n + p];
+    bad |= !isfinite(xp[a]);
+    const double t = floor((xp[a] - G.lo[a]) / hsub);
+    const double tc = t < 0.0 ? 0.0 : t;
+    big |= tc >= double(1 << 14);
+    sc[a] = bad || big ? 0 : uint64_t(tc);
+  }
+  if (bad || big) {
+    if (atomicCAS(&err->code, 0, bad ? MPM_ENONFINITE : MPM_ESTENCIL) == 0) err->index = p;
+    keys[p] = 0;
+    idx[p] = p;
+    return;
+  }
+  const int64_t e = leaf_of_point(G, xp[0], xp[1], xp[2]);
+  keys[p] = (uint64_t(e) << kSubBits) | morton(sc[0], sc[1], sc[2]);
+  idx[p] = p;
+}
+
+// ------------------------------------------------------------------ stable LSD radix sort
+constexpr int kRsThreads = 256;
+constexpr int kRsRounds = 16;
+constexpr int kRsTile = kRsThreads * kRsRounds;
+
+__global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
+                                                        uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = int64_t(blockIdx.x) * kRsTile;
+  for (int i = threadIdx.x; i < kRsTile; i += kRsThreads) {
+    const int64_t j = base + i;
+    if (j < n) atomicAdd(&h[(keys[j] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[int64_t(threadIdx.x) * gridDim.x + blockIdx.x] = h[threadIdx.x];
+}
+
+// exclusive scan of one digit's per-block counts (one workgroup per digit); total -> tot[d]
+__global__ __launch_bounds__(kRsThreads) void k_rs_scan_digit(uint32_t* __restrict__ hist, int nblk,
+                                                              uint32_t* __restrict__ tot) {
+  __shared__ uint32_t s[kRsThreads];
+  uint32_t* row = hist + int64_t(blockIdx.x) * nblk;
+  uint32_t carry = 0;
+  for (int base = 0; base < nblk; base += kRsThreads) {
+    const int i = base + threadIdx.x;
+    const uint32_t v = i < nblk ? row[i] : 0u;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < kRsThreads; off <<= 1) {  // Hillis-Steele inclusive scan
+      const uint32_t t = threadIdx.x >= off ? s[threadIdx.x - off] : 0u;
+      __syncthreads();
+      s[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < nblk) row[i] = carry + s[threadIdx.x] - v;
+    carry += s[kRsThreads - 1];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) tot[blockIdx.x] = carry;
+}
+
+__global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t* __restrict__ kin,
+                                                           const int64_t* __restrict__ vin, uint64_t* __restrict__ kout,
+                                                           int64_t* __restrict__ vout, int64_t n, int shift,
+                                                           const uint32_t* __restrict__ hist,
+                                                           const uint32_t* __restrict__ tot) {
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wcnt[kRsThreads / 64][256];
+  __shared__ uint32_t dbase[256];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  if (tid == 0) {
+    uint32_t acc = 0;
+    for (int d = 0; d < 256; ++d) {
+      dbase[d] = acc;
+      acc += tot[d];
+    }
+  }
+  __syncthreads();
+  run[tid] = dbase[tid] + hist[int64_t(tid) * gridDim.x + blockIdx.x];
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t base = int64_t(blockIdx.x) * kRsTile;
+  for (int r = 0; r < kRsRounds; ++r) {
+    for (int i = tid; i < (kRsThreads / 64) * 256; i += kRsThreads) (&wcnt[0][0])[i] = 0u;
+    const int64_t j = base + int64_t(r) * kRsThreads + tid;
+    const bool valid = j < n;
+    const uint64_t k = valid ? kin[j] : 0ull;
+    const int64_t v = valid ? vin[j] : 0;
+    const uint32_t d = uint32_t(k >> shift) & 255u;
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t bb = __ballot((d >> b) & 1u);
+      peers &= ((d >> b) & 1u) ? bb : ~bb;
+    }
+    const uint32_t rank = __popcll(peers & lt);
+    __syncthreads();
+    if (valid && rank == 0) wcnt[wave][d] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t off = run[d] + rank;
+      for (int w = 0; w < wave; ++w) off += wcnt[w][d];
+      kout[off] = k;
+      vout[off] = v;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+    for (int w = 0; w < kRsThreads / 64; ++w) add += wcnt[w][tid];
+    run[tid] += add;
+    __syncthreads();
+  }
+}
+
+// sorts (keys, vals) by the low `bits` bits of keys; result in keys/vals (scratch used)
+static int32_t radix_sort(uint64_t* keys, int64_t* vals, int64_t n, int bits, uint64_t* ktmp, int64_t* vtmp,
+                          uint32_t* hist, uint32_t* tot, hipStream_t st) {
+  if (n <= 1) return MPM_OK;
+  const int nblk = int((n + kRsTile - 1) / kRsTile);
+  uint64_t *ka = keys, *kb = ktmp;
+  int64_t *va = vals, *vb = vtmp;
+  const int passes = (bits + 7) / 8;
+  for (int ps = 0; ps < passes; ++ps) {
+    const int shift = 8 * ps;
+    hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(kRsThreads), 0, st, ka, n, shift, hist);
+    hipLaunchKernelGGL(k_rs_scan_digit, dim3(256), dim3(kRsThreads), 0, st, hist, nblk, tot);
+    hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(kRsThreads), 0, st, ka, va, kb, vb, n, shift, hist, tot);
+    std::swap(ka, kb);
+    std::swap(va, vb);
+  }
+  if (ka != keys) {
+    MPM_HIP(hipMemcpyAsync(keys, ka, size_t(n) * 8, hipMemcpyDeviceToDevice, st));
+    MPM_HIP(hipMemcpyAsync(vals, va, size_t(n) * 8, hipMemcpyDeviceToDevice, st));
+  }
+  MPM_HIP(hipGetLastError());
+  return MPM_OK;
+}
+
+__global__ void k_unpack_keys(const uint64_t* __restrict__ keys, int64_t n, int32_t* __restrict__ leaf) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) leaf[i] = int32_t(keys[i] >> kSubBits);
+}
+
+// overlap classification in sorted order: number of leaves each domain overlaps
+__global__ void k_classify(const double* __restrict__ x, const double* __restrict__ l, int64_t n,
+                           const int64_t* __restrict__ perm, const int32_t* __restrict__ pleaf, LeafGeo G,
+                           uint8_t* __restrict__ nleaf, DevErr* err) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t p = perm[i];
+  double xp[3], lp[3];
+  bool bad = false;
+  for (int a = 0; a < 3; ++a) {
+    xp[a] = x[a * n + p];
+    lp[a] = l[a * n + p];
+    bad |= !isfinite(lp[a]) || !(lp[a] > 0.0);
+  }
+  if (bad) {
+    if (atomicCAS(&err->code, 0, MPM_ENONFINITE) == 0) err->index = i;
+    nleaf[i] = 0;
+    return;
+  }
+  int32_t lv[kMaxPointLeaves];
+  const int c = domain_leaves(G, pleaf[i], xp, lp, lv);
+  if (c < 0) {
+    if (atomicCAS(&err->code, 0, c) == 0) err->index = i;
+    nleaf[i] = 0;
+    return;
+  }
+  nleaf[i] = uint8_t(c);
+}
+
+__global__ void k_strad_leaves(const double* __restrict__ x, const double* __restrict__ l, int64_t n,
+                               const int64_t* __restrict__ perm, const int32_t* __restrict__ pleaf,
+                               const int64_t* __restrict__ strad, int64_t ns, LeafGeo G, int32_t* __restrict__ out) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= ns) return;
+  const int64_t i = strad[t], p = perm[i];
+  double xp[3], lp[3];
+  for (int a = 0; a < 3; ++a) {
+    xp[a] = x[a * n + p];
+    lp[a] = l[a * n + p];
+  }
+  int32_t lv[kMaxPointLeaves];
+  const int c = domain_leaves(G, pleaf[i], xp, lp, lv);
+  for (int k = 0; k < kMaxPointLeaves; ++k) out[t * kMaxPointLeaves + k] = k < c ? lv[k] : -1;
+}
+
+__global__ void k_permute(const int64_t* __restrict__ perm, const double* __restrict__ src, double* __restrict__ dst,
+                          int64_t n, int ncomp) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t p = perm[i];
+  for (int c = 0; c < ncomp; ++c) dst[c * n + i] = src[c * n + p];
+}
+
+LeafGeo make_geo(const mpm_mesh* m) {
+  LeafGeo G;
+  G.leaf = m->d_leaf;
+  G.leaf_key = m->d_leaf_key;
+  G.n_leaf = m->n_leaf;
+  for (int a = 0; a < 3; ++a) G.lo[a] = m->crit.lo[a];
+  G.hmin = m->hmin;
+  G.lmax = m->crit.lvl_max;
+  G.lat[0] = m->nx;
+  G.lat[1] = m->ny;
+  G.lat[2] = m->nz;
+  return G;
+}
+
+template <typename T>
+static int32_t upload(T** dst, const std::vector<T>& v, hipStream_t st) {
+  MPM_HIP(hipMalloc(dst, std::max<size_t>(1, v.size()) * sizeof(T)));
+  if (!v.empty()) MPM_HIP(hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  return MPM_OK;
+}
+
+int32_t read_error(mpm_mesh* m, hipStream_t st, const char* what) {
+  DevErr e;
+  MPM_HIP(hipMemcpyAsync(&e, m->d_err, sizeof(DevErr), hipMemcpyDeviceToHost, st));
+  MPM_HIP(hipStreamSynchronize(st));
+  if (e.code != 0) {
+    static const char* names[] = {"", "bad argument", "det(dF) <= 0 or non-positive trial eigenvalue",
+                                  "domain spans more than one leaf boundary per axis or key overflow",
+                                  "point domain outside the mesh", "tree inconsistency", "HIP error",
+                                  "non-finite input"};
+    const int c = -e.code;
+    set_error(e.code, std::string(what) + ": " + (c >= 0 && c < 8 ? names[c] : "error"), int64_t(e.index));
+    MPM_HIP(hipMemsetAsync(m->d_err, 0, sizeof(DevErr), st));
+    return e.code;
+  }
+  return MPM_OK;
+}
+
+// sort points (device x [3][n]) into perm / leaf with the mesh's leaves
+int32_t sort_points(const mpm_mesh* m, const double* dx, int64_t n, int64_t* perm, int32_t* leaf, hipStream_t st) {
+  if (n == 0) return MPM_OK;
+  const int bits = kSubBits + m->leaf_bits;
+  uint64_t *keys = nullptr, *ktmp = nullptr;
+  int64_t* vtmp = nullptr;
+  uint32_t *hist = nullptr, *tot = nullptr;
+  const int nblk = int((n + kRsTile - 1) / kRsTile);
+  int32_t rc = MPM_OK;
+  auto fail = [&](hipError_t e, const char* w) { rc = hip_fail(e, w); };
+  hipError_t e;
+  if ((e = hipMallocAsync((void**)&keys, size_t(n) * 8, st)) != hipSuccess) fail(e, "alloc keys");
+  if (!rc && (e = hipMallocAsync((void**)&ktmp, size_t(n) * 8, st)) != hipSuccess) fail(e, "alloc keys");
+  if (!rc && (e = hipMallocAsync((void**)&vtmp, size_t(n) * 8, st)) != hipSuccess) fail(e, "alloc vals");
+  if (!rc && (e = hipMallocAsync((void**)&hist, size_t(nblk) * 256 * 4, st)) != hipSuccess) fail(e, "alloc hist");
+  if (!rc && (e = hipMallocAsync((void**)&tot, 256 * 4, st)) != hipSuccess) fail(e, "alloc tot");
+  if (!rc) {
+    const LeafGeo G = make_geo(m);
+    hipLaunchKernelGGL(k_point_keys, dim3((n + 255) / 256), dim3(256), 0, st, dx, n, G, keys, perm, m->d_err);
+    rc = radix_sort(keys, perm, n, bits, ktmp, vtmp, hist, tot, st);
+    if (!rc) hipLaunchKernelGGL(k_unpack_keys, dim3((n + 255) / 256), dim3(256), 0, st, keys, n, leaf);
+  }
+  hipFreeAsync(keys, st);
+  hipFreeAsync(ktmp, st);
+  hipFreeAsync(vtmp, st);
+  hipFreeAsync(hist, st);
+  hipFreeAsync(tot, st);
+  if (!rc) MPM_HIP(hipGetLastError());
+  return rc;
+}
+
+static bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+}  // namespace mpm
+
+using namespace mpm;
+
+extern "C" int32_t mpm_last_error(char* buf, size_t n) {
+  if (buf && n) {
+    std::strncpy(buf, g_msg.c_str(), n - 1);
+    buf[n - 1] = 0;
+  }
+  return int32_t(g_msg.size());
+}
+extern "C" int64_t mpm_last_error_index(void) { return g_index; }
+
+extern "C" void mpm_mesh_free(mpm_mesh_t* m) {
+  if (!m) return;
+  void* ptrs[] = {m->d_leaf, m->d_leaf_key, m->d_cell_nodes, m->d_cell_code, m->d_cell_cmat, m->d_node_ijk,
+                  m->d_hang_ijk, m->d_hang_sup, m->d_hang_w, m->d_hang_owner, m->d_perm, m->d_pleaf, m->d_pnleaf,
+                  m->d_row_ptr, m->d_col, m->d_slot, m->d_stride, m->d_strad, m->d_strad_leaf, m->d_err,
+                  m->d_partial, m->d_scratch};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete m;
+}
+
+extern "C" int32_t octree_build(const mpm_refine_t* crit, const double* x, const double* l, int64_t n, void* stream,
+                                mpm_mesh_t** out_mesh) {
+  if (!crit || !out_mesh || n < 0 || (n > 0 && (!x || !l))) {
+    set_error(MPM_EARG, "octree_build: null argument or negative n");
+    return MPM_EARG;
+  }
+  *out_mesh = nullptr;
+  hipStream_t st = (hipStream_t)stream;
+  HostTree T;
+  int lat[3];
+  double hmin;
+  int32_t rc = build_tree(*crit, T, lat, &hmin);
+  if (rc) return rc;
+  mpm_mesh* m = new mpm_mesh();
+  m->crit = *crit;
+  m->nx = lat[0];
+  m->ny = lat[1];
+  m->nz = lat[2];
+  m->hmin = hmin;
+  m->n_leaf = int64_t(T.leaf_key.size());
+  m->n_node = int64_t(T.node_ijk.size() / 3);
+  m->n_hang = int64_t(T.hang_owner.size());
+  while ((int64_t(1) << m->leaf_bits) < m->n_leaf + 1) ++m->leaf_bits;
+  if (kSubBits + m->leaf_bits > 64) {
+    set_error(MPM_ESTENCIL, "octree_build: too many leaves for 64-bit point keys");
+    mpm_mesh_free(m);
+    return MPM_ESTENCIL;
+  }
+#define UP(dst, v)                     \
+  if ((rc = upload(&(dst), v, st))) { \
+    mpm_mesh_free(m);                  \
+    return rc;                         \
+  }
+  UP(m->d_leaf, T.leaf);
+  UP(m->d_leaf_key, T.leaf_key);
+  UP(m->d_cell_nodes, T.cell_nodes);
+  UP(m->d_cell_code, T.cell_code);
+  UP(m->d_cell_cmat, T.cell_cmat);
+  UP(m->d_node_ijk, T.node_ijk);
+  UP(m->d_hang_ijk, T.hang_ijk);
+  UP(m->d_hang_sup, T.hang_sup);
+  UP(m->d_hang_w, T.hang_w);
+  UP(m->d_hang_owner, T.hang_owner);
+  if (hipMalloc(&m->d_err, sizeof(DevErr)) != hipSuccess || hipMemsetAsync(m->d_err, 0, sizeof(DevErr), st) != hipSuccess) {
+    mpm_mesh_free(m);
+    return hip_fail(hipErrorOutOfMemory, "octree_build: error word");
+  }
+  m->n_point = n;
+  std::vector<int32_t> pleaf;
+  std::vector<uint8_t> pnleaf;
+  std::vector<int64_t> strad;
+  std::vector<int32_t> sleaf;
+  if (n > 0) {
+    const double *dx = x, *dl = l;
+    double *tx = nullptr, *tl = nullptr;
+    auto cleanup = [&]() {
+      if (tx) (void)hipFree(tx);
+      if (tl) (void)hipFree(tl);
+    };
+    if (!is_device_ptr(x) || !is_device_ptr(l)) {
+      hipError_t e1 = hipMalloc(&tx, size_t(3 * n) * 8), e2 = hipMalloc(&tl, size_t(3 * n) * 8);
+      if (e1 != hipSuccess || e2 != hipSuccess) {
+        cleanup();
+        mpm_mesh_free(m);
+        return hip_fail(e1 != hipSuccess ? e1 : e2, "octree_build: point upload");
+      }
+      (void)hipMemcpyAsync(tx, x, size_t(3 * n) * 8, hipMemcpyHostToDevice, st);
+      (void)hipMemcpyAsync(tl, l, size_t(3 * n) * 8, hipMemcpyHostToDevice, st);
+      dx = tx;
+      dl = tl;
+    }
+    hipError_t e = hipMalloc(&m->d_perm, size_t(n) * 8);
+    if (e == hipSuccess) e = hipMalloc(&m->d_pleaf, size_t(n) * 4);
+    if (e == hipSuccess) e = hipMalloc(&m->d_pnleaf, size_t(n));
+    if (e != hipSuccess) {
+      cleanup();
+      mpm_mesh_free(m);
+      return hip_fail(e, "octree_build: point arrays");
+    }
+    rc = sort_points(m, dx, n, m->d_perm, m->d_pleaf, st);
+    if (!rc) rc = read_error(m, st, "octree_build (point keys)");
+    if (!rc) {
+      const LeafGeo G = make_geo(m);
+      hipLaunchKernelGGL(k_classify, dim3((n + 255) / 256), dim3(256), 0, st, dx, dl, n, m->d_perm, m->d_pleaf, G,
+                         m->d_pnleaf, m->d_err);
+      rc = read_error(m, st, "octree_build (domain overlaps)");
+    }
+    if (!rc) {
+      pleaf.resize(n);
+      pnleaf.resize(n);
+      if (hipMemcpy(pleaf.data(), m->d_pleaf, size_t(n) * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(pnleaf.data(), m->d_pnleaf, size_t(n), hipMemcpyDeviceToHost) != hipSuccess)
+        rc = hip_fail(hipGetLastError(), "octree_build: copy classification");
+    }
+    if (!rc) {
+      for (int64_t i = 0; i < n; ++i)
+        if (pnleaf[i] > 1) strad.push_back(i);
+      m->n_straddle = int64_t(strad.size());
+      if (!strad.empty()) {
+        rc = upload(&m->d_strad, strad, st);
+        if (!rc) rc = (hipMalloc(&m->d_strad_leaf, strad.size() * kMaxPointLeaves * 4) == hipSuccess)
+                          ? MPM_OK
+                          : hip_fail(hipErrorOutOfMemory, "octree_build: straddle list");
+        if (!rc) {
+          const LeafGeo G = make_geo(m);
+          hipLaunchKernelGGL(k_strad_leaves, dim3((strad.size() + 255) / 256), dim3(256), 0, st, dx, dl, n,
+                             m->d_perm, m->d_pleaf, m->d_strad, int64_t(strad.size()), G, m->d_strad_leaf);
+          sleaf.resize(strad.size() * kMaxPointLeaves);
+          if (hipMemcpyAsync(sleaf.data(), m->d_strad_leaf, sleaf.size() * 4, hipMemcpyDeviceToHost, st) !=
+                  hipSuccess ||
+              hipStreamSynchronize(st) != hipSuccess)
+            rc = hip_fail(hipGetLastError(), "octree_build: copy straddle leaves");
+        }
+      }
+    }
+    (void)hipStreamSynchronize(st);
+    cleanup();
+    if (rc) {
+      mpm_mesh_free(m);
+      return rc;
+    }
+  }
+
+  // CSR pattern: pairs of nodes sharing a point support, 3x3 blocks
+  const int64_t nl = m->n_leaf, nn = m->n_node;
+  std::vector<uint8_t> populated(nl, 0);
+  for (int64_t i = 0; i < n; ++i)
+    if (pnleaf[i] == 1) populated[pleaf[i]] = 1;
+  std::vector<uint64_t> pairs;
+  int64_t npop = 0;
+  for (int64_t e = 0; e < nl; ++e) npop += populated[e];
+  pairs.reserve(size_t(npop) * 64 + size_t(m->n_straddle) * 200);
+  for (int64_t e = 0; e < nl; ++e) {
+    if (!populated[e]) continue;
+    const int32_t* s = &T.cell_nodes[8 * e];
+    for (int a = 0; a < 8; ++a)
+      for (int b = 0; b < 8; ++b) pairs.push_back((uint64_t(uint32_t(s[a])) << 32) | uint32_t(s[b]));
+  }
+  m->max_support = npop ? 8 : 0;
+  for (int64_t t = 0; t < m->n_straddle; ++t) {
+    int32_t sup[kMaxPointLeaves * 8];
+    int ns = 0;
+    for (int k = 0; k < kMaxPointLeaves; ++k) {
+      const int32_t e = sleaf[t * kMaxPointLeaves + k];
+      if (e < 0) break;
+      for (int v = 0; v < 8; ++v) {
+        const int32_t id = T.cell_nodes[8 * int64_t(e) + v];
+        bool f = false;
+        for (int z = 0; z < ns; ++z) f |= sup[z] == id;
+        if (!f) sup[ns++] = id;
+      }
+    }
+    m->max_support = std::max(m->max_support, ns);
+    for (int a = 0; a < ns; ++a)
+      for (int b = 0; b < ns; ++b) pairs.push_back((uint64_t(uint32_t(sup[a])) << 32) | uint32_t(sup[b]));
+  }
+  std::sort(pairs.begin(), pairs.end());
+  pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
+  std::vector<int64_t> nb_off(nn + 1, 0);
+  for (uint64_t pr : pairs) nb_off[(pr >> 32) + 1]++;
+  for (int64_t a = 0; a < nn; ++a) nb_off[a + 1] += nb_off[a];
+  std::vector<int64_t> row_ptr(3 * nn + 1, 0);
+  for (int64_t a = 0; a < nn; ++a) {
+    const int64_t deg = nb_off[a + 1] - nb_off[a];
+    for (int c = 0; c < 3; ++c) row_ptr[3 * a + c + 1] = row_ptr[3 * a + c] + 3 * deg;
+    if (deg) m->n_active_rows += 3;
+  }
+  m->nnz = row_ptr[3 * nn];
+  if (m->nnz >= (int64_t(1) << 62)) {
+    set_error(MPM_EARG, "octree_build: nnz overflow");
+    mpm_mesh_free(m);
+    return MPM_EARG;
+  }
+  std::vector<int32_t> col(size_t(m->nnz));
+  for (int64_t a = 0; a < nn; ++a)
+    for (int c = 0; c < 3; ++c) {
+      int64_t w = row_ptr[3 * a + c];
+      for (int64_t t = nb_off[a]; t < nb_off[a + 1]; ++t) {
+        const int32_t b = int32_t(pairs[t] & 0xffffffffu);
+        for (int k = 0; k < 3; ++k) col[w++] = 3 * b + k;
+      }
+    }
+  // slot map of populated leaves: CSR offset of block (a,b) and row length of slot a
+  std::vector<int64_t> slot(size_t(nl) * 64, -1);
+  std::vector<int32_t> stride(size_t(nl) * 8, 0);
+  for (int64_t e = 0; e < nl; ++e) {
+    if (!populated[e]) continue;
+    const int32_t* s = &T.cell_nodes[8 * e];
+    for (int a = 0; a < 8; ++a) {
+      const int64_t na = s[a];
+      const uint64_t* lo = pairs.data() + nb_off[na];
+      const uint64_t* hi = pairs.data() + nb_off[na + 1];
+      stride[8 * e + a] = int32_t(3 * (nb_off[na + 1] - nb_off[na]));
+      for (int b = 0; b < 8; ++b) {
+        const uint64_t key = (uint64_t(uint32_t(na)) << 32) | uint32_t(s[b]);
+        const uint64_t* it = std::lower_bound(lo, hi, key);
+        slot[64 * e + 8 * a + b] = row_ptr[3 * na] + 3 * int64_t(it - lo);
+      }
+    }
+  }
+  UP(m->d_row_ptr, row_ptr);
+  UP(m->d_col, col);
+  UP(m->d_slot, slot);
+  UP(m->d_stride, stride);
+#undef UP
+  if (hipMalloc(&m->d_partial, 4096 * sizeof(double)) != hipSuccess) {
+    mpm_mesh_free(m);
+    return hip_fail(hipErrorOutOfMemory, "octree_build: partials");
+  }
+  hipError_t e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    mpm_mesh_free(m);
+    return hip_fail(e, "octree_build: final sync");
+  }
+  *out_mesh = m;
+  return MPM_OK;
+}
+
+extern "C" int32_t mpm_mesh_info(const mpm_mesh_t* m, mpm_mesh_info_t* o) {
+  if (!m || !o) {
+    set_error(MPM_EARG, "mpm_mesh_info: null argument");
+    return MPM_EARG;
+  }
+  o->n_leaf = m->n_leaf;
+  o->n_node = m->n_node;
+  o->n_hang = m->n_hang;
+  o->n_dof = 3 * m->n_node;
+  o->nnz = m->nnz;
+  o->n_point = m->n_point;
+  o->n_straddle = m->n_straddle;
+  o->n_active_rows = m->n_active_rows;
+  o->max_support = m->max_support;
+  o->lattice[0] = m->nx;
+  o->lattice[1] = m->ny;
+  o->lattice[2] = m->nz;
+  o->h_min = m->hmin;
+  return MPM_OK;
+}
+
+extern "C" int32_t mpm_mesh_arrays(const mpm_mesh_t* m, mpm_mesh_arrays_t* o) {
+  if (!m || !o) {
+    set_error(MPM_EARG, "mpm_mesh_arrays: null argument");
+    return MPM_EARG;
+  }
+  o->leaf = m->d_leaf;
+  o->node_ijk = m->d_node_ijk;
+  o->hang_ijk = m->d_hang_ijk;
+  o->hang_support = m->d_hang_sup;
+  o->hang_weight = m->d_hang_w;
+  o->hang_owner = m->d_hang_owner;
+  o->cell_nodes = m->d_cell_nodes;
+  o->cell_cmat = m->d_cell_cmat;
+  o->perm = m->d_perm;
+  o->point_leaf = m->d_pleaf;
+  o->point_nleaf = m->d_pnleaf;
+  o->row_ptr = m->d_row_ptr;
+  o->col = m->d_col;
+  return MPM_OK;
+}
+
+extern "C" int32_t mpm_point_sort(const mpm_mesh_t* m, const double* x, int64_t n, int64_t* perm_out,
+                                  int32_t* leaf_out, void* stream) {
+  if (!m || !x || !perm_out || !leaf_out || n != m->n_point) {
+    set_error(MPM_EARG, "mpm_point_sort: null argument or n differs from the mesh's point count");
+    return MPM_EARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  int32_t rc = sort_points(m, x, n, perm_out, leaf_out, st);
+  return rc;
+}
+
+extern "C" int32_t mpm_permute(const mpm_mesh_t* m, const int64_t* perm, const double* src, double* dst,
+                               int32_t ncomp, void* stream) {
+  if (!m || !src || !dst || ncomp <= 0) {
+    set_error(MPM_EARG, "mpm_permute: null argument");
+    return MPM_EARG;
+  }
+  const int64_t n = m->n_point;
+  if (n == 0) return MPM_OK;
+  hipLaunchKernelGGL(k_permute, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, perm ? perm : m->d_perm,
+                     src, dst, n, ncomp);
+  MPM_HIP(hipGetLastError());
+  return MPM_OK;
+}

@@ -1,0 +1,304 @@
+// Per-material-point arithmetic of the assembly, templated on the working precision T.
+//
+//  - discrete GIMP basis (one-point rule on each domain/leaf overlap box, Section 3.2,
+//    eq. GIMP numerical) mapped through the hanging-node constraints (Section 3.1, hanging
+//    node basis): phi~_slot = sum_vertex C_K[vertex][slot] phi_vertex;
+//  - Hencky elasticity with a von Mises perfect-plasticity return in principal logarithmic
+//    strains (Section 2.2), computed from Y = b_tr - I so that small strains keep their
+//    relative accuracy (eps_a = log1p(y_a) / 2);
+//  - the linearisation of the Kirchhoff stress in the principal frame of b_tr: for a
+//    displacement-gradient variation Z, dtau~_aa = sum_c D_ac Z~_cc and
+//    dtau~_ab = G_eff theta_ab (Z~_ab x_b + x_a Z~_ba), theta_ab = (ln x_a - ln x_b)/(x_a - x_b).
+#pragma once
+#include "geom.h"
+
+namespace mpm {
+
+template <typename T>
+__device__ __forceinline__ T t_log1p(T v);
+template <>
+__device__ __forceinline__ double t_log1p<double>(double v) { return log1p(v); }
+template <>
+__device__ __forceinline__ float t_log1p<float>(float v) { return log1pf(v); }
+template <typename T>
+__device__ __forceinline__ T t_sqrt(T v);
+template <>
+__device__ __forceinline__ double t_sqrt<double>(double v) { return sqrt(v); }
+template <>
+__device__ __forceinline__ float t_sqrt<float>(float v) { return sqrtf(v); }
+template <typename T>
+__device__ __forceinline__ T t_exp(T v);
+template <>
+__device__ __forceinline__ double t_exp<double>(double v) { return exp(v); }
+template <>
+__device__ __forceinline__ float t_exp<float>(float v) { return expf(v); }
+
+template <typename T>
+struct Eps;
+template <>
+struct Eps<double> {
+  static constexpr double v = 1e-16;
+};
+template <>
+struct Eps<float> {
+  static constexpr float v = 6e-8f;
+};
+
+// trilinear vertex functions and gradients of a leaf at local coordinates xi (vertex v has
+// bit a = 1 at xi_a = 1), then the constraint map to the 8 slots of I(K)
+template <typename T>
+__device__ __forceinline__ void slot_basis(const T xi[3], T inv_h, int32_t code, T wgt, T S[8], T dS[8][3]) {
+  T w[3][2];
+  for (int a = 0; a < 3; ++a) {
+    w[a][0] = T(1) - xi[a];
+    w[a][1] = xi[a];
+  }
+  T ph[8], g0[8], g1[8], g2[8];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    const int b0 = v & 1, b1 = (v >> 1) & 1, b2 = (v >> 2) & 1;
+    const T s0 = b0 ? inv_h : -inv_h, s1 = b1 ? inv_h : -inv_h, s2 = b2 ? inv_h : -inv_h;
+    ph[v] = w[0][b0] * w[1][b1] * w[2][b2];
+    g0[v] = s0 * w[1][b1] * w[2][b2];
+    g1[v] = w[0][b0] * s1 * w[2][b2];
+    g2[v] = w[0][b0] * w[1][b1] * s2;
+  }
+  const int hm = code_hmask(code);
+  if (hm == 0) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      S[k] = ph[k] * wgt;
+      dS[k][0] = g0[k] * wgt;
+      dS[k][1] = g1[k] * wgt;
+      dS[k][2] = g2[k] * wgt;
+    }
+    return;
+  }
+  const int cc = code_child(code);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    T s = 0, d0 = 0, d1 = 0, d2 = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int M = (j ^ cc) & 7;
+      const int nm = (M & 1) + ((M >> 1) & 1) + ((M >> 2) & 1);
+      const bool hj = (hm >> j) & 1;
+      T c;
+      if (hj) c = (((j ^ k) & ~M & 7) == 0) ? (nm == 1 ? T(0.5) : T(0.25)) : T(0);
+      else c = (j == k) ? T(1) : T(0);
+      s += c * ph[j];
+      d0 += c * g0[j];
+      d1 += c * g1[j];
+      d2 += c * g2[j];
+    }
+    S[k] = s * wgt;
+    dS[k][0] = d0 * wgt;
+    dS[k][1] = d1 * wgt;
+    dS[k][2] = d2 * wgt;
+  }
+}
+
+// one Jacobi rotation annihilating the (p,q) entry of the symmetric A (storage a[p][q]),
+// accumulating the eigenvectors in the columns of V
+template <typename T>
+__device__ __forceinline__ void jrot(T A[3][3], T V[3][3], int p, int q, int r) {
+  const T apq = A[p][q];
+  if (apq == T(0)) return;
+  const T th = (A[q][q] - A[p][p]) / (T(2) * apq);
+  const T t = (th >= T(0) ? T(1) : T(-1)) / (fabs(th) + t_sqrt<T>(T(1) + th * th));
+  const T c = T(1) / t_sqrt<T>(T(1) + t * t), s = t * c;
+  A[p][p] -= t * apq;
+  A[q][q] += t * apq;
+  A[p][q] = A[q][p] = T(0);
+  const T arp = A[r][p], arq = A[r][q];
+  A[r][p] = A[p][r] = c * arp - s * arq;
+  A[r][q] = A[q][r] = s * arp + c * arq;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const T vip = V[i][p], viq = V[i][q];
+    V[i][p] = c * vip - s * viq;
+    V[i][q] = s * vip + c * viq;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void eig_sym3(T A[3][3], T y[3], T V[3][3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) V[i][j] = i == j ? T(1) : T(0);
+  const T scale = fabs(A[0][0]) + fabs(A[1][1]) + fabs(A[2][2]) + fabs(A[0][1]) + fabs(A[0][2]) + fabs(A[1][2]);
+  const T tol = Eps<T>::v * scale;
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    const T off = fabs(A[0][1]) + fabs(A[0][2]) + fabs(A[1][2]);
+    if (!(off > tol)) break;
+    jrot(A, V, 0, 1, 2);
+    jrot(A, V, 0, 2, 1);
+    jrot(A, V, 1, 2, 0);
+  }
+  y[0] = A[0][0];
+  y[1] = A[1][1];
+  y[2] = A[2][2];
+}
+
+// material state of one point after the return map
+template <typename T>
+struct PointMat {
+  T N[3][3];     // eigenvectors of b_tr (columns)
+  T x[3];        // eigenvalues of b_tr
+  T tp[3];       // principal Kirchhoff stresses
+  T D[3][3];     // algorithmic principal moduli d tau_a / d eps_b
+  T Geff;        // shear modulus of the return (G or G r)
+  T th01, th02, th12;
+  T tau[3][3];   // Kirchhoff stress
+  T eps[3], s_hat[3], r, lam, G;
+  bool plastic;
+};
+
+template <typename T>
+__device__ __forceinline__ T theta_pair(T ya, T yb) {
+  // (ln x_a - ln x_b)/(x_a - x_b) with x = 1 + y, through log1p of the ratio minus one
+  const T d = ya - yb;
+  if (d == T(0)) return T(1) / (T(1) + yb);
+  return t_log1p<T>(d / (T(1) + yb)) / d;
+}
+
+// returns 0 or a negative status
+template <typename T>
+__device__ __forceinline__ int material(const T H[3][3], const T B[3][3], double Ed, double nud, double syd,
+                                        PointMat<T>& P) {
+  // Y = b_tr - I = H + H^T + H H^T + (I+H) (b_n - I) (I+H)^T
+  T A1[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      T t = 0;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) t += ((i == m ? T(1) : T(0)) + H[i][m]) * B[m][j];
+      A1[i][j] = t;
+    }
+  T Y[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      T t = H[i][j] + H[j][i];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) t += H[i][m] * H[j][m] + A1[i][m] * ((j == m ? T(1) : T(0)) + H[j][m]);
+      Y[i][j] = Y[j][i] = t;
+    }
+  T y[3];
+  eig_sym3(Y, y, P.N);
+  if (!(y[0] > T(-1)) || !(y[1] > T(-1)) || !(y[2] > T(-1))) return MPM_EDET;
+  const T E = T(Ed), nu = T(nud);
+  const T lam = E * nu / ((T(1) + nu) * (T(1) - T(2) * nu));
+  const T G = E / (T(2) * (T(1) + nu));
+  const T Kb = lam + T(2) * G / T(3);
+  P.lam = lam;
+  P.G = G;
+  T tr = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    P.x[a] = T(1) + y[a];
+    P.eps[a] = T(0.5) * t_log1p<T>(y[a]);
+    tr += P.eps[a];
+  }
+  T t[3], s[3], p = 0, ns = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    t[a] = lam * tr + T(2) * G * P.eps[a];
+    p += t[a];
+  }
+  p /= T(3);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    s[a] = t[a] - p;
+    ns += s[a] * s[a];
+  }
+  ns = t_sqrt<T>(ns);
+  const T q = t_sqrt<T>(T(1.5)) * ns;
+  P.plastic = isfinite(syd) && (q - T(syd) > T(0));
+  const T inv_ns = ns > T(0) ? T(1) / ns : T(0);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) P.s_hat[a] = s[a] * inv_ns;
+  if (P.plastic) {
+    const T r = t_sqrt<T>(T(2) / T(3)) * T(syd) * inv_ns;
+    P.r = r;
+    P.Geff = G * r;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      P.tp[a] = p + r * s[a];
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+        P.D[a][b] = Kb + T(2) * G * r * ((a == b ? T(1) : T(0)) - T(1) / T(3) - P.s_hat[a] * P.s_hat[b]);
+    }
+  } else {
+    P.r = T(1);
+    P.Geff = G;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      P.tp[a] = t[a];
+#pragma unroll
+      for (int b = 0; b < 3; ++b) P.D[a][b] = lam + (a == b ? T(2) * G : T(0));
+    }
+  }
+  P.th01 = theta_pair(y[0], y[1]);
+  P.th02 = theta_pair(y[0], y[2]);
+  P.th12 = theta_pair(y[1], y[2]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      T v = 0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) v += P.tp[a] * P.N[i][a] * P.N[j][a];
+      P.tau[i][j] = P.tau[j][i] = v;
+    }
+  return 0;
+}
+
+// variation of tau for Z = e_k (x) g (principal-frame formula), symmetric result dt[3][3]
+template <typename T>
+__device__ __forceinline__ void dtau_rank1(const PointMat<T>& P, int k, const T gt[3], T dt[3][3]) {
+  // Z~ = (N^T e_k)(N^T g)^T: Z~_ab = N[k][a] gt[b]
+  const T z0 = P.N[k][0] * gt[0], z1 = P.N[k][1] * gt[1], z2 = P.N[k][2] * gt[2];
+  const T d0 = P.D[0][0] * z0 + P.D[0][1] * z1 + P.D[0][2] * z2;
+  const T d1 = P.D[1][0] * z0 + P.D[1][1] * z1 + P.D[1][2] * z2;
+  const T d2 = P.D[2][0] * z0 + P.D[2][1] * z1 + P.D[2][2] * z2;
+  const T o01 = P.Geff * P.th01 * (P.N[k][0] * gt[1] * P.x[1] + P.x[0] * P.N[k][1] * gt[0]);
+  const T o02 = P.Geff * P.th02 * (P.N[k][0] * gt[2] * P.x[2] + P.x[0] * P.N[k][2] * gt[0]);
+  const T o12 = P.Geff * P.th12 * (P.N[k][1] * gt[2] * P.x[2] + P.x[1] * P.N[k][2] * gt[1]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      const T v = d0 * P.N[i][0] * P.N[j][0] + d1 * P.N[i][1] * P.N[j][1] + d2 * P.N[i][2] * P.N[j][2] +
+                  o01 * (P.N[i][0] * P.N[j][1] + P.N[i][1] * P.N[j][0]) +
+                  o02 * (P.N[i][0] * P.N[j][2] + P.N[i][2] * P.N[j][0]) +
+                  o12 * (P.N[i][1] * P.N[j][2] + P.N[i][2] * P.N[j][1]);
+      dt[i][j] = dt[j][i] = v;
+    }
+}
+
+// kinematics from nodal displacements: H = sum u (x) dS, dF = I + H, inverse, det
+template <typename T>
+__device__ __forceinline__ T inv3(const T F[3][3], T R[3][3]) {
+  const T c00 = F[1][1] * F[2][2] - F[1][2] * F[2][1];
+  const T c01 = F[1][2] * F[2][0] - F[1][0] * F[2][2];
+  const T c02 = F[1][0] * F[2][1] - F[1][1] * F[2][0];
+  const T det = F[0][0] * c00 + F[0][1] * c01 + F[0][2] * c02;
+  const T id = T(1) / det;
+  R[0][0] = c00 * id;
+  R[1][0] = c01 * id;
+  R[2][0] = c02 * id;
+  R[0][1] = (F[0][2] * F[2][1] - F[0][1] * F[2][2]) * id;
+  R[1][1] = (F[0][0] * F[2][2] - F[0][2] * F[2][0]) * id;
+  R[2][1] = (F[0][1] * F[2][0] - F[0][0] * F[2][1]) * id;
+  R[0][2] = (F[0][1] * F[1][2] - F[0][2] * F[1][1]) * id;
+  R[1][2] = (F[0][2] * F[1][0] - F[0][0] * F[1][2]) * id;
+  R[2][2] = (F[0][0] * F[1][1] - F[0][1] * F[1][0]) * id;
+  return det;
+}
+
+}  // namespace mpm

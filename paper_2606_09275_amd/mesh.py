@@ -1,0 +1,190 @@
+"""Python front end of the C ABI: torch tensors in, torch tensors out (marshalling only;
+every step runs in the HIP library)."""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import torch
+
+from . import _lib
+from ._lib import MPM_F32K, MPM_F64, check, lib
+
+PRECISION = {"f64": MPM_F64, "fp64": MPM_F64, "f32k": MPM_F32K, "fp32k": MPM_F32K, MPM_F64: MPM_F64,
+             MPM_F32K: MPM_F32K}
+STATE_KEYS = ("x", "l", "vol", "mass", "Jn", "bn", "Fn", "E", "nu", "sy")
+_D2D = 3
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def refine_struct(crit: dict) -> _lib.RefineT:
+    r = _lib.RefineT()
+    r.lo = (C.c_double * 3)(*crit["lo"])
+    r.base = (C.c_int32 * 3)(*crit["base"])
+    r.h0 = crit["h0"]
+    r.lvl_base = crit["lvl_base"]
+    r.lvl_max = crit["lvl_max"]
+    r.body_kind = crit["body_kind"]
+    b = list(crit.get("body", ())) + [0.0] * (8 - len(crit.get("body", ())))
+    r.body = (C.c_double * 8)(*b)
+    r.dx_region = crit["dx_region"]
+    return r
+
+
+class Mesh:
+    """Octree mesh + point order + CSR pattern, owned by the HIP library."""
+
+    def __init__(self, crit: dict, x: Optional[torch.Tensor] = None, l: Optional[torch.Tensor] = None):
+        self._crit = refine_struct(crit)
+        self.crit = dict(crit)
+        h = C.c_void_p()
+        n = 0 if x is None else int(x.shape[1])
+        xp = lp = None
+        if x is not None:
+            x = x.contiguous()
+            l = l.contiguous()
+            xp = C.c_void_p(x.data_ptr()) if x.is_cuda else x.numpy().ctypes.data_as(C.c_void_p)
+            lp = C.c_void_p(l.data_ptr()) if l.is_cuda else l.numpy().ctypes.data_as(C.c_void_p)
+        check(lib().octree_build(C.byref(self._crit), xp, lp, n, _stream(), C.byref(h)))
+        self.h = h
+        inf = _lib.MeshInfoT()
+        check(lib().mpm_mesh_info(self.h, C.byref(inf)))
+        self.info = {k: (list(getattr(inf, k)) if k == "lattice" else getattr(inf, k)) for k, _ in inf._fields_}
+        self._arrays = None
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            lib().mpm_mesh_free(h)
+            self.h = None
+
+    # -------------------------------------------------------------- inspection
+    def _copy(self, ptr, shape, dtype):
+        out = torch.empty(shape, dtype=dtype, device="cuda")
+        nbytes = out.numel() * out.element_size()
+        if nbytes:
+            torch.cuda.synchronize()
+            rc = _lib.hip().hipMemcpy(C.c_void_p(out.data_ptr()), C.c_void_p(ptr), nbytes, _D2D)
+            if rc != 0:
+                raise RuntimeError(f"hipMemcpy failed ({rc})")
+        return out
+
+    def arrays(self) -> dict:
+        if self._arrays is None:
+            a = _lib.MeshArraysT()
+            check(lib().mpm_mesh_arrays(self.h, C.byref(a)))
+            i = self.info
+            self._arrays = {
+                "leaf": self._copy(a.leaf, (i["n_leaf"], 4), torch.int32),
+                "node_ijk": self._copy(a.node_ijk, (i["n_node"], 3), torch.int32),
+                "hang_ijk": self._copy(a.hang_ijk, (i["n_hang"], 3), torch.int32),
+                "hang_support": self._copy(a.hang_support, (i["n_hang"], 4), torch.int32),
+                "hang_weight": self._copy(a.hang_weight, (i["n_hang"], 4), torch.float64),
+                "hang_owner": self._copy(a.hang_owner, (i["n_hang"],), torch.int32),
+                "cell_nodes": self._copy(a.cell_nodes, (i["n_leaf"], 8), torch.int32),
+                "cell_cmat": self._copy(a.cell_cmat, (i["n_leaf"], 8, 8), torch.float64),
+                "perm": self._copy(a.perm, (i["n_point"],), torch.int64),
+                "point_leaf": self._copy(a.point_leaf, (i["n_point"],), torch.int32),
+                "point_nleaf": self._copy(a.point_nleaf, (i["n_point"],), torch.uint8),
+                "row_ptr": self._copy(a.row_ptr, (i["n_dof"] + 1,), torch.int64),
+                "col": self._copy(a.col, (i["nnz"],), torch.int32),
+            }
+        return self._arrays
+
+    # -------------------------------------------------------------- point order
+    def permute(self, src: torch.Tensor, perm: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """[ncomp, n] (or [n]) original-order float64 device tensor -> sorted order."""
+        flat = src.dim() == 1
+        s = src.reshape(1, -1) if flat else src
+        s = s.contiguous().to(torch.float64)
+        out = torch.empty_like(s)
+        check(lib().mpm_permute(self.h, _ptr(perm), _ptr(s), _ptr(out), int(s.shape[0]), _stream()))
+        return out.reshape(-1) if flat else out
+
+    def point_sort(self, x: torch.Tensor, perm_out=None, leaf_out=None):
+        n = int(x.shape[1])
+        perm_out = torch.empty(n, dtype=torch.int64, device="cuda") if perm_out is None else perm_out
+        leaf_out = torch.empty(n, dtype=torch.int32, device="cuda") if leaf_out is None else leaf_out
+        check(lib().mpm_point_sort(self.h, _ptr(x.contiguous()), n, _ptr(perm_out), _ptr(leaf_out), _stream()))
+        return perm_out, leaf_out
+
+    def sorted_state(self, state: dict) -> dict:
+        """Original-order state (numpy or torch, [ncomp, n]) -> sorted-order device tensors."""
+        out = {}
+        for k in STATE_KEYS:
+            v = state.get(k)
+            if v is None:
+                continue
+            t = torch.as_tensor(v, dtype=torch.float64).cuda()
+            out[k] = self.permute(t)
+        out["g"] = tuple(state.get("g", (0.0, 0.0, -9.81)))
+        return out
+
+    # -------------------------------------------------------------- compute
+    @staticmethod
+    def _state(s: dict) -> _lib.StateT:
+        st = _lib.StateT()
+        for k in STATE_KEYS:
+            t = s.get(k)
+            setattr(st, k, None if t is None else _ptr(t).value)
+        st.g = (C.c_double * 3)(*s.get("g", (0.0, 0.0, -9.81)))
+        return st
+
+    def external_force(self, s: dict, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        out = torch.empty(self.info["n_dof"], dtype=torch.float64, device="cuda") if out is None else out
+        st = self._state(s)
+        check(lib().mpm_external_force(self.h, C.byref(st), _ptr(out), _stream()))
+        return out
+
+    def assemble(self, s: dict, u: torch.Tensor, precision="f64", f_ext=None, dirichlet=None, want_K=True,
+                 want_sigma=True, want_residual=True, commit=False, out: Optional[dict] = None) -> dict:
+        p = PRECISION[precision]
+        i = self.info
+        n = i["n_point"]
+        o = {} if out is None else out
+        dev = "cuda"
+        if "f_int" not in o:
+            o["f_int"] = torch.empty(i["n_dof"], dtype=torch.float64, device=dev)
+        if want_K and "K" not in o:
+            o["K"] = torch.empty(i["nnz"], dtype=torch.float64 if p == MPM_F64 else torch.float32, device=dev)
+        if want_sigma and "sigma" not in o:
+            o["sigma"] = torch.empty((6, n), dtype=torch.float64, device=dev)
+        if want_residual:
+            o.setdefault("r", torch.empty(i["n_dof"], dtype=torch.float64, device=dev))
+            o.setdefault("rnorm", torch.empty(1, dtype=torch.float64, device=dev))
+        if commit:
+            o.setdefault("F_new", torch.empty((9, n), dtype=torch.float64, device=dev))
+            o.setdefault("be_new", torch.empty((6, n), dtype=torch.float64, device=dev))
+        st = self._state(s)
+        check(lib().mpm_assemble(self.h, C.byref(st), _ptr(u), p, _ptr(f_ext), _ptr(dirichlet), _ptr(o["f_int"]),
+                                 _ptr(o.get("K") if want_K else None), _ptr(o.get("sigma") if want_sigma else None),
+                                 _ptr(o.get("r") if want_residual else None),
+                                 _ptr(o.get("rnorm") if want_residual else None),
+                                 _ptr(o.get("F_new") if commit else None), _ptr(o.get("be_new") if commit else None),
+                                 _stream()))
+        return o
+
+    def adjoint(self, s: dict, u: torch.Tensor, lam: torch.Tensor, precision="f64", out: Optional[dict] = None):
+        p = PRECISION[precision]
+        n = self.info["n_point"]
+        o = {} if out is None else out
+        for k in ("dE", "dnu", "dsy", "dV"):
+            if k not in o:
+                o[k] = torch.empty(n, dtype=torch.float64, device="cuda")
+        st = self._state(s)
+        check(lib().mpm_assemble_adjoint(self.h, C.byref(st), _ptr(u), _ptr(lam), p, _ptr(o["dE"]), _ptr(o["dnu"]),
+                                         _ptr(o["dsy"]), _ptr(o["dV"]), _stream()))
+        return o

@@ -1,0 +1,101 @@
+"""Host part of octree_build (refinement, balance, nodes, hanging-node constraints, I(K), C_K)
+against the oracle, bit-exact, on CPU. The library's host code is compiled with a tiny test
+shim (no GPU call is made)."""
+import ctypes as C
+import subprocess
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.oracle import OracleMesh
+from tests.helpers import tiny_workload
+
+ROOT = Path(__file__).resolve().parent.parent
+SHIM_SRC = ROOT / "tests" / "shim" / "host_tree_shim.cpp"
+SHIM = ROOT / "tests" / "shim" / "libhosttree.so"
+_lib = None
+
+
+def shim():
+    global _lib
+    if _lib is None:
+        srcs = [SHIM_SRC, ROOT / "paper_2606_09275_amd" / "csrc" / "octree_host.cpp"]
+        stale = not SHIM.exists() or any(s.stat().st_mtime > SHIM.stat().st_mtime for s in srcs)
+        if stale:
+            cmd = ["/opt/rocm/bin/hipcc", "-O2", "-std=c++17", "-fPIC", "-shared", "-x", "c++",
+                   "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"] + [str(s) for s in srcs] + ["-o", str(SHIM)]
+            r = subprocess.run(cmd, capture_output=True, text=True)
+            assert r.returncode == 0, r.stderr
+        _lib = C.CDLL(str(SHIM))
+        _lib.shim_build.restype = C.c_int32
+    return _lib
+
+
+class Refine(C.Structure):
+    _fields_ = [("lo", C.c_double * 3), ("base", C.c_int32 * 3), ("h0", C.c_double), ("lvl_base", C.c_int32),
+                ("lvl_max", C.c_int32), ("body_kind", C.c_int32), ("body", C.c_double * 8), ("dx_region", C.c_double)]
+
+
+def host_tree(crit):
+    r = Refine()
+    r.lo = (C.c_double * 3)(*crit["lo"])
+    r.base = (C.c_int32 * 3)(*crit["base"])
+    r.h0, r.lvl_base, r.lvl_max, r.body_kind = crit["h0"], crit["lvl_base"], crit["lvl_max"], crit["body_kind"]
+    r.body = (C.c_double * 8)(*crit["body"])
+    r.dx_region = crit["dx_region"]
+    cnt = np.zeros(3, np.int64)
+    rc = shim().shim_build(C.byref(r), cnt.ctypes.data_as(C.c_void_p))
+    assert rc == 0
+    nl, nn, nh = (int(v) for v in cnt)
+    a = dict(leaf=np.zeros((nl, 4), np.int32), node=np.zeros((nn, 3), np.int32), hang=np.zeros((nh, 3), np.int32),
+             sup=np.zeros((nh, 4), np.int32), w=np.zeros((nh, 4)), owner=np.zeros(nh, np.int32),
+             cell=np.zeros((nl, 8), np.int32), code=np.zeros(nl, np.int32), cmat=np.zeros((nl, 8, 8)))
+    p = lambda k: a[k].ctypes.data_as(C.c_void_p)
+    shim().shim_arrays(p("leaf"), p("node"), p("hang"), p("sup"), p("w"), p("owner"), p("cell"), p("code"), p("cmat"))
+    return a
+
+
+CASES = ["tiny_sphere", "tiny_cone", "tiny_box", "c0", "c1", "c4"]
+
+
+def _work(name):
+    return tiny_workload(name.split("_")[1], lvl_extra=3) if name.startswith("tiny") else W.get(name)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_host_tree_matches_oracle(name):
+    w = _work(name)
+    o = OracleMesh(w.crit())
+    h = host_tree(w.crit())
+    assert np.array_equal(h["leaf"], o.leaves())
+    assert np.array_equal(h["node"], o.nodes())
+    ijk, sup, wt, own = o.hanging()
+    assert np.array_equal(h["hang"], ijk)
+    assert np.array_equal(h["owner"], own)
+    # supports and weights per hanging node, order-free
+    for arr_l, arr_o in ((h["sup"], sup),):
+        key_l = np.sort(np.where(arr_l < 0, np.iinfo(np.int32).max, arr_l), axis=1)
+        key_o = np.sort(np.where(arr_o < 0, np.iinfo(np.int32).max, arr_o), axis=1)
+        assert np.array_equal(key_l, key_o)
+    assert np.array_equal(np.sort(h["w"], axis=1), np.sort(wt, axis=1))
+    # I(K) and C_K: the library's slot order vs the oracle's ascending order
+    n, ids, cm = o.cells()
+    assert np.all(n == 8)
+    order = np.argsort(h["cell"], axis=1)
+    assert np.array_equal(np.take_along_axis(h["cell"], order, axis=1), ids[:, :8])
+    cm_l = np.take_along_axis(h["cmat"], order[:, None, :], axis=2)
+    assert np.array_equal(cm_l, cm[:, :, :8])
+
+
+@pytest.mark.slow
+def test_host_tree_matches_oracle_c2():
+    w = W.get("c2")
+    o = OracleMesh(w.crit())
+    h = host_tree(w.crit())
+    assert np.array_equal(h["leaf"], o.leaves())
+    assert np.array_equal(h["node"], o.nodes())
+    ijk, sup, wt, own = o.hanging()
+    assert np.array_equal(h["hang"], ijk)
+    assert np.array_equal(h["owner"], own)

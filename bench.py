@@ -1,0 +1,248 @@
+#!/usr/bin/env python3
+"""Throughput of the octree GIMP assembly hot path on one GPU.
+
+One step = one pass of the whole hot path over the workload's points:
+  point-to-cell (Morton keys, radix sort, leaf search) + state gather into sorted order,
+  fused assembly (basis, kinematics, Hencky/von Mises return, consistent tangent, per-leaf
+  reduction, scatter into f_int and CSR K) + residual and its FP64 norm,
+  adjoint assembly (dL/dE, dL/dnu, dL/dsigma_y, dL/dV_n per point).
+`value` = points / wall time of one step (FP64 primary run); the FP32-tangent run is
+reported beside it. Inputs are resident in HBM before the timed region starts.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+from pathlib import Path
+
+import numpy as np
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+METRIC = "material points/s for residual+tangent assembly (FP64 vs FP32) + adjoint cost"
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_VEC_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+PEAK_FP32_VEC_TFLOPS = 157.3   # packed FP32 (the library is built without packed FP32 ops)
+
+# Algorithmic cost of one point with an 8-node stencil (flops; FMA = 2):
+# basis 100, kinematics (H, grad_x S, dF^-1) 330, b_tr 90, symmetric 3x3 eigen 400,
+# return map 50, spatial tangent 3000, T_b = a.g_b 1296, upper-triangle K blocks 1944,
+# force 144.
+FLOPS_PER_POINT = 100 + 330 + 90 + 400 + 50 + 3000 + 1296 + 1944 + 144
+# Algorithmic HBM bytes of one assembly launch: per point read x, l (48), V_n, J_n (16),
+# b_n (48), E, nu, sy (24) and write sigma (48) = 184 B; plus K values written once
+# (nnz x 8 or 4) and u read + f_int written once (3 n_node x 16).
+BYTES_PER_POINT = 184
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--cpu-sample", type=int, default=300000, help="points in the oracle CPU baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["f64", "f32k"], default=None, help="time one precision only")
+    ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB device copy (counter calibration)")
+    return ap.parse_args()
+
+
+def calib_copy():
+    import torch
+    n = 1 << 27
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes_read": n * 8, "calib_copy_bytes_written": n * 8, "launches": 3}))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is a "
+              "design note (contiguous Morton ranges per GPU with one halo exchange of interface rows), "
+              "not a measured path.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import workloads as W
+    from paper_2606_09275_amd.mesh import Mesh
+
+    if args.calib_copy:
+        calib_copy()
+        return
+    torch.cuda.set_device(0)
+    w = W.get(args.workload)
+    t0 = time.time()
+    m0 = Mesh(w.crit())
+    lv = m0.arrays()["leaf"].cpu().numpy()
+    del m0
+    ps = W.make_points(w, lv[:, :3], lv[:, 3])
+    st = W.make_state(w, ps)
+    log(f"[bench] workload {w.name}: {ps.n} points, {lv.shape[0]} leaves ({time.time() - t0:.1f}s)")
+    x_dev = torch.from_numpy(ps.x).cuda()
+    l_dev = torch.from_numpy(ps.l).cuda()
+    t0 = time.time()
+    mesh = Mesh(w.crit(), x_dev, l_dev)
+    info = mesh.info
+    log(f"[bench] octree_build {time.time() - t0:.1f}s: nodes {info['n_node']} hanging {info['n_hang']} "
+        f"nnz {info['nnz']} straddle {info['n_straddle']}")
+    nodes = mesh.arrays()["node_ijk"].cpu().numpy()
+    u = torch.from_numpy(W.make_u(w, nodes)).cuda()
+    lam = torch.from_numpy(W.make_lambda(w, nodes)).cuda()
+    dirichlet = torch.from_numpy(W.dirichlet_dofs(nodes)).cuda()
+    n = ps.n
+    # original-order state packed as one [ncomp, n] device array; sorted-order views of a copy
+    keys = [("x", 3), ("l", 3), ("vol", 1), ("mass", 1), ("Jn", 1), ("bn", 6), ("E", 1), ("nu", 1), ("sy", 1)]
+    packed = torch.cat([torch.from_numpy(np.asarray(st[k], np.float64).reshape(c, n)) for k, c in keys]).cuda()
+    sorted_buf = torch.empty_like(packed)
+    views, r = {}, 0
+    for k, c in keys:
+        v = sorted_buf[r:r + c]
+        views[k] = v.reshape(-1) if c == 1 else v
+        r += c
+    views["g"] = (0.0, 0.0, -9.81)
+    perm_buf = torch.empty(n, dtype=torch.int64, device="cuda")
+    leaf_buf = torch.empty(n, dtype=torch.int32, device="cuda")
+    # f_ext is constant over the Newton iterations of a step: computed once, outside the timing
+    mesh.permute(packed, None, out=sorted_buf)
+    f_ext = mesh.external_force(views)
+    torch.cuda.synchronize()
+
+    def step(prec, outs, ev=None):
+        mesh.point_sort(x_dev, perm_buf, leaf_buf)
+        mesh.permute(packed, perm_buf, out=sorted_buf)
+        if ev is not None:
+            ev[0].record()
+        mesh.assemble(views, u, prec, f_ext=f_ext, dirichlet=dirichlet, out=outs["asm"])
+        if ev is not None:
+            ev[1].record()
+        mesh.adjoint(views, u, lam, prec, out=outs["adj"])
+        if ev is not None:
+            ev[2].record()
+
+    results = {}
+    precs = [args.only] if args.only else ["f64", "f32k"]
+    for prec in precs:
+        outs = {"asm": {}, "adj": {}}
+        for _ in range(args.warmup):
+            step(prec, outs)
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+        mesh.kernel_timing(1)
+        mesh.kernel_timing(-1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            evs[k][3].record()
+            step(prec, outs, ev=evs[k])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kt = mesh.kernel_timing(0)
+        ms = (t1 - t0) * 1e3 / args.steps
+        sort_ms = float(np.mean([e[3].elapsed_time(e[0]) for e in evs]))
+        asm_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+        adj_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+        k_asm = kt[0] / max(kt[1], 1)
+        k_adj = kt[2] / max(kt[3], 1)
+        rn = float(outs["asm"]["rnorm"].item())
+        results[prec] = dict(ms_per_step=ms, value=n / (ms * 1e-3), sort_ms=sort_ms, assemble_ms=asm_ms,
+                             adjoint_ms=adj_ms, assemble_kernel_ms=k_asm, adjoint_kernel_ms=k_adj,
+                             assembly_points_per_s=n / (asm_ms * 1e-3), adjoint_points_per_s=n / (adj_ms * 1e-3),
+                             adjoint_over_assembly=adj_ms / asm_ms, rnorm=rn)
+        log(f"[bench] {prec}: step {ms:.3f} ms ({n / ms / 1e3:.3e} pts/s) | sort+gather {sort_ms:.3f} "
+            f"assemble {asm_ms:.3f} (kernel {k_asm:.3f}) adjoint {adj_ms:.3f} (kernel {k_adj:.3f}) ms")
+
+    prim = "f64" if "f64" in results else precs[0]
+    R = results[prim]
+    n_fast = n - info["n_straddle"]
+    kbytes = 8 if prim == "f64" else 4
+    alg_flops = FLOPS_PER_POINT * n_fast
+    alg_bytes = BYTES_PER_POINT * n + info["nnz"] * kbytes + 3 * info["n_node"] * 16
+    kt_s = R["assemble_kernel_ms"] * 1e-3
+    peak = PEAK_FP64_VEC_TFLOPS if prim == "f64" else PEAK_FP32_VEC_TFLOPS
+    roofline = {
+        "bound": "alu", "kernel": "k_assemble_fast<%s>" % ("double" if prim == "f64" else "float"),
+        "achieved": alg_flops / kt_s / 1e12, "peak": peak, "unit": "TFLOP/s",
+        "frac": alg_flops / kt_s / 1e12 / peak, "traffic": None,
+        "flops_per_point": FLOPS_PER_POINT, "points_per_launch": n_fast,
+        "hbm": {"achieved": alg_bytes / kt_s / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": alg_bytes / kt_s / 1e9 / PEAK_HBM_GBS, "bytes_per_launch": alg_bytes},
+    }
+    out = {
+        "metric": METRIC, "value": R["value"], "unit": "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": R["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if prim == "f64" else "f32",
+        "data": "synthetic (seeded octree workload; no experimental data)",
+        "config": {"workload": f"{w.name}: {w.note}", "n_points": n, "n_leaf": info["n_leaf"],
+                   "n_node": info["n_node"], "n_hang": info["n_hang"], "nnz": info["nnz"],
+                   "n_straddle": info["n_straddle"],
+                   "step": "point sort + state gather + assemble (f_int, K, sigma, residual norm) + adjoint"},
+        "phases_ms": {k: R[k] for k in ("sort_ms", "assemble_ms", "adjoint_ms", "assemble_kernel_ms",
+                                        "adjoint_kernel_ms")},
+        "assembly_points_per_s": R["assembly_points_per_s"], "adjoint_points_per_s": R["adjoint_points_per_s"],
+        "adjoint_over_assembly": R["adjoint_over_assembly"],
+        "roofline": roofline,
+    }
+    if "f32k" in results and prim != "f32k":
+        out["fp32k"] = {k: results["f32k"][k] for k in ("value", "ms_per_step", "assembly_points_per_s",
+                                                         "adjoint_points_per_s", "assemble_kernel_ms",
+                                                         "adjoint_kernel_ms")}
+        out["fp32k"]["speedup_assembly_vs_fp64"] = results["f32k"]["assembly_points_per_s"] / R["assembly_points_per_s"]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, ps, st, nodes, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(w, ps, st, nodes, sample):
+    """The FP64 oracle (single thread, as written) on a bounded sample of the same workload:
+    every k-th point, assembly (f_int, K, sigma) + adjoint, points per second."""
+    import workloads as W
+    from oracle.oracle import OracleMesh
+    k = max(1, ps.n // sample)
+    idx = np.arange(0, ps.n, k)
+    o = OracleMesh(w.crit())
+    o.set_points(ps.x[:, idx], ps.l[:, idx])
+    ss = {key: (v[..., idx] if isinstance(v, np.ndarray) else v) for key, v in st.items()}
+    u = W.make_u(w, nodes)
+    lam = W.make_lambda(w, nodes)
+    t0 = time.perf_counter()
+    o.assemble(ss, u)
+    t1 = time.perf_counter()
+    o.adjoint(ss, u, lam)
+    t2 = time.perf_counter()
+    log(f"[bench] cpu oracle: {idx.size} points, assemble {t1 - t0:.2f}s adjoint {t2 - t1:.2f}s")
+    return {"value": idx.size / (t2 - t0), "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": f"every {k}-th point of the workload ({idx.size} points), FP64 assembly of f_int, K, sigma "
+                      f"({t1 - t0:.1f}s) + adjoint ({t2 - t1:.1f}s), single thread",
+            "assembly_points_per_s": idx.size / (t1 - t0), "cpu": _cpu_name(), "host_threads": os.cpu_count()}
+
+
+def _cpu_name():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+if __name__ == "__main__":
+    main()

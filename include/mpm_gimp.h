@@ -185,6 +185,14 @@ int32_t mpm_assemble_adjoint(const mpm_mesh_t* mesh, const mpm_state_t* s, const
                              int32_t precision, double* dL_dE, double* dL_dnu, double* dL_dsy, double* dL_dV,
                              void* stream);
 
+/* Kernel timing for measurement tools. enable = 1: from now on HIP events bracket the fused
+ * assembly kernel (single-leaf points) and the adjoint kernel on the caller's stream, and
+ * their elapsed times accumulate in the handle (read at the synchronisation that ends each
+ * call); enable = 0: stop; enable = -1: only read. ms_out (host, 4 doubles, may be NULL):
+ * [0] assembly-kernel ms summed, [1] its launch count, [2] adjoint-kernel ms, [3] adjoint
+ * launches; reading resets the sums. */
+int32_t mpm_kernel_timing(mpm_mesh_t* mesh, int32_t enable, double* ms_out);
+
 /* last error of the calling thread */
 int32_t mpm_last_error(char* buf, size_t n);
 int64_t mpm_last_error_index(void);

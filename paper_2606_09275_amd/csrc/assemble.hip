@@ -680,11 +680,15 @@ extern "C" int32_t mpm_assemble(const mpm_mesh_t* m, const mpm_state_t* s, const
   MPM_HIP(hipMemsetAsync(f_int, 0, size_t(3 * m->n_node) * 8, st));
   if (K_vals && kbytes) MPM_HIP(hipMemsetAsync(K_vals, 0, kbytes, st));
   const int64_t n = m->n_point;
+  mpm_mesh* mm = const_cast<mpm_mesh*>(m);
+  const bool timed = mm->timing && n;
+  if (timed) MPM_HIP(hipEventRecord(mm->ev[0], st));
   if (n) {
     const dim3 grid(unsigned((n + 63) / 64));
     if (precision == MPM_F64) hipLaunchKernelGGL(k_assemble_fast<double>, grid, dim3(64), 0, st, A);
     else hipLaunchKernelGGL(k_assemble_fast<float>, grid, dim3(64), 0, st, A);
   }
+  if (timed) MPM_HIP(hipEventRecord(mm->ev[1], st));
   if (m->n_straddle) {
     const dim3 grid(unsigned((m->n_straddle + 63) / 64));
     if (precision == MPM_F64) hipLaunchKernelGGL(k_assemble_general<double>, grid, dim3(64), 0, st, A);
@@ -698,7 +702,14 @@ extern "C" int32_t mpm_assemble(const mpm_mesh_t* m, const mpm_state_t* s, const
     if (rnorm) hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(256), 0, st, m->d_partial, nb, rnorm);
   }
   MPM_HIP(hipGetLastError());
-  return read_error(const_cast<mpm_mesh*>(m), st, "mpm_assemble");
+  const int32_t rc = read_error(mm, st, "mpm_assemble");
+  if (timed) {
+    float ms = 0;
+    MPM_HIP(hipEventElapsedTime(&ms, mm->ev[0], mm->ev[1]));
+    mm->t_asm += ms;
+    mm->n_asm += 1;
+  }
+  return rc;
 }
 
 extern "C" int32_t mpm_assemble_adjoint(const mpm_mesh_t* m, const mpm_state_t* s, const double* u,
@@ -718,11 +729,22 @@ extern "C" int32_t mpm_assemble_adjoint(const mpm_mesh_t* m, const mpm_state_t* 
   A.dsy = dsy;
   A.dV = dV;
   const int64_t n = m->n_point;
+  mpm_mesh* mm = const_cast<mpm_mesh*>(m);
+  const bool timed = mm->timing && n;
+  if (timed) MPM_HIP(hipEventRecord(mm->ev[2], st));
   if (n) {
     const dim3 grid(unsigned((n + 63) / 64));
     if (precision == MPM_F64) hipLaunchKernelGGL(k_adjoint<double>, grid, dim3(64), 0, st, A);
     else hipLaunchKernelGGL(k_adjoint<float>, grid, dim3(64), 0, st, A);
   }
+  if (timed) MPM_HIP(hipEventRecord(mm->ev[3], st));
   MPM_HIP(hipGetLastError());
-  return read_error(const_cast<mpm_mesh*>(m), st, "mpm_assemble_adjoint");
+  const int32_t rc = read_error(mm, st, "mpm_assemble_adjoint");
+  if (timed) {
+    float ms = 0;
+    MPM_HIP(hipEventElapsedTime(&ms, mm->ev[2], mm->ev[3]));
+    mm->t_adj += ms;
+    mm->n_adj += 1;
+  }
+  return rc;
 }

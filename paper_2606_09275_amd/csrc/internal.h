@@ -95,4 +95,9 @@ struct mpm_mesh {
   double* d_partial = nullptr;      // residual partial sums
   void* d_scratch = nullptr;        // radix sort scratch
   size_t scratch_bytes = 0;
+  // kernel timing (measurement)
+  bool timing = false;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  double t_asm = 0, t_adj = 0;
+  int64_t n_asm = 0, n_adj = 0;
 };

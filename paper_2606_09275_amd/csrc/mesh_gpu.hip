@@ -329,6 +329,8 @@ extern "C" void mpm_mesh_free(mpm_mesh_t* m) {
                   m->d_partial, m->d_scratch};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  for (hipEvent_t e : m->ev)
+    if (e) (void)hipEventDestroy(e);
   delete m;
 }
 
@@ -614,5 +616,24 @@ extern "C" int32_t mpm_permute(const mpm_mesh_t* m, const int64_t* perm, const d
   hipLaunchKernelGGL(k_permute, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, perm ? perm : m->d_perm,
                      src, dst, n, ncomp);
   MPM_HIP(hipGetLastError());
+  return MPM_OK;
+}
+
+extern "C" int32_t mpm_kernel_timing(mpm_mesh_t* m, int32_t enable, double* ms_out) {
+  if (!m || enable < -1 || enable > 1) {
+    set_error(MPM_EARG, "mpm_kernel_timing: null mesh or bad flag");
+    return MPM_EARG;
+  }
+  if (enable == 1 && !m->ev[0])
+    for (auto& e : m->ev) MPM_HIP(hipEventCreate(&e));
+  if (enable >= 0) m->timing = enable == 1;
+  if (ms_out) {
+    ms_out[0] = m->t_asm;
+    ms_out[1] = double(m->n_asm);
+    ms_out[2] = m->t_adj;
+    ms_out[3] = double(m->n_adj);
+    m->t_asm = m->t_adj = 0;
+    m->n_asm = m->n_adj = 0;
+  }
   return MPM_OK;
 }

@@ -105,14 +105,16 @@ class Mesh:
         return self._arrays
 
     # -------------------------------------------------------------- point order
-    def permute(self, src: torch.Tensor, perm: Optional[torch.Tensor] = None) -> torch.Tensor:
-        """[ncomp, n] (or [n]) original-order float64 device tensor -> sorted order."""
+    def permute(self, src: torch.Tensor, perm: Optional[torch.Tensor] = None,
+                out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """[ncomp, n] (or [n]) original-order float64 device tensor -> sorted order (perm: the
+        mesh's order when None)."""
         flat = src.dim() == 1
         s = src.reshape(1, -1) if flat else src
         s = s.contiguous().to(torch.float64)
-        out = torch.empty_like(s)
-        check(lib().mpm_permute(self.h, _ptr(perm), _ptr(s), _ptr(out), int(s.shape[0]), _stream()))
-        return out.reshape(-1) if flat else out
+        o = torch.empty_like(s) if out is None else out.reshape(s.shape)
+        check(lib().mpm_permute(self.h, _ptr(perm), _ptr(s), _ptr(o), int(s.shape[0]), _stream()))
+        return o.reshape(-1) if flat else o
 
     def point_sort(self, x: torch.Tensor, perm_out=None, leaf_out=None):
         n = int(x.shape[1])
@@ -132,6 +134,13 @@ class Mesh:
             out[k] = self.permute(t)
         out["g"] = tuple(state.get("g", (0.0, 0.0, -9.81)))
         return out
+
+    def kernel_timing(self, enable: int = -1):
+        """enable 1/0 switches event timing of the assembly/adjoint kernels; returns and resets
+        (assembly ms, launches, adjoint ms, launches)."""
+        buf = (C.c_double * 4)()
+        check(lib().mpm_kernel_timing(self.h, int(enable), buf))
+        return tuple(buf)
 
     # -------------------------------------------------------------- compute
     @staticmethod

@@ -161,13 +161,15 @@ def main():
         adj_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
         k_asm = kt[0] / max(kt[1], 1)
         k_adj = kt[2] / max(kt[3], 1)
+        k_gat = kt[4] / max(kt[5], 1)
         rn = float(outs["asm"]["rnorm"].item())
         results[prec] = dict(ms_per_step=ms, value=n / (ms * 1e-3), sort_ms=sort_ms, assemble_ms=asm_ms,
                              adjoint_ms=adj_ms, assemble_kernel_ms=k_asm, adjoint_kernel_ms=k_adj,
+                             gather_kernel_ms=k_gat,
                              assembly_points_per_s=n / (asm_ms * 1e-3), adjoint_points_per_s=n / (adj_ms * 1e-3),
                              adjoint_over_assembly=adj_ms / asm_ms, rnorm=rn)
         log(f"[bench] {prec}: step {ms:.3f} ms ({n / ms / 1e3:.3e} pts/s) | sort+gather {sort_ms:.3f} "
-            f"assemble {asm_ms:.3f} (kernel {k_asm:.3f}) adjoint {adj_ms:.3f} (kernel {k_adj:.3f}) ms")
+            f"assemble {asm_ms:.3f} (kernel {k_asm:.3f} + gather {k_gat:.3f}) adjoint {adj_ms:.3f} (kernel {k_adj:.3f}) ms")
 
     prim = "f64" if "f64" in results else precs[0]
     R = results[prim]
@@ -195,7 +197,7 @@ def main():
                    "n_straddle": info["n_straddle"],
                    "step": "point sort + state gather + assemble (f_int, K, sigma, residual norm) + adjoint"},
         "phases_ms": {k: R[k] for k in ("sort_ms", "assemble_ms", "adjoint_ms", "assemble_kernel_ms",
-                                        "adjoint_kernel_ms")},
+                                        "gather_kernel_ms", "adjoint_kernel_ms")},
         "assembly_points_per_s": R["assembly_points_per_s"], "adjoint_points_per_s": R["adjoint_points_per_s"],
         "adjoint_over_assembly": R["adjoint_over_assembly"],
         "roofline": roofline,

@@ -186,11 +186,12 @@ int32_t mpm_assemble_adjoint(const mpm_mesh_t* mesh, const mpm_state_t* s, const
                              void* stream);
 
 /* Kernel timing for measurement tools. enable = 1: from now on HIP events bracket the fused
- * assembly kernel (single-leaf points) and the adjoint kernel on the caller's stream, and
- * their elapsed times accumulate in the handle (read at the synchronisation that ends each
- * call); enable = 0: stop; enable = -1: only read. ms_out (host, 4 doubles, may be NULL):
- * [0] assembly-kernel ms summed, [1] its launch count, [2] adjoint-kernel ms, [3] adjoint
- * launches; reading resets the sums. */
+ * assembly kernel (single-leaf points), the row-gather kernel that writes f_int and K, and
+ * the adjoint kernel on the caller's stream, and their elapsed times accumulate in the handle
+ * (read at the synchronisation that ends each call); enable = 0: stop; enable = -1: only read.
+ * ms_out (host, 6 doubles, may be NULL): [0] assembly-kernel ms summed, [1] its launches,
+ * [2] adjoint-kernel ms, [3] adjoint launches, [4] gather-kernel ms, [5] gather launches;
+ * reading resets the sums. */
 int32_t mpm_kernel_timing(mpm_mesh_t* mesh, int32_t enable, double* ms_out);
 
 /* last error of the calling thread */

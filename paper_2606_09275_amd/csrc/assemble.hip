@@ -18,8 +18,15 @@ struct AsmArgs {
   const int32_t* cell_code;
   const int32_t* pleaf;
   const uint8_t* pnleaf;
-  const int64_t* slot;
-  const int32_t* stride;
+  const int32_t* wave_seg;
+  const int32_t* leaf_seg0;
+  const int32_t* leaf_nseg;
+  const int32_t* con_off;
+  const int32_t* con_seg;
+  const int32_t* con_bp;
+  const int16_t* bpos;
+  void* segK;
+  double* segF;
   const int64_t* row_ptr;
   const int32_t* col;
   const int64_t* strad;
@@ -122,20 +129,39 @@ __device__ __forceinline__ void write_point(const AsmArgs& A, int64_t i, const P
 // One 64-lane workgroup = one wavefront = 64 consecutive sorted points. Points whose domain
 // lies in one leaf share that leaf's 8-node stencil; each lane computes its point's force
 // (24 values) and upper-triangle stiffness blocks (36 x 9); the values are reduced per leaf
-// segment through LDS (36 values per round) and the segment sums go to global memory with
-// atomics (K mirrored into the lower triangle).
+// segment (run of one leaf inside the wavefront) through LDS, 36 values per round, and each
+// segment's sums are stored once, contiguously, in the segment buffer. No atomics: the
+// row-gather kernel below turns segment sums into f_int and the CSR values.
 constexpr int kRound = 36;
+
+// sum of row[0..len) with four independent accumulators (a fixed order for a given len)
+template <typename T>
+__device__ __forceinline__ T seg_sum(const T* row, int len) {
+  T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  int j = 0;
+  for (; j + 4 <= len; j += 4) {
+    s0 += row[j];
+    s1 += row[j + 1];
+    s2 += row[j + 2];
+    s3 += row[j + 3];
+  }
+  for (; j < len; ++j) s0 += row[j];
+  return (s0 + s1) + (s2 + s3);
+}
+
+// LDS rows of the reduction are padded by one element: lanes that sum different values of
+// one segment read one element per row, and a row stride of 65 elements spreads them over
+// the banks (a stride of 64 would put them all in one bank).
+constexpr int kRow = 65;
 
 template <typename T>
 __global__ __launch_bounds__(64) void k_assemble_fast(AsmArgs A) {
-  __shared__ __align__(16) unsigned char red_raw[(kRound * 64 * sizeof(T) > 24 * 64 * 8) ? kRound * 64 * sizeof(T)
-                                                                                          : 24 * 64 * 8];
+  __shared__ __align__(16) unsigned char red_raw[(kRound * kRow * sizeof(T) > 24 * kRow * 8) ? kRound * kRow * sizeof(T)
+                                                                                              : 24 * kRow * 8];
   __shared__ int32_t seg_start[65];
-  __shared__ int32_t seg_leaf[64];
-  __shared__ int32_t seg_act[64];
   __shared__ int32_t seg_cnt;
-  T(*red)[64] = reinterpret_cast<T(*)[64]>(red_raw);
-  double(*redd)[64] = reinterpret_cast<double(*)[64]>(red_raw);
+  T(*red)[kRow] = reinterpret_cast<T(*)[kRow]>(red_raw);
+  double(*redd)[kRow] = reinterpret_cast<double(*)[kRow]>(red_raw);
 
   const int lane = threadIdx.x;
   const int64_t i = int64_t(blockIdx.x) * 64 + lane;
@@ -150,13 +176,9 @@ __global__ __launch_bounds__(64) void k_assemble_fast(AsmArgs A) {
   const uint64_t heads = __ballot(head);
   const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
   const int my_seg = __popcll(heads & le) - 1;
-  if (lane < 64) seg_act[lane] = 0;
   if (lane == 0) seg_cnt = __popcll(heads);
   __syncthreads();
-  if (head) {
-    seg_start[my_seg] = lane;
-    seg_leaf[my_seg] = leaf;
-  }
+  if (head) seg_start[my_seg] = lane;
   if (lane == 0) {
     const int64_t rem = n - int64_t(blockIdx.x) * 64;
     seg_start[__popcll(heads)] = int32_t(rem < 64 ? rem : 64);
@@ -220,7 +242,6 @@ __global__ __launch_bounds__(64) void k_assemble_fast(AsmArgs A) {
       }
     }
   }
-  if (act) seg_act[my_seg] = 1;
   if (!act) {
     c = 0;
     for (int v = 0; v < 8; ++v) {
@@ -246,19 +267,17 @@ __global__ __launch_bounds__(64) void k_assemble_fast(AsmArgs A) {
     for (int r = 0; r < 3; ++r)
       redd[3 * v + r][lane] = double(c) * double(P.tau[r][0] * g[v][0] + P.tau[r][1] * g[v][1] + P.tau[r][2] * g[v][2]);
   __syncthreads();
+  const int64_t seg0 = A.wave_seg[blockIdx.x];
   for (int pp = lane; pp < nseg * 24; pp += 64) {
     const int sg = pp / 24, v = pp % 24;
-    if (!seg_act[sg]) continue;
-    double sum = 0;
-    for (int ln = seg_start[sg]; ln < seg_start[sg + 1]; ++ln) sum += redd[v][ln];
-    const int32_t node = A.cell_nodes[8 * int64_t(seg_leaf[sg]) + v / 3];
-    atomicAdd(A.f + 3 * int64_t(node) + (v % 3), sum);
+    const double sum = seg_sum<double>(&redd[v][seg_start[sg]], seg_start[sg + 1] - seg_start[sg]);
+    A.segF[(seg0 + sg) * 24 + v] = sum;
   }
   __syncthreads();
   if (!A.K) return;
 
   // ---------------- stiffness: K_(a,i)(b,k) = c [ (dtau(b,k) g_a)_i - (tau g_b)_i g_a,k ]
-  T* Kout = reinterpret_cast<T*>(A.K);
+  T* segK = reinterpret_cast<T*>(A.segK);
   int blk = 0;
 #pragma unroll
   for (int b = 0; b < 8; ++b) {
@@ -266,44 +285,107 @@ __global__ __launch_bounds__(64) void k_assemble_fast(AsmArgs A) {
 #pragma unroll
     for (int al = 0; al < 3; ++al) gt[al] = P.N[0][al] * g[b][0] + P.N[1][al] * g[b][1] + P.N[2][al] * g[b][2];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) tg[r] = P.tau[r][0] * g[b][0] + P.tau[r][1] * g[b][1] + P.tau[r][2] * g[b][2];
+    for (int r = 0; r < 3; ++r) tg[r] = c * (P.tau[r][0] * g[b][0] + P.tau[r][1] * g[b][1] + P.tau[r][2] * g[b][2]);
     T dt[3][3][3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) dtau_rank1<T>(P, k, gt, dt[k]);
+    for (int k = 0; k < 3; ++k) dtau_rank1<T>(P, k, gt, c, dt[k]);
 #pragma unroll
     for (int a = 0; a <= b; ++a) {
       const int slotv = (blk % 4) * 9;
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const T m = dt[k][r][0] * g[a][0] + dt[k][r][1] * g[a][1] + dt[k][r][2] * g[a][2] - tg[r] * g[a][k];
-          red[slotv + 3 * r + k][lane] = c * m;
-        }
+        for (int k = 0; k < 3; ++k)
+          red[slotv + 3 * r + k][lane] =
+              dt[k][r][0] * g[a][0] + dt[k][r][1] * g[a][1] + dt[k][r][2] * g[a][2] - tg[r] * g[a][k];
       if (blk % 4 == 3) {
         __syncthreads();
         const int rnd = blk / 4;
         for (int pp = lane; pp < nseg * kRound; pp += 64) {
           const int sg = pp / kRound, v = pp % kRound;
-          if (!seg_act[sg]) continue;
-          T sum = 0;
-          for (int ln = seg_start[sg]; ln < seg_start[sg + 1]; ++ln) sum += red[v][ln];
-          const int bi = rnd * 4 + v / 9;
+          const T sum = seg_sum<T>(&red[v][seg_start[sg]], seg_start[sg + 1] - seg_start[sg]);
+          // slot-major record [a][b][r][k]: block (a,b) and, off the diagonal, its transpose
+          const int bi = rnd * 4 + v / 9, r = (v % 9) / 3, k = v % 3;
           const int ba = c_blk_a[bi], bb = c_blk_b[bi];
-          const int r = (v % 9) / 3, k = v % 3;
-          const int64_t e = seg_leaf[sg];
-          const int64_t o1 = A.slot[64 * e + 8 * ba + bb] + int64_t(r) * A.stride[8 * e + ba] + k;
-          atomic_add_val<T>(Kout + o1, sum);
-          if (ba != bb) {
-            const int64_t o2 = A.slot[64 * e + 8 * bb + ba] + int64_t(k) * A.stride[8 * e + bb] + r;
-            atomic_add_val<T>(Kout + o2, sum);
-          }
+          T* rec = segK + (seg0 + sg) * 576;
+          rec[ba * 72 + bb * 9 + r * 3 + k] = sum;
+          if (ba != bb) rec[bb * 72 + ba * 9 + k * 3 + r] = sum;
         }
         __syncthreads();
       }
       ++blk;
     }
   }
+}
+
+// ------------------------------------------------------------------ row gather
+// One workgroup per independent node n: the three CSR rows of n are accumulated in LDS from
+// the reduced segment blocks of every (populated leaf, slot a) incidence of n, in ascending
+// leaf order, and written once. A contribution is the contiguous [a][0..7][r][k] slab of a
+// segment record. Rows and f_int are overwritten.
+template <typename T>
+__global__ __launch_bounds__(64) void k_gather(AsmArgs A, int64_t n_node) {
+  extern __shared__ __align__(16) unsigned char gsm[];
+  T* acc = reinterpret_cast<T*>(gsm);
+  constexpr int kBatch = 8;  // contributions whose loads are in flight together
+  const int64_t nd = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int64_t base = A.row_ptr[3 * nd];
+  const int deg = int((A.row_ptr[3 * nd + 1] - base) / 3);
+  const int len = 9 * deg;
+  const bool wantK = A.K != nullptr;
+  for (int j = lane; j < len; j += 64) acc[j] = T(0);
+  double fsum = 0.0;
+  __syncthreads();
+  const T* segK = reinterpret_cast<const T*>(A.segK);
+  // lane -> (b, r, k) of the 72 values a contribution adds; lanes 0..7 also take values 64..71
+  const int v0 = lane, v1 = lane + 64;
+  const int b0 = v0 / 9, r0 = (v0 % 9) / 3, k0 = v0 % 3;
+  const int b1 = v1 / 9, r1 = (v1 % 9) / 3, k1 = v1 % 3;
+  const bool has1 = v1 < 72;
+  const int c0 = A.con_off[nd], c1 = A.con_off[nd + 1];
+  for (int cb = c0; cb < c1; cb += kBatch) {
+    const int nb = c1 - cb < kBatch ? c1 - cb : kBatch;
+    T val0[kBatch], val1[kBatch];
+    int d0[kBatch], d1[kBatch];
+    double fv[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      val0[j] = val1[j] = T(0);
+      d0[j] = d1[j] = 0;
+      fv[j] = 0.0;
+      if (j >= nb) continue;
+      const int32_t cs = A.con_seg[cb + j];   // segment * 8 + slot
+      const int16_t* bp = A.bpos + A.con_bp[cb + j];
+      const T* src = segK + int64_t(cs >> 3) * 576 + (cs & 7) * 72;  // slot a's 72 values
+      if (wantK) {
+        val0[j] = src[v0];
+        d0[j] = r0 * 3 * deg + 3 * bp[b0] + k0;
+        if (has1) {
+          val1[j] = src[v1];
+          d1[j] = r1 * 3 * deg + 3 * bp[b1] + k1;
+        }
+      }
+      if (lane < 3) fv[j] = A.segF[int64_t(cs >> 3) * 24 + 3 * (cs & 7) + lane];
+    }
+    // accumulate in contribution order; the 72 destinations of one contribution are distinct
+    // and a single wavefront executes its LDS operations in program order
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      if (j >= nb) break;
+      if (wantK) {
+        acc[d0[j]] += val0[j];
+        if (has1) acc[d1[j]] += val1[j];
+      }
+      fsum += fv[j];
+    }
+  }
+  __syncthreads();
+  if (wantK) {
+    T* Kout = reinterpret_cast<T*>(A.K);
+    for (int j = lane; j < len; j += 64) Kout[base + j] = acc[j];
+  }
+  if (lane < 3) A.f[3 * nd + lane] = fsum;
 }
 
 // ------------------------------------------------------------------ general path
@@ -408,7 +490,7 @@ __global__ __launch_bounds__(64) void k_assemble_general(AsmArgs A) {
     for (int al = 0; al < 3; ++al) gt[al] = P.N[0][al] * g[b][0] + P.N[1][al] * g[b][1] + P.N[2][al] * g[b][2];
     for (int r = 0; r < 3; ++r) tg[r] = P.tau[r][0] * g[b][0] + P.tau[r][1] * g[b][1] + P.tau[r][2] * g[b][2];
     T dt[3][3][3];
-    for (int k = 0; k < 3; ++k) dtau_rank1<T>(P, k, gt, dt[k]);
+    for (int k = 0; k < 3; ++k) dtau_rank1<T>(P, k, gt, T(1), dt[k]);
     for (int a = 0; a < ns; ++a) {
       for (int r = 0; r < 3; ++r) {
         const int64_t row = 3 * int64_t(nd[a]) + r;
@@ -500,50 +582,17 @@ __global__ __launch_bounds__(256) void k_norm_final(const double* __restrict__ p
 
 // ------------------------------------------------------------------ adjoint
 // L = lambda . f_int: per point L_p = c tau : G with c = V_n/J_n, G = sum_v lambda_v (x) grad_x S_v.
-// dL/dV_n = tau:G / J_n; dL/dtheta = c sum_a (d tau_a / d theta) (n_a . G n_a).
-template <typename T>
-__global__ __launch_bounds__(64) void k_adjoint(AsmArgs A) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+// dL/dV_n = tau:G / J_n; dL/dtheta = c sum_a (d tau_a / d theta) (n_a . G n_a): elastic points
+// d tau_a/dE = tau_a/E, d tau_a/dnu = lam' tr(eps) + 2 G' eps_a; plastic points (radial return
+// onto the von Mises circle, direction independent of E and nu) d tau_a/dE = tr(eps)/(3(1-2nu)),
+// d tau_a/dnu = 2E tr(eps)/(3(1-2nu)^2), d tau_a/dsy = sqrt(2/3) s^_a.
+template <typename T, int NS>
+__device__ __forceinline__ void adjoint_point(const AsmArgs& A, int64_t i, int ns, const int32_t* nd, const T (*dS)[3]) {
   const int64_t n = A.n;
-  if (i >= n) return;
-  double x[3], l[3];
-  for (int a = 0; a < 3; ++a) {
-    x[a] = A.s.x[a * n + i];
-    l[a] = A.s.l[a * n + i];
-  }
-  int32_t nd[kMaxSup];
-  T S[kMaxSup], dS[kMaxSup][3];
-  int ns;
-  if (A.pnleaf[i] == 1) {
-    const int32_t e = A.pleaf[i];
-    T s8[8], d8[8][3];
-    leaf_overlap_basis<T>(A.G, e, A.cell_code[e], x, l, s8, d8);
-    for (int v = 0; v < 8; ++v) {
-      nd[v] = A.cell_nodes[8 * int64_t(e) + v];
-      S[v] = s8[v];
-      for (int q = 0; q < 3; ++q) dS[v][q] = d8[v][q];
-    }
-    ns = 8;
-  } else {
-    // locate this point in the straddle list (sorted ascending)
-    int64_t lo = 0, hi = A.n_strad - 1, t = -1;
-    while (lo <= hi) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (A.strad[mid] == i) {
-        t = mid;
-        break;
-      }
-      if (A.strad[mid] < i) lo = mid + 1;
-      else hi = mid - 1;
-    }
-    if (t < 0) {
-      raise(A.err, MPM_ETREE, i);
-      return;
-    }
-    ns = general_basis<T>(A, t, x, l, nd, S, dS);
-  }
   T H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  for (int v = 0; v < ns; ++v) {
+#pragma unroll
+  for (int v = 0; v < NS; ++v) {
+    if (v >= ns) break;
     const double* uv = A.u + 3 * int64_t(nd[v]);
     for (int r = 0; r < 3; ++r)
       for (int q = 0; q < 3; ++q) H[r][q] += T(uv[r]) * dS[v][q];
@@ -571,7 +620,9 @@ __global__ __launch_bounds__(64) void k_adjoint(AsmArgs A) {
     return;
   }
   T Gm[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  for (int v = 0; v < ns; ++v) {
+#pragma unroll
+  for (int v = 0; v < NS; ++v) {
+    if (v >= ns) break;
     T gv[3];
     for (int q = 0; q < 3; ++q) gv[q] = Fi[0][q] * dS[v][0] + Fi[1][q] * dS[v][1] + Fi[2][q] * dS[v][2];
     const double* lv = A.lam + 3 * int64_t(nd[v]);
@@ -614,6 +665,40 @@ __global__ __launch_bounds__(64) void k_adjoint(AsmArgs A) {
   A.dV[i] = tauG / Jn;
 }
 
+template <typename T>
+__global__ __launch_bounds__(64) void k_adjoint_fast(AsmArgs A) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t n = A.n;
+  if (i >= n || A.pnleaf[i] != 1) return;
+  double x[3], l[3];
+  for (int a = 0; a < 3; ++a) {
+    x[a] = A.s.x[a * n + i];
+    l[a] = A.s.l[a * n + i];
+  }
+  const int32_t e = A.pleaf[i];
+  int32_t nd[8];
+  T S[8], dS[8][3];
+  leaf_overlap_basis<T>(A.G, e, A.cell_code[e], x, l, S, dS);
+  for (int v = 0; v < 8; ++v) nd[v] = A.cell_nodes[8 * int64_t(e) + v];
+  adjoint_point<T, 8>(A, i, 8, nd, dS);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_adjoint_general(AsmArgs A) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= A.n_strad) return;
+  const int64_t i = A.strad[t], n = A.n;
+  double x[3], l[3];
+  for (int a = 0; a < 3; ++a) {
+    x[a] = A.s.x[a * n + i];
+    l[a] = A.s.l[a * n + i];
+  }
+  int32_t nd[kMaxSup];
+  T S[kMaxSup], dS[kMaxSup][3];
+  const int ns = general_basis<T>(A, t, x, l, nd, S, dS);
+  adjoint_point<T, kMaxSup>(A, i, ns, nd, dS);
+}
+
 static AsmArgs make_args(const mpm_mesh* m, const mpm_state_t* s) {
   AsmArgs A;
   std::memset(&A, 0, sizeof(A));
@@ -622,8 +707,15 @@ static AsmArgs make_args(const mpm_mesh* m, const mpm_state_t* s) {
   A.cell_code = m->d_cell_code;
   A.pleaf = m->d_pleaf;
   A.pnleaf = m->d_pnleaf;
-  A.slot = m->d_slot;
-  A.stride = m->d_stride;
+  A.wave_seg = m->d_wave_seg;
+  A.leaf_seg0 = m->d_leaf_seg0;
+  A.leaf_nseg = m->d_leaf_nseg;
+  A.con_off = m->d_con_off;
+  A.con_seg = m->d_con_seg;
+  A.con_bp = m->d_con_bp;
+  A.bpos = m->d_bpos;
+  A.segK = m->d_segK;
+  A.segF = m->d_segF;
   A.row_ptr = m->d_row_ptr;
   A.col = m->d_col;
   A.strad = m->d_strad;
@@ -676,9 +768,6 @@ extern "C" int32_t mpm_assemble(const mpm_mesh_t* m, const mpm_state_t* s, const
   A.sigma = sigma6;
   A.Fnew = F_new;
   A.be = be_new;
-  const size_t kbytes = size_t(m->nnz) * (precision == MPM_F64 ? 8 : 4);
-  MPM_HIP(hipMemsetAsync(f_int, 0, size_t(3 * m->n_node) * 8, st));
-  if (K_vals && kbytes) MPM_HIP(hipMemsetAsync(K_vals, 0, kbytes, st));
   const int64_t n = m->n_point;
   mpm_mesh* mm = const_cast<mpm_mesh*>(m);
   const bool timed = mm->timing && n;
@@ -689,6 +778,15 @@ extern "C" int32_t mpm_assemble(const mpm_mesh_t* m, const mpm_state_t* s, const
     else hipLaunchKernelGGL(k_assemble_fast<float>, grid, dim3(64), 0, st, A);
   }
   if (timed) MPM_HIP(hipEventRecord(mm->ev[1], st));
+  // f_int and every CSR value are written by the gather (zero where no point contributes)
+  if (m->n_node) {
+    const dim3 grid(unsigned(m->n_node));
+    if (precision == MPM_F64)
+      hipLaunchKernelGGL(k_gather<double>, grid, dim3(64), size_t(9) * m->max_deg * 8, st, A, m->n_node);
+    else
+      hipLaunchKernelGGL(k_gather<float>, grid, dim3(64), size_t(9) * m->max_deg * 4, st, A, m->n_node);
+  }
+  if (timed) MPM_HIP(hipEventRecord(mm->ev[4], st));
   if (m->n_straddle) {
     const dim3 grid(unsigned((m->n_straddle + 63) / 64));
     if (precision == MPM_F64) hipLaunchKernelGGL(k_assemble_general<double>, grid, dim3(64), 0, st, A);
@@ -704,10 +802,13 @@ extern "C" int32_t mpm_assemble(const mpm_mesh_t* m, const mpm_state_t* s, const
   MPM_HIP(hipGetLastError());
   const int32_t rc = read_error(mm, st, "mpm_assemble");
   if (timed) {
-    float ms = 0;
+    float ms = 0, mg = 0;
     MPM_HIP(hipEventElapsedTime(&ms, mm->ev[0], mm->ev[1]));
+    MPM_HIP(hipEventElapsedTime(&mg, mm->ev[1], mm->ev[4]));
     mm->t_asm += ms;
     mm->n_asm += 1;
+    mm->t_gat += mg;
+    mm->n_gat += 1;
   }
   return rc;
 }
@@ -734,10 +835,15 @@ extern "C" int32_t mpm_assemble_adjoint(const mpm_mesh_t* m, const mpm_state_t* 
   if (timed) MPM_HIP(hipEventRecord(mm->ev[2], st));
   if (n) {
     const dim3 grid(unsigned((n + 63) / 64));
-    if (precision == MPM_F64) hipLaunchKernelGGL(k_adjoint<double>, grid, dim3(64), 0, st, A);
-    else hipLaunchKernelGGL(k_adjoint<float>, grid, dim3(64), 0, st, A);
+    if (precision == MPM_F64) hipLaunchKernelGGL(k_adjoint_fast<double>, grid, dim3(64), 0, st, A);
+    else hipLaunchKernelGGL(k_adjoint_fast<float>, grid, dim3(64), 0, st, A);
   }
   if (timed) MPM_HIP(hipEventRecord(mm->ev[3], st));
+  if (m->n_straddle) {
+    const dim3 grid(unsigned((m->n_straddle + 63) / 64));
+    if (precision == MPM_F64) hipLaunchKernelGGL(k_adjoint_general<double>, grid, dim3(64), 0, st, A);
+    else hipLaunchKernelGGL(k_adjoint_general<float>, grid, dim3(64), 0, st, A);
+  }
   MPM_HIP(hipGetLastError());
   const int32_t rc = read_error(mm, st, "mpm_assemble_adjoint");
   if (timed) {

@@ -87,17 +87,31 @@ struct mpm_mesh {
   uint8_t* d_pnleaf = nullptr;      // n_point (sorted)
   int64_t* d_row_ptr = nullptr;
   int32_t* d_col = nullptr;
-  int64_t* d_slot = nullptr;        // n_leaf x 64: CSR offset of block (a,b) (row 3 n_a, block col n_b)
-  int32_t* d_stride = nullptr;      // n_leaf x 8: row length of node a
+  // segments: maximal runs of one leaf inside a 64-point wavefront of the sorted points
+  int64_t n_wave = 0, n_seg = 0, n_con = 0;
+  int32_t max_deg = 0;              // largest number of coupled nodes of one node row
+  int32_t* d_wave_seg = nullptr;    // n_wave + 1: first segment of each wavefront
+  int32_t* d_leaf_seg0 = nullptr;   // n_leaf: first segment of the leaf
+  int32_t* d_leaf_nseg = nullptr;   // n_leaf: number of segments of the leaf
+  // node -> contributions (segment, slot) of its (populated leaf, slot) incidences, in
+  // ascending leaf then segment order
+  int32_t* d_con_off = nullptr;     // n_node + 1
+  int32_t* d_con_seg = nullptr;     // segment * 8 + slot
+  int32_t* d_con_bp = nullptr;      // offset of the slot's 8 block columns in d_bpos
+  int16_t* d_bpos = nullptr;        // n_leaf x 64: block column of slot b's node in the row of slot a's node
+  void* d_segK = nullptr;           // n_seg x [8][8][3][3] reduced slot blocks (double or float)
+  double* d_segF = nullptr;         // n_seg x 24 reduced nodal forces
   int64_t* d_strad = nullptr;       // n_straddle sorted positions
   int32_t* d_strad_leaf = nullptr;  // n_straddle x 8 overlapped leaves (-1 pad)
   mpm::DevErr* d_err = nullptr;
+  mpm::DevErr* h_err = nullptr;     // pinned host copy of the error word
+  hipEvent_t err_ev = nullptr;      // marks the error-word copy (polled, no blocking sync)
   double* d_partial = nullptr;      // residual partial sums
   void* d_scratch = nullptr;        // radix sort scratch
   size_t scratch_bytes = 0;
   // kernel timing (measurement)
   bool timing = false;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  double t_asm = 0, t_adj = 0;
-  int64_t n_asm = 0, n_adj = 0;
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  double t_asm = 0, t_adj = 0, t_gat = 0;
+  int64_t n_asm = 0, n_adj = 0, n_gat = 0;
 };

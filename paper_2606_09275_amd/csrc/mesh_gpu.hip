@@ -229,6 +229,40 @@ __global__ void k_permute(const int64_t* __restrict__ perm, const double* __rest
   for (int c = 0; c < ncomp; ++c) dst[c * n + i] = src[c * n + p];
 }
 
+// A random permutation of a [ncomp][n] array touches one cache line per component and
+// point; staging an AoS copy makes each point's record one contiguous read. Step 1: tiled
+// SoA -> AoS transpose through LDS (coalesced on both sides).
+constexpr int kPermTile = 128, kPermMaxComp = 32;
+__global__ __launch_bounds__(kPermTile) void k_soa_to_aos(const double* __restrict__ src, double* __restrict__ aos,
+                                                          int64_t n, int ncomp) {
+  __shared__ double tile[kPermMaxComp * kPermTile];
+  const int64_t p0 = int64_t(blockIdx.x) * kPermTile;
+  const int t = threadIdx.x;
+  const int cnt = int(n - p0 < kPermTile ? n - p0 : kPermTile);
+  for (int c = 0; c < ncomp; ++c)
+    if (t < cnt) tile[t * ncomp + c] = src[c * n + p0 + t];
+  __syncthreads();
+  double* out = aos + p0 * ncomp;
+  for (int j = t; j < cnt * ncomp; j += kPermTile) out[j] = tile[j];
+}
+// Step 2: gather one record per sorted position, write component rows (coalesced).
+__global__ __launch_bounds__(256) void k_aos_gather(const int64_t* __restrict__ perm, const double* __restrict__ aos,
+                                                    double* __restrict__ dst, int64_t n, int ncomp) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double* r = aos + perm[i] * ncomp;
+  if ((ncomp & 1) == 0) {  // records start on 16-byte boundaries: 16-byte loads
+    const double2* r2 = reinterpret_cast<const double2*>(r);
+    for (int c = 0; c < ncomp / 2; ++c) {
+      const double2 v = r2[c];
+      dst[(2 * c) * n + i] = v.x;
+      dst[(2 * c + 1) * n + i] = v.y;
+    }
+  } else {
+    for (int c = 0; c < ncomp; ++c) dst[c * n + i] = r[c];
+  }
+}
+
 LeafGeo make_geo(const mpm_mesh* m) {
   LeafGeo G;
   G.leaf = m->d_leaf;
@@ -250,10 +284,19 @@ static int32_t upload(T** dst, const std::vector<T>& v, hipStream_t st) {
   return MPM_OK;
 }
 
+// Copies the device error word to pinned host memory and waits for it by polling an event
+// (a blocking stream synchronisation can leave the device idle for hundreds of microseconds
+// after the work has finished, before the host thread is woken).
 int32_t read_error(mpm_mesh* m, hipStream_t st, const char* what) {
-  DevErr e;
-  MPM_HIP(hipMemcpyAsync(&e, m->d_err, sizeof(DevErr), hipMemcpyDeviceToHost, st));
-  MPM_HIP(hipStreamSynchronize(st));
+  if (!m->h_err) MPM_HIP(hipHostMalloc((void**)&m->h_err, sizeof(DevErr), hipHostMallocDefault));
+  if (!m->err_ev) MPM_HIP(hipEventCreateWithFlags(&m->err_ev, hipEventDisableTiming));
+  MPM_HIP(hipMemcpyAsync(m->h_err, m->d_err, sizeof(DevErr), hipMemcpyDeviceToHost, st));
+  MPM_HIP(hipEventRecord(m->err_ev, st));
+  hipError_t q;
+  while ((q = hipEventQuery(m->err_ev)) == hipErrorNotReady) {
+  }
+  if (q != hipSuccess) return hip_fail(q, what);
+  const DevErr e = *m->h_err;
   if (e.code != 0) {
     static const char* names[] = {"", "bad argument", "det(dF) <= 0 or non-positive trial eigenvalue",
                                   "domain spans more than one leaf boundary per axis or key overflow",
@@ -325,12 +368,15 @@ extern "C" void mpm_mesh_free(mpm_mesh_t* m) {
   if (!m) return;
   void* ptrs[] = {m->d_leaf, m->d_leaf_key, m->d_cell_nodes, m->d_cell_code, m->d_cell_cmat, m->d_node_ijk,
                   m->d_hang_ijk, m->d_hang_sup, m->d_hang_w, m->d_hang_owner, m->d_perm, m->d_pleaf, m->d_pnleaf,
-                  m->d_row_ptr, m->d_col, m->d_slot, m->d_stride, m->d_strad, m->d_strad_leaf, m->d_err,
+                  m->d_row_ptr, m->d_col, m->d_wave_seg, m->d_leaf_seg0, m->d_leaf_nseg, m->d_con_off, m->d_con_seg, m->d_con_bp, m->d_bpos,
+                  m->d_segK, m->d_segF, m->d_strad, m->d_strad_leaf, m->d_err,
                   m->d_partial, m->d_scratch};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (hipEvent_t e : m->ev)
     if (e) (void)hipEventDestroy(e);
+  if (m->h_err) (void)hipHostFree(m->h_err);
+  if (m->err_ev) (void)hipEventDestroy(m->err_ev);
   delete m;
 }
 
@@ -516,28 +562,80 @@ extern "C" int32_t octree_build(const mpm_refine_t* crit, const double* x, const
         for (int k = 0; k < 3; ++k) col[w++] = 3 * b + k;
       }
     }
-  // slot map of populated leaves: CSR offset of block (a,b) and row length of slot a
-  std::vector<int64_t> slot(size_t(nl) * 64, -1);
-  std::vector<int32_t> stride(size_t(nl) * 8, 0);
-  for (int64_t e = 0; e < nl; ++e) {
+  // segments (runs of one leaf inside each 64-point wavefront), per-leaf segment ranges,
+  // node -> (leaf, slot) incidences of populated leaves and the block column of every
+  // (slot a, slot b) pair of a populated leaf in the row of slot a's node
+  m->n_wave = (n + 63) / 64;
+  std::vector<int32_t> wave_seg(m->n_wave + 1, 0), leaf_seg0(nl, 0), leaf_nseg(nl, 0);
+  int64_t nseg = 0;
+  for (int64_t w = 0; w < m->n_wave; ++w) {
+    wave_seg[w] = int32_t(nseg);
+    for (int64_t i = 64 * w; i < std::min<int64_t>(n, 64 * w + 64); ++i) {
+      if (i != 64 * w && pleaf[i] == pleaf[i - 1]) continue;
+      if (leaf_nseg[pleaf[i]] == 0) leaf_seg0[pleaf[i]] = int32_t(nseg);
+      leaf_nseg[pleaf[i]]++;
+      ++nseg;
+    }
+  }
+  wave_seg[m->n_wave] = int32_t(nseg);
+  m->n_seg = nseg;
+  if (nseg >= (int64_t(1) << 31)) {
+    set_error(MPM_EARG, "octree_build: too many point segments");
+    mpm_mesh_free(m);
+    return MPM_EARG;
+  }
+  std::vector<int32_t> con_off(nn + 1, 0);
+  for (int64_t e = 0; e < nl; ++e)
+    if (populated[e])
+      for (int a = 0; a < 8; ++a) con_off[T.cell_nodes[8 * e + a] + 1] += leaf_nseg[e];
+  for (int64_t a = 0; a < nn; ++a) con_off[a + 1] += con_off[a];
+  m->n_con = con_off[nn];
+  if (m->n_con >= (int64_t(1) << 31) || nseg >= (int64_t(1) << 28)) {
+    set_error(MPM_EARG, "octree_build: too many segment contributions");
+    mpm_mesh_free(m);
+    return MPM_EARG;
+  }
+  std::vector<int32_t> con_seg(std::max<int64_t>(1, m->n_con)), con_bp(std::max<int64_t>(1, m->n_con));
+  std::vector<int32_t> fill(con_off.begin(), con_off.end() - 1);
+  std::vector<int16_t> bpos(size_t(nl) * 64, -1);
+  for (int64_t e = 0; e < nl; ++e) {  // ascending leaf order per node: a fixed summation order
     if (!populated[e]) continue;
-    const int32_t* s = &T.cell_nodes[8 * e];
+    const int32_t* sl = &T.cell_nodes[8 * e];
     for (int a = 0; a < 8; ++a) {
-      const int64_t na = s[a];
+      const int64_t na = sl[a];
+      for (int g = 0; g < leaf_nseg[e]; ++g) {
+        con_seg[fill[na]] = int32_t((int64_t(leaf_seg0[e] + g) << 3) | a);
+        con_bp[fill[na]] = int32_t(64 * e + 8 * a);
+        fill[na]++;
+      }
       const uint64_t* lo = pairs.data() + nb_off[na];
       const uint64_t* hi = pairs.data() + nb_off[na + 1];
-      stride[8 * e + a] = int32_t(3 * (nb_off[na + 1] - nb_off[na]));
       for (int b = 0; b < 8; ++b) {
-        const uint64_t key = (uint64_t(uint32_t(na)) << 32) | uint32_t(s[b]);
-        const uint64_t* it = std::lower_bound(lo, hi, key);
-        slot[64 * e + 8 * a + b] = row_ptr[3 * na] + 3 * int64_t(it - lo);
+        const uint64_t key = (uint64_t(uint32_t(na)) << 32) | uint32_t(sl[b]);
+        bpos[64 * e + 8 * a + b] = int16_t(std::lower_bound(lo, hi, key) - lo);
       }
     }
   }
+  for (int64_t a = 0; a < nn; ++a) m->max_deg = std::max<int32_t>(m->max_deg, int32_t(nb_off[a + 1] - nb_off[a]));
+  if (m->max_deg > 1024 || nl >= (int64_t(1) << 25)) {
+    set_error(MPM_ESTENCIL, "octree_build: node row too wide or too many leaves for the gather");
+    mpm_mesh_free(m);
+    return MPM_ESTENCIL;
+  }
   UP(m->d_row_ptr, row_ptr);
   UP(m->d_col, col);
-  UP(m->d_slot, slot);
-  UP(m->d_stride, stride);
+  UP(m->d_wave_seg, wave_seg);
+  UP(m->d_leaf_seg0, leaf_seg0);
+  UP(m->d_leaf_nseg, leaf_nseg);
+  UP(m->d_con_off, con_off);
+  UP(m->d_con_seg, con_seg);
+  UP(m->d_con_bp, con_bp);
+  UP(m->d_bpos, bpos);
+  if (hipMalloc(&m->d_segK, size_t(std::max<int64_t>(1, nseg)) * 576 * 8) != hipSuccess ||
+      hipMalloc(&m->d_segF, size_t(std::max<int64_t>(1, nseg)) * 24 * 8) != hipSuccess) {
+    mpm_mesh_free(m);
+    return hip_fail(hipErrorOutOfMemory, "octree_build: segment buffers");
+  }
 #undef UP
   if (hipMalloc(&m->d_partial, 4096 * sizeof(double)) != hipSuccess) {
     mpm_mesh_free(m);
@@ -613,8 +711,18 @@ extern "C" int32_t mpm_permute(const mpm_mesh_t* m, const int64_t* perm, const d
   }
   const int64_t n = m->n_point;
   if (n == 0) return MPM_OK;
-  hipLaunchKernelGGL(k_permute, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, perm ? perm : m->d_perm,
-                     src, dst, n, ncomp);
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t* pm = perm ? perm : m->d_perm;
+  double* aos = nullptr;
+  if (ncomp >= 2 && ncomp <= kPermMaxComp && hipMallocAsync((void**)&aos, size_t(n) * ncomp * 8, st) == hipSuccess) {
+    hipLaunchKernelGGL(k_soa_to_aos, dim3((n + kPermTile - 1) / kPermTile), dim3(kPermTile), 0, st, src, aos, n,
+                       ncomp);
+    hipLaunchKernelGGL(k_aos_gather, dim3((n + 255) / 256), dim3(256), 0, st, pm, aos, dst, n, ncomp);
+    MPM_HIP(hipFreeAsync(aos, st));
+  } else {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_permute, dim3((n + 255) / 256), dim3(256), 0, st, pm, src, dst, n, ncomp);
+  }
   MPM_HIP(hipGetLastError());
   return MPM_OK;
 }
@@ -632,8 +740,10 @@ extern "C" int32_t mpm_kernel_timing(mpm_mesh_t* m, int32_t enable, double* ms_o
     ms_out[1] = double(m->n_asm);
     ms_out[2] = m->t_adj;
     ms_out[3] = double(m->n_adj);
-    m->t_asm = m->t_adj = 0;
-    m->n_asm = m->n_adj = 0;
+    ms_out[4] = m->t_gat;
+    ms_out[5] = double(m->n_gat);
+    m->t_asm = m->t_adj = m->t_gat = 0;
+    m->n_asm = m->n_adj = m->n_gat = 0;
   }
   return MPM_OK;
 }

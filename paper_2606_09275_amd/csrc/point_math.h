@@ -258,27 +258,29 @@ __device__ __forceinline__ int material(const T H[3][3], const T B[3][3], double
   return 0;
 }
 
-// variation of tau for Z = e_k (x) g (principal-frame formula), symmetric result dt[3][3]
+// variation of tau for Z = e_k (x) g (principal-frame formula), scaled by `sc`, symmetric
+// result dt[3][3] = sc N dtau~ N^T
 template <typename T>
-__device__ __forceinline__ void dtau_rank1(const PointMat<T>& P, int k, const T gt[3], T dt[3][3]) {
+__device__ __forceinline__ void dtau_rank1(const PointMat<T>& P, int k, const T gt[3], T sc, T dt[3][3]) {
   // Z~ = (N^T e_k)(N^T g)^T: Z~_ab = N[k][a] gt[b]
   const T z0 = P.N[k][0] * gt[0], z1 = P.N[k][1] * gt[1], z2 = P.N[k][2] * gt[2];
-  const T d0 = P.D[0][0] * z0 + P.D[0][1] * z1 + P.D[0][2] * z2;
-  const T d1 = P.D[1][0] * z0 + P.D[1][1] * z1 + P.D[1][2] * z2;
-  const T d2 = P.D[2][0] * z0 + P.D[2][1] * z1 + P.D[2][2] * z2;
-  const T o01 = P.Geff * P.th01 * (P.N[k][0] * gt[1] * P.x[1] + P.x[0] * P.N[k][1] * gt[0]);
-  const T o02 = P.Geff * P.th02 * (P.N[k][0] * gt[2] * P.x[2] + P.x[0] * P.N[k][2] * gt[0]);
-  const T o12 = P.Geff * P.th12 * (P.N[k][1] * gt[2] * P.x[2] + P.x[1] * P.N[k][2] * gt[1]);
+  T m[3][3];
+  m[0][0] = sc * (P.D[0][0] * z0 + P.D[0][1] * z1 + P.D[0][2] * z2);
+  m[1][1] = sc * (P.D[1][0] * z0 + P.D[1][1] * z1 + P.D[1][2] * z2);
+  m[2][2] = sc * (P.D[2][0] * z0 + P.D[2][1] * z1 + P.D[2][2] * z2);
+  const T gs = sc * P.Geff;
+  m[0][1] = m[1][0] = gs * P.th01 * (P.N[k][0] * gt[1] * P.x[1] + P.x[0] * P.N[k][1] * gt[0]);
+  m[0][2] = m[2][0] = gs * P.th02 * (P.N[k][0] * gt[2] * P.x[2] + P.x[0] * P.N[k][2] * gt[0]);
+  m[1][2] = m[2][1] = gs * P.th12 * (P.N[k][1] * gt[2] * P.x[2] + P.x[1] * P.N[k][2] * gt[1]);
+  T W[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = i; j < 3; ++j) {
-      const T v = d0 * P.N[i][0] * P.N[j][0] + d1 * P.N[i][1] * P.N[j][1] + d2 * P.N[i][2] * P.N[j][2] +
-                  o01 * (P.N[i][0] * P.N[j][1] + P.N[i][1] * P.N[j][0]) +
-                  o02 * (P.N[i][0] * P.N[j][2] + P.N[i][2] * P.N[j][0]) +
-                  o12 * (P.N[i][1] * P.N[j][2] + P.N[i][2] * P.N[j][1]);
-      dt[i][j] = dt[j][i] = v;
-    }
+    for (int b = 0; b < 3; ++b) W[i][b] = P.N[i][0] * m[0][b] + P.N[i][1] * m[1][b] + P.N[i][2] * m[2][b];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) dt[i][j] = dt[j][i] = W[i][0] * P.N[j][0] + W[i][1] * P.N[j][1] + W[i][2] * P.N[j][2];
 }
 
 // kinematics from nodal displacements: H = sum u (x) dS, dF = I + H, inverse, det

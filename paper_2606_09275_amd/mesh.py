@@ -136,9 +136,9 @@ class Mesh:
         return out
 
     def kernel_timing(self, enable: int = -1):
-        """enable 1/0 switches event timing of the assembly/adjoint kernels; returns and resets
-        (assembly ms, launches, adjoint ms, launches)."""
-        buf = (C.c_double * 4)()
+        """enable 1/0 switches event timing of the assembly/gather/adjoint kernels; returns and
+        resets (assembly ms, launches, adjoint ms, launches, gather ms, launches)."""
+        buf = (C.c_double * 6)()
         check(lib().mpm_kernel_timing(self.h, int(enable), buf))
         return tuple(buf)
 

@@ -44,6 +44,27 @@ FLOPS_PER_POINT = 100 + 330 + 90 + 400 + 50 + 3000 + 1296 + 1944 + 144
 BYTES_PER_POINT = 184
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("assemble.hip", "point_math.h", "geom.h", "internal.h"):
+        h.update((ROOT / "paper_2606_09275_amd" / "csrc" / f).read_bytes())
+    return h.hexdigest()
+
+
+def measured_traffic(workload_name, prim):
+    """HBM bytes per launch of the FP64 assembly kernel from the committed rocprofv3 counter
+    runs (FETCH_SIZE x2 + WRITE_SIZE, calibrated on a plain copy); None when the kernel
+    sources changed since the counters were taken or no run exists for this workload."""
+    p = ROOT / "profiles" / f"assemble_fast_traffic_{workload_name.split('_')[0]}.json"
+    if prim != "f64" or not p.exists():
+        return None
+    d = json.loads(p.read_text())
+    if d.get("source_sha256") != kernel_source_hash() or not d.get("workload", "").startswith(workload_name[:2]):
+        return None
+    return float(d["hbm_bytes_per_launch"])
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -54,7 +75,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2")
-    ap.add_argument("--cpu-sample", type=int, default=300000, help="points in the oracle CPU baseline sample")
+    ap.add_argument("--cpu-sample", type=int, default=1000000, help="points in the oracle CPU baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["f64", "f32k"], default=None, help="time one precision only")
     ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB device copy (counter calibration)")
@@ -182,7 +203,7 @@ def main():
     roofline = {
         "bound": "alu", "kernel": "k_assemble_fast<%s>" % ("double" if prim == "f64" else "float"),
         "achieved": alg_flops / kt_s / 1e12, "peak": peak, "unit": "TFLOP/s",
-        "frac": alg_flops / kt_s / 1e12 / peak, "traffic": None,
+        "frac": alg_flops / kt_s / 1e12 / peak, "traffic": measured_traffic(w.name, prim),
         "flops_per_point": FLOPS_PER_POINT, "points_per_launch": n_fast,
         "hbm": {"achieved": alg_bytes / kt_s / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": alg_bytes / kt_s / 1e9 / PEAK_HBM_GBS, "bytes_per_launch": alg_bytes},

@@ -132,7 +132,6 @@ __device__ __forceinline__ void write_point(const AsmArgs& A, int64_t i, const P
 // segment (run of one leaf inside the wavefront) through LDS, 36 values per round, and each
 // segment's sums are stored once, contiguously, in the segment buffer. No atomics: the
 // row-gather kernel below turns segment sums into f_int and the CSR values.
-constexpr int kRound = 36;
 
 // sum of row[0..len) with four independent accumulators (a fixed order for a given len)
 template <typename T>
@@ -154,10 +153,21 @@ __device__ __forceinline__ T seg_sum(const T* row, int len) {
 // the banks (a stride of 64 would put them all in one bank).
 constexpr int kRow = 65;
 
+// Values per reduction round: four 3x3 blocks in FP64; two in FP32, where the smaller LDS
+// footprint lets four wavefronts share a SIMD (the FP64 kernel is register-bound at two).
+template <typename T>
+struct Rounds {
+  static constexpr int kBlocks = sizeof(T) == 8 ? 4 : 2;
+  static constexpr int kVals = 9 * kBlocks;
+  static constexpr int kForce = sizeof(T) == 8 ? 24 : 12;  // force values per round
+  static constexpr int kBytes = (kVals * kRow * int(sizeof(T)) > kForce * kRow * 8) ? kVals * kRow * int(sizeof(T))
+                                                                                 : kForce * kRow * 8;
+};
+
 template <typename T>
 __global__ __launch_bounds__(64) void k_assemble_fast(AsmArgs A) {
-  __shared__ __align__(16) unsigned char red_raw[(kRound * kRow * sizeof(T) > 24 * kRow * 8) ? kRound * kRow * sizeof(T)
-                                                                                              : 24 * kRow * 8];
+  constexpr int kRound = Rounds<T>::kVals, kBPR = Rounds<T>::kBlocks, kFR = Rounds<T>::kForce;
+  __shared__ __align__(16) unsigned char red_raw[Rounds<T>::kBytes];
   __shared__ int32_t seg_start[65];
   __shared__ int32_t seg_cnt;
   T(*red)[kRow] = reinterpret_cast<T(*)[kRow]>(red_raw);
@@ -261,19 +271,23 @@ __global__ __launch_bounds__(64) void k_assemble_fast(AsmArgs A) {
   const int nseg = seg_cnt;
 
   // ---------------- force: f_v = c tau g_v (FP64 accumulation)
-#pragma unroll
-  for (int v = 0; v < 8; ++v)
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-      redd[3 * v + r][lane] = double(c) * double(P.tau[r][0] * g[v][0] + P.tau[r][1] * g[v][1] + P.tau[r][2] * g[v][2]);
-  __syncthreads();
   const int64_t seg0 = A.wave_seg[blockIdx.x];
-  for (int pp = lane; pp < nseg * 24; pp += 64) {
-    const int sg = pp / 24, v = pp % 24;
-    const double sum = seg_sum<double>(&redd[v][seg_start[sg]], seg_start[sg + 1] - seg_start[sg]);
-    A.segF[(seg0 + sg) * 24 + v] = sum;
+#pragma unroll
+  for (int part = 0; part < 24 / kFR; ++part) {  // 24 force values in rounds of kFR
+#pragma unroll
+    for (int v = part * (kFR / 3); v < (part + 1) * (kFR / 3); ++v)
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+        redd[3 * v + r - part * kFR][lane] =
+            double(c) * double(P.tau[r][0] * g[v][0] + P.tau[r][1] * g[v][1] + P.tau[r][2] * g[v][2]);
+    __syncthreads();
+    for (int pp = lane; pp < nseg * kFR; pp += 64) {
+      const int sg = pp / kFR, v = pp % kFR;
+      const double sum = seg_sum<double>(&redd[v][seg_start[sg]], seg_start[sg + 1] - seg_start[sg]);
+      A.segF[(seg0 + sg) * 24 + part * kFR + v] = sum;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   if (!A.K) return;
 
   // ---------------- stiffness: K_(a,i)(b,k) = c [ (dtau(b,k) g_a)_i - (tau g_b)_i g_a,k ]
@@ -291,21 +305,21 @@ __global__ __launch_bounds__(64) void k_assemble_fast(AsmArgs A) {
     for (int k = 0; k < 3; ++k) dtau_rank1<T>(P, k, gt, c, dt[k]);
 #pragma unroll
     for (int a = 0; a <= b; ++a) {
-      const int slotv = (blk % 4) * 9;
+      const int slotv = (blk % kBPR) * 9;
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int k = 0; k < 3; ++k)
           red[slotv + 3 * r + k][lane] =
               dt[k][r][0] * g[a][0] + dt[k][r][1] * g[a][1] + dt[k][r][2] * g[a][2] - tg[r] * g[a][k];
-      if (blk % 4 == 3) {
+      if (blk % kBPR == kBPR - 1) {
         __syncthreads();
-        const int rnd = blk / 4;
+        const int rnd = blk / kBPR;
         for (int pp = lane; pp < nseg * kRound; pp += 64) {
           const int sg = pp / kRound, v = pp % kRound;
           const T sum = seg_sum<T>(&red[v][seg_start[sg]], seg_start[sg + 1] - seg_start[sg]);
           // slot-major record [a][b][r][k]: block (a,b) and, off the diagonal, its transpose
-          const int bi = rnd * 4 + v / 9, r = (v % 9) / 3, k = v % 3;
+          const int bi = rnd * kBPR + v / 9, r = (v % 9) / 3, k = v % 3;
           const int ba = c_blk_a[bi], bb = c_blk_b[bi];
           T* rec = segK + (seg0 + sg) * 576;
           rec[ba * 72 + bb * 9 + r * 3 + k] = sum;

@@ -160,7 +160,7 @@ class Mesh:
 
     def assemble(self, s: dict, u: torch.Tensor, precision="f64", f_ext=None, dirichlet=None, want_K=True,
                  want_sigma=True, want_residual=True, commit=False, out: Optional[dict] = None) -> dict:
-        p = PRECISION[precision]
+        p = PRECISION.get(precision, precision)
         i = self.info
         n = i["n_point"]
         o = {} if out is None else out
@@ -187,7 +187,7 @@ class Mesh:
         return o
 
     def adjoint(self, s: dict, u: torch.Tensor, lam: torch.Tensor, precision="f64", out: Optional[dict] = None):
-        p = PRECISION[precision]
+        p = PRECISION.get(precision, precision)
         n = self.info["n_point"]
         o = {} if out is None else out
         for k in ("dE", "dnu", "dsy", "dV"):

@@ -1,0 +1,161 @@
+"""Full-size parity on the cone-penetration workload (5.75M points), in the launch
+configuration bench.py times. Integer outputs (leaves, nodes, constraints, point order,
+CSR) are compared whole and bit-exact. Floating-point outputs are compared on samples the
+oracle computes exactly: the f_int entries and K rows of sampled nodes from an oracle run
+over every point whose support holds those nodes, sigma of sampled points, and the adjoint
+gradients of 64 seeded points (against the oracle and central differences)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle.oracle import OracleMesh
+from tests.gpu_common import log, rel_err, to_np
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-11
+
+
+@pytest.fixture(scope="module")
+def c2():
+    from paper_2606_09275_amd.mesh import Mesh
+    w = W.get("c2")
+    o = OracleMesh(w.crit())
+    lv = o.leaves()
+    ps = W.make_points(w, lv[:, :3], lv[:, 3])
+    log(f"[setup] c2 full size: {ps.n} points, {lv.shape[0]} leaves")
+    o.set_points(ps.x, ps.l)
+    m = Mesh(w.crit(), torch.from_numpy(ps.x).cuda(), torch.from_numpy(ps.l).cuda())
+    st = W.make_state(w, ps)
+    nodes = o.nodes()
+    u = W.make_u(w, nodes)
+    lam = W.make_lambda(w, nodes)
+    s_dev = m.sorted_state(st)
+    return dict(w=w, o=o, m=m, ps=ps, st=st, nodes=nodes, u=u, lam=lam, s_dev=s_dev)
+
+
+def test_c2_mesh_order_csr_bitexact(c2):
+    o, m = c2["o"], c2["m"]
+    a = m.arrays()
+    assert np.array_equal(to_np(a["leaf"]), o.leaves())
+    assert np.array_equal(to_np(a["node_ijk"]), o.nodes())
+    ijk, sup, wt, own = o.hanging()
+    assert np.array_equal(to_np(a["hang_ijk"]), ijk)
+    assert np.array_equal(to_np(a["hang_owner"]), own)
+    perm_o, pleaf_o, nleaf_o = o.perm()
+    perm = to_np(a["perm"])
+    assert np.array_equal(perm, perm_o)
+    assert np.array_equal(to_np(a["point_leaf"]), pleaf_o[perm])
+    rp, col = o.csr()
+    assert np.array_equal(to_np(a["row_ptr"]), rp)
+    assert np.array_equal(to_np(a["col"]), col)
+
+
+def _subset_for_nodes(c, node_ids):
+    """Original indices of every point whose support holds one of the nodes."""
+    o = c["o"]
+    n_, ids, _ = o.cells()
+    leaves = np.nonzero(np.isin(ids[:, :8], node_ids).any(axis=1))[0]
+    perm_o, pleaf_o, nleaf_o = o.perm()
+    assert np.all(nleaf_o == 1)
+    return np.nonzero(np.isin(pleaf_o, leaves))[0]
+
+
+def _oracle_subset(c, idx):
+    w, ps, st = c["w"], c["ps"], c["st"]
+    sub = OracleMesh(w.crit())
+    sub.set_points(ps.x[:, idx], ps.l[:, idx])
+    ss = {k: (v[..., idx] if isinstance(v, np.ndarray) else v) for k, v in st.items()}
+    return sub, ss
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", TOL64), ("f32k", 2e-5)])
+def test_c2_sampled_rows_and_stress(c2, prec, tol):
+    m, o = c2["m"], c2["o"]
+    out = m.assemble(c2["s_dev"], torch.from_numpy(c2["u"]).cuda(), prec)
+    torch.cuda.synchronize()
+    f = to_np(out["f_int"])
+    K = to_np(out["K"]).astype(np.float64)
+    rp, col = o.csr()
+    # forces balance (sum over nodes of f_int = 0) to the working precision of the point arithmetic
+    assert np.abs(f.reshape(-1, 3).sum(axis=0)).max() < (1e-10 if prec == "f64" else 1e-6) * np.abs(f).sum()
+    rng = np.random.default_rng(11)
+    active = np.nonzero(np.diff(rp)[0::3] > 0)[0]
+    nodes = rng.choice(active, 40, replace=False)
+    idx = _subset_for_nodes(c2, nodes)
+    sub, ss = _oracle_subset(c2, idx)
+    ref = sub.assemble(ss, c2["u"])
+    srp, scol = sub.csr()
+    ef = ek = 0.0
+    fscale = np.abs(f).max()
+    for nd in nodes:
+        ef = max(ef, np.abs(f[3 * nd:3 * nd + 3] - ref["f_int"][3 * nd:3 * nd + 3]).max() / fscale)
+        for r in range(3):
+            row = 3 * nd + r
+            a0, a1 = rp[row], rp[row + 1]
+            b0, b1 = srp[row], srp[row + 1]
+            assert np.array_equal(col[a0:a1], scol[b0:b1])
+            ek = max(ek, np.abs(K[a0:a1] - ref["K"][b0:b1]).max() / np.abs(ref["K"][b0:b1]).max())
+    perm = to_np(m.arrays()["perm"])
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(perm.size)
+    sig = to_np(out["sigma"])[:, inv[idx]]
+    es = rel_err(sig, ref["sigma"])
+    log(f"[parity] c2 full {prec}: sampled f={ef:.2e} K rows={ek:.2e} sigma={es:.2e} ({idx.size} points)")
+    assert ef <= tol and ek <= tol and es <= tol
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", TOL64), ("f32k", 1e-4)])
+def test_c3_adjoint_64_points(c2, prec, tol):
+    """dL/d(E, nu, sigma_y, V_n) for L = lambda . f_int at 64 seeded points (32 in level-8
+    leaves, 32 coarser): against the oracle gradient and, in FP64, central differences of L
+    with a 1e-6 relative step."""
+    m, o = c2["m"], c2["o"]
+    g = m.adjoint(c2["s_dev"], torch.from_numpy(c2["u"]).cuda(), torch.from_numpy(c2["lam"]).cuda(), prec)
+    torch.cuda.synchronize()
+    perm = to_np(m.arrays()["perm"])
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(perm.size)
+    perm_o, pleaf_o, _ = o.perm()
+    lvl = o.leaves()[pleaf_o, 3]
+    rng = np.random.default_rng(3)
+    fine = rng.choice(np.nonzero(lvl == 8)[0], 32, replace=False)
+    coarse = rng.choice(np.nonzero(lvl < 8)[0], 32, replace=False)
+    pts = np.concatenate([fine, coarse])
+    sub, ss = _oracle_subset(c2, pts)
+    ref = sub.adjoint(ss, c2["u"], c2["lam"])
+    errs = {}
+    for key in ("dE", "dnu", "dsy", "dV"):
+        got = to_np(g[key])[inv[pts]]
+        errs[key] = rel_err(got, ref[key])
+    log(f"[parity] c3 adjoint {prec} 64 points: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    assert all(v <= tol for v in errs.values()), errs
+    if prec != "f64":
+        return
+    # central differences of L over the subset (only point p's term changes with its parameters)
+    base = sub.assemble(ss, c2["u"], want_K=False)
+    fd_all, got_all = {k: [] for k in ("dE", "dnu", "dsy", "dV")}, {k: [] for k in ("dE", "dnu", "dsy", "dV")}
+    for j in range(0, 64, 4):
+        for key, gk in (("E", "dE"), ("nu", "dnu"), ("sy", "dsy"), ("vol", "dV")):
+            if key == "sy" and not math.isfinite(ss["sy"][j]):
+                continue
+            h = 1e-6 * abs(ss[key][j])
+            Ls = []
+            for sgn in (1, -1):
+                s2 = dict(ss)
+                s2[key] = ss[key].copy()
+                s2[key][j] += sgn * h
+                o2 = sub.assemble(s2, c2["u"], want_K=False)
+                if o2["plastic"][j] != base["plastic"][j]:
+                    break
+                Ls.append(c2["lam"] @ o2["f_int"])
+            if len(Ls) < 2:
+                continue
+            fd_all[gk].append((Ls[0] - Ls[1]) / (2 * h))
+            got_all[gk].append(to_np(g[gk])[inv[pts[j]]])
+    fd_err = {k: rel_err(np.array(got_all[k]), np.array(fd_all[k])) for k in fd_all if fd_all[k]}
+    log("[parity] c3 adjoint vs central differences: " + " ".join(f"{k}={v:.2e}" for k, v in fd_err.items()))
+    assert all(v <= 1e-6 for v in fd_err.values()), fd_err

@@ -119,10 +119,21 @@ def main():
     log(f"[bench] workload {w.name}: {ps.n} points, {lv.shape[0]} leaves ({time.time() - t0:.1f}s)")
     x_dev = torch.from_numpy(ps.x).cuda()
     l_dev = torch.from_numpy(ps.l).cuda()
-    t0 = time.time()
+    if "prev_x_s" in w.extra:
+        # moving tool: the mesh of the previous tool position exists first; the timed build
+        # below is the re-adaptation to the current position with the same points
+        b = list(w.body)
+        dx = float(w.extra["prev_x_s"]) - b[0]
+        prev = dict(w.crit(), body=tuple([b[0] + dx, b[1] + dx] + b[2:] + [0.0] * (8 - len(b))))
+        pm = Mesh(prev, x_dev, l_dev)
+        del pm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     mesh = Mesh(w.crit(), x_dev, l_dev)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
     info = mesh.info
-    log(f"[bench] octree_build {time.time() - t0:.1f}s: nodes {info['n_node']} hanging {info['n_hang']} "
+    log(f"[bench] octree_build {build_ms:.1f} ms: nodes {info['n_node']} hanging {info['n_hang']} "
         f"nnz {info['nnz']} straddle {info['n_straddle']}")
     nodes = mesh.arrays()["node_ijk"].cpu().numpy()
     u = torch.from_numpy(W.make_u(w, nodes)).cuda()
@@ -177,6 +188,7 @@ def main():
         t1 = time.perf_counter()
         kt = mesh.kernel_timing(0)
         ms = (t1 - t0) * 1e3 / args.steps
+        step_ms = np.array([e[3].elapsed_time(e[2]) for e in evs])
         sort_ms = float(np.mean([e[3].elapsed_time(e[0]) for e in evs]))
         asm_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
         adj_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
@@ -188,7 +200,10 @@ def main():
                              adjoint_ms=adj_ms, assemble_kernel_ms=k_asm, adjoint_kernel_ms=k_adj,
                              gather_kernel_ms=k_gat,
                              assembly_points_per_s=n / (asm_ms * 1e-3), adjoint_points_per_s=n / (adj_ms * 1e-3),
-                             adjoint_over_assembly=adj_ms / asm_ms, rnorm=rn)
+                             adjoint_over_assembly=adj_ms / asm_ms, rnorm=rn,
+                             step_ms_p10=float(np.percentile(step_ms, 10)),
+                             step_ms_p50=float(np.percentile(step_ms, 50)),
+                             step_ms_p90=float(np.percentile(step_ms, 90)))
         log(f"[bench] {prec}: step {ms:.3f} ms ({n / ms / 1e3:.3e} pts/s) | sort+gather {sort_ms:.3f} "
             f"assemble {asm_ms:.3f} (kernel {k_asm:.3f} + gather {k_gat:.3f}) adjoint {adj_ms:.3f} (kernel {k_adj:.3f}) ms")
 
@@ -218,7 +233,9 @@ def main():
                    "n_straddle": info["n_straddle"],
                    "step": "point sort + state gather + assemble (f_int, K, sigma, residual norm) + adjoint"},
         "phases_ms": {k: R[k] for k in ("sort_ms", "assemble_ms", "adjoint_ms", "assemble_kernel_ms",
-                                        "gather_kernel_ms", "adjoint_kernel_ms")},
+                                        "gather_kernel_ms", "adjoint_kernel_ms", "step_ms_p10",
+                                        "step_ms_p50", "step_ms_p90")},
+        "setup_ms": {"octree_build": build_ms},
         "assembly_points_per_s": R["assembly_points_per_s"], "adjoint_points_per_s": R["adjoint_points_per_s"],
         "adjoint_over_assembly": R["adjoint_over_assembly"],
         "roofline": roofline,
@@ -228,9 +245,37 @@ def main():
                                                          "adjoint_points_per_s", "assemble_kernel_ms",
                                                          "adjoint_kernel_ms")}
         out["fp32k"]["speedup_assembly_vs_fp64"] = results["f32k"]["assembly_points_per_s"] / R["assembly_points_per_s"]
+    if "prev_x_s" in w.extra:
+        out["protocol"] = tool_protocol(mesh, w, nodes, views, x_dev, perm_buf, leaf_buf, packed, sorted_buf,
+                                        f_ext, dirichlet, lam)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, ps, st, nodes, args.cpu_sample)
     print(json.dumps(out), flush=True)
+
+
+def tool_protocol(mesh, w, nodes, views, x_dev, perm_buf, leaf_buf, packed, sorted_buf, f_ext, dirichlet, lam):
+    """Moving-tool protocol after re-adaptation: re-sort of the points, then the Newton
+    iterations of one step (10 assemblies with FP32 tangent and FP64 f_int, displacement k
+    drawn with seed (seed_u, 1, k)) and one adjoint; mean milliseconds of each."""
+    import torch
+    import workloads as W
+    us = [torch.from_numpy(W.make_u(w, nodes, k=k)).cuda() for k in range(10)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    outs = {}
+    mesh.assemble(views, us[0], "f32k", f_ext=f_ext, dirichlet=dirichlet, out=outs)
+    torch.cuda.synchronize()
+    ev[0].record()
+    mesh.point_sort(x_dev, perm_buf, leaf_buf)
+    mesh.permute(packed, perm_buf, out=sorted_buf)
+    ev[1].record()
+    for k in range(10):
+        mesh.assemble(views, us[k], "f32k", f_ext=f_ext, dirichlet=dirichlet, out=outs)
+    ev[2].record()
+    mesh.adjoint(views, us[-1], lam, "f32k")
+    ev[3].record()
+    torch.cuda.synchronize()
+    return {"resort_ms": ev[0].elapsed_time(ev[1]), "assembly_f32k_ms": ev[1].elapsed_time(ev[2]) / 10,
+            "adjoint_f32k_ms": ev[2].elapsed_time(ev[3]), "iterations": 10}
 
 
 def cpu_baseline(w, ps, st, nodes, sample):

@@ -1,6 +1,7 @@
 // Assembly kernels: fused per-point GIMP basis -> kinematics -> Hencky/von Mises return ->
-// consistent tangent -> per-leaf segmented reduction in LDS -> atomics into f_int and the
-// CSR values; a general kernel for domains overlapping several leaves; body force;
+// consistent tangent -> per-leaf segmented reduction in LDS -> segment records -> (records
+// of heavily populated leaves summed) -> one workgroup per node row writes f_int and the CSR
+// values; a general kernel with atomics for domains overlapping several leaves; body force;
 // residual and its FP64 norm; the adjoint gather.
 #include <algorithm>
 #include <cstring>
@@ -164,6 +165,25 @@ struct Rounds {
                                                                                  : kForce * kRow * 8;
 };
 
+// Segments of this wavefront's 64 points (runs of one leaf): seg_start[s] is the first lane
+// of segment s and seg_start[nseg] the number of points; all 64 lanes must call it.
+__device__ __forceinline__ void wave_segments(int32_t leaf, bool inr, int64_t n, int32_t* seg_start,
+                                              int32_t* seg_cnt) {
+  const int lane = threadIdx.x;
+  const int32_t prev = __shfl_up(leaf, 1);
+  const bool head = inr && (lane == 0 || prev != leaf);
+  const uint64_t heads = __ballot(head);
+  const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+  const int my_seg = __popcll(heads & le) - 1;
+  if (lane == 0) *seg_cnt = __popcll(heads);
+  __syncthreads();
+  if (head) seg_start[my_seg] = lane;
+  if (lane == 0) {
+    const int64_t rem = n - int64_t(blockIdx.x) * 64;
+    seg_start[__popcll(heads)] = int32_t(rem < 64 ? rem : 64);
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(64) void k_assemble_fast(AsmArgs A) {
   constexpr int kRound = Rounds<T>::kVals, kBPR = Rounds<T>::kBlocks, kFR = Rounds<T>::kForce;
@@ -179,20 +199,7 @@ __global__ __launch_bounds__(64) void k_assemble_fast(AsmArgs A) {
   const bool inr = i < n;
   const int32_t leaf = inr ? A.pleaf[i] : -1;
   bool act = inr && A.pnleaf[i] == 1;
-
-  // segments = runs of equal leaf
-  const int32_t prev = __shfl_up(leaf, 1);
-  const bool head = inr && (lane == 0 || prev != leaf);
-  const uint64_t heads = __ballot(head);
-  const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
-  const int my_seg = __popcll(heads & le) - 1;
-  if (lane == 0) seg_cnt = __popcll(heads);
-  __syncthreads();
-  if (head) seg_start[my_seg] = lane;
-  if (lane == 0) {
-    const int64_t rem = n - int64_t(blockIdx.x) * 64;
-    seg_start[__popcll(heads)] = int32_t(rem < 64 ? rem : 64);
-  }
+  wave_segments(leaf, inr, n, seg_start, &seg_cnt);
 
   // ---------------- per-point arithmetic
   T S[8], dS[8][3], g[8][3];
@@ -330,6 +337,49 @@ __global__ __launch_bounds__(64) void k_assemble_fast(AsmArgs A) {
       ++blk;
     }
   }
+}
+
+// ------------------------------------------------------------------ record reduction
+// Task t = (first, count, out): record out = sum of records first .. first+count-1 (K values
+// when wantK, forces always), summed in ascending order. 192 threads x 3 K values.
+template <typename T>
+__global__ __launch_bounds__(192) void k_rec_reduce(void* segK_, double* __restrict__ segF,
+                                                    const int32_t* __restrict__ task, bool wantK) {
+  const int64_t first = task[3 * blockIdx.x], out = task[3 * blockIdx.x + 2];
+  const int cnt = task[3 * blockIdx.x + 1];
+  const int t = threadIdx.x;
+  if (wantK) {
+    T* segK = reinterpret_cast<T*>(segK_);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const T* p = segK + first * 576 + t + 192 * q;
+      T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+      int j = 0;
+      for (; j + 4 <= cnt; j += 4) {
+        s0 += p[int64_t(j) * 576];
+        s1 += p[int64_t(j + 1) * 576];
+        s2 += p[int64_t(j + 2) * 576];
+        s3 += p[int64_t(j + 3) * 576];
+      }
+      for (; j < cnt; ++j) s0 += p[int64_t(j) * 576];
+      segK[out * 576 + t + 192 * q] = (s0 + s1) + (s2 + s3);
+    }
+  }
+  if (t < 24) {
+    double s = 0;
+    for (int j = 0; j < cnt; ++j) s += segF[(first + j) * 24 + t];
+    segF[out * 24 + t] = s;
+  }
+}
+
+template <typename T>
+static void launch_rec_reduce(const mpm_mesh* m, hipStream_t st, bool wantK) {
+  if (m->n_red1)
+    hipLaunchKernelGGL(k_rec_reduce<T>, dim3(unsigned(m->n_red1)), dim3(192), 0, st, m->d_segK, m->d_segF,
+                       m->d_red1, wantK);
+  if (m->n_red2)
+    hipLaunchKernelGGL(k_rec_reduce<T>, dim3(unsigned(m->n_red2)), dim3(192), 0, st, m->d_segK, m->d_segF,
+                       m->d_red2, wantK);
 }
 
 // ------------------------------------------------------------------ row gather
@@ -523,22 +573,40 @@ __global__ __launch_bounds__(64) void k_assemble_general(AsmArgs A) {
 }
 
 // ------------------------------------------------------------------ body force
-__global__ void k_external_force(AsmArgs A) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+// f_ext,v = sum_p S_vp m_p g, through the same segment records and row gather as f_int.
+__global__ __launch_bounds__(64) void k_external_fast(AsmArgs A) {
+  __shared__ double redd[24][kRow];
+  __shared__ int32_t seg_start[65];
+  __shared__ int32_t seg_cnt;
+  const int lane = threadIdx.x;
+  const int64_t i = int64_t(blockIdx.x) * 64 + lane;
   const int64_t n = A.n;
-  if (i >= n || A.pnleaf[i] != 1) return;
-  const int32_t e = A.pleaf[i];
-  double x[3], l[3];
-  for (int a = 0; a < 3; ++a) {
-    x[a] = A.s.x[a * n + i];
-    l[a] = A.s.l[a * n + i];
+  const bool inr = i < n;
+  const int32_t leaf = inr ? A.pleaf[i] : -1;
+  const bool act = inr && A.pnleaf[i] == 1;
+  wave_segments(leaf, inr, n, seg_start, &seg_cnt);
+  double S[8], dS[8][3], mass = 0.0;
+  if (act) {
+    double x[3], l[3];
+    for (int a = 0; a < 3; ++a) {
+      x[a] = A.s.x[a * n + i];
+      l[a] = A.s.l[a * n + i];
+    }
+    leaf_overlap_basis<double>(A.G, leaf, A.cell_code[leaf], x, l, S, dS);
+    mass = A.s.mass[i];
+  } else {
+    for (int v = 0; v < 8; ++v) S[v] = 0.0;
   }
-  double S[8], dS[8][3];
-  leaf_overlap_basis<double>(A.G, e, A.cell_code[e], x, l, S, dS);
-  const double m = A.s.mass[i];
-  for (int v = 0; v < 8; ++v) {
-    const int64_t nd = A.cell_nodes[8 * int64_t(e) + v];
-    for (int r = 0; r < 3; ++r) atomicAdd(A.f + 3 * nd + r, S[v] * m * A.s.g[r]);
+#pragma unroll
+  for (int v = 0; v < 8; ++v)
+#pragma unroll
+    for (int r = 0; r < 3; ++r) redd[3 * v + r][lane] = S[v] * mass * A.s.g[r];
+  __syncthreads();
+  const int nseg = seg_cnt;
+  const int64_t seg0 = A.wave_seg[blockIdx.x];
+  for (int pp = lane; pp < nseg * 24; pp += 64) {
+    const int sg = pp / 24, v = pp % 24;
+    A.segF[(seg0 + sg) * 24 + v] = seg_sum<double>(&redd[v][seg_start[sg]], seg_start[sg + 1] - seg_start[sg]);
   }
 }
 
@@ -757,8 +825,15 @@ extern "C" int32_t mpm_external_force(const mpm_mesh_t* m, const mpm_state_t* s,
   hipStream_t st = (hipStream_t)stream;
   AsmArgs A = make_args(m, s);
   A.f = f_ext;
-  MPM_HIP(hipMemsetAsync(f_ext, 0, size_t(3 * m->n_node) * 8, st));
-  if (m->n_point) hipLaunchKernelGGL(k_external_force, dim3((m->n_point + 255) / 256), dim3(256), 0, st, A);
+  A.K = nullptr;
+  if (m->n_point) {
+    hipLaunchKernelGGL(k_external_fast, dim3(unsigned((m->n_point + 63) / 64)), dim3(64), 0, st, A);
+    launch_rec_reduce<double>(m, st, false);
+  }
+  // every f_ext entry is written by the gather (zero where no point contributes)
+  if (m->n_node)
+    hipLaunchKernelGGL(k_gather<double>, dim3(unsigned(m->n_node)), dim3(64), size_t(9) * m->max_deg * 8, st, A,
+                       m->n_node);
   if (m->n_straddle)
     hipLaunchKernelGGL(k_external_force_general, dim3((m->n_straddle + 63) / 64), dim3(64), 0, st, A);
   MPM_HIP(hipGetLastError());
@@ -792,6 +867,10 @@ extern "C" int32_t mpm_assemble(const mpm_mesh_t* m, const mpm_state_t* s, const
     else hipLaunchKernelGGL(k_assemble_fast<float>, grid, dim3(64), 0, st, A);
   }
   if (timed) MPM_HIP(hipEventRecord(mm->ev[1], st));
+  if (n) {
+    if (precision == MPM_F64) launch_rec_reduce<double>(m, st, K_vals != nullptr);
+    else launch_rec_reduce<float>(m, st, K_vals != nullptr);
+  }
   // f_int and every CSR value are written by the gather (zero where no point contributes)
   if (m->n_node) {
     const dim3 grid(unsigned(m->n_node));

@@ -7,6 +7,7 @@ namespace mpm {
 struct LeafGeo {
   const int32_t* leaf;      // n_leaf x 4
   const uint64_t* leaf_key; // n_leaf, ascending
+  const int32_t* cellmap;   // leaf of every finest lattice cell, x fastest (or null: search the keys)
   int64_t n_leaf;
   double lo[3];
   double hmin;
@@ -25,6 +26,7 @@ __host__ __device__ inline int64_t leaf_of_point(const LeafGeo& G, double px, do
     int v = t < 0.0 ? 0 : (t > double(G.lat[a] - 1) ? G.lat[a] - 1 : int(t));
     q[a] = v;
   }
+  if (G.cellmap) return G.cellmap[(int64_t(q[2]) * G.lat[1] + q[1]) * G.lat[0] + q[0]];
   const uint64_t m = morton(uint64_t(q[0]), uint64_t(q[1]), uint64_t(q[2]));
   int64_t lo = 0, hi = G.n_leaf;  // first key > m
   while (lo < hi) {

@@ -71,6 +71,8 @@ struct mpm_mesh {
   int64_t n_leaf = 0, n_node = 0, n_hang = 0, n_point = 0, nnz = 0, n_straddle = 0, n_active_rows = 0;
   int32_t max_support = 0;
   int leaf_bits = 1;            // bits needed for a leaf rank
+  int sub_bits = 0;             // bits of a point's position key inside its leaf
+  int32_t* d_cellmap = nullptr; // nx*ny*nz leaf ranks of the finest cells (x fastest), if not too large
   // device arrays (owned)
   int32_t* d_leaf = nullptr;        // n_leaf x 4
   uint64_t* d_leaf_key = nullptr;   // n_leaf
@@ -99,8 +101,15 @@ struct mpm_mesh {
   int32_t* d_con_seg = nullptr;     // segment * 8 + slot
   int32_t* d_con_bp = nullptr;      // offset of the slot's 8 block columns in d_bpos
   int16_t* d_bpos = nullptr;        // n_leaf x 64: block column of slot b's node in the row of slot a's node
-  void* d_segK = nullptr;           // n_seg x [8][8][3][3] reduced slot blocks (double or float)
-  double* d_segF = nullptr;         // n_seg x 24 reduced nodal forces
+  // records 0..n_seg-1 are wavefront segments; after them one record per heavily populated
+  // leaf (its segments summed) and the partial sums of those leaves' chunks
+  int64_t n_rec = 0;
+  void* d_segK = nullptr;           // n_rec x [8][8][3][3] reduced slot blocks (double or float)
+  double* d_segF = nullptr;         // n_rec x 24 reduced nodal forces
+  // record reductions (first record, count, output record), run in two stages
+  int64_t n_red1 = 0, n_red2 = 0;
+  int32_t* d_red1 = nullptr;        // n_red1 x 3: chunks of a heavy leaf's segments
+  int32_t* d_red2 = nullptr;        // n_red2 x 3: chunk records of a heavy leaf
   int64_t* d_strad = nullptr;       // n_straddle sorted positions
   int32_t* d_strad_leaf = nullptr;  // n_straddle x 8 overlapped leaves (-1 pad)
   mpm::DevErr* d_err = nullptr;

@@ -26,8 +26,11 @@ int32_t hip_fail(hipError_t e, const char* what) {
 int32_t build_tree(const mpm_refine_t& c, HostTree& T, int lat_out[3], double* hmin_out);
 
 // ------------------------------------------------------------------ point keys
-__global__ void k_point_keys(const double* __restrict__ x, int64_t n, LeafGeo G, uint64_t* __restrict__ keys,
-                             int64_t* __restrict__ idx, DevErr* err) {
+// key = leaf rank << sub_bits | Morton code of the point's h_min/16 sub-cell, masked to the
+// low sub_bits bits. A leaf is an aligned Morton block of sub-cells, so inside one leaf the
+// masked code orders points exactly as the full code does; value = original index.
+__global__ void k_point_keys(const double* __restrict__ x, int64_t n, LeafGeo G, int sub_bits,
+                             uint64_t* __restrict__ keys, uint32_t* __restrict__ idx, DevErr* err) {
 #pragma clang fp contract(off)
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= n) return;
@@ -43,18 +46,38 @@ __global__ void k_point_keys(const double* __restrict__ x, int64_t n, LeafGeo G,
     big |= tc >= double(1 << 14);
     sc[a] = bad || big ? 0 : uint64_t(tc);
   }
+  idx[p] = uint32_t(p);
   if (bad || big) {
     if (atomicCAS(&err->code, 0, bad ? MPM_ENONFINITE : MPM_ESTENCIL) == 0) err->index = p;
     keys[p] = 0;
-    idx[p] = p;
     return;
   }
-  const int64_t e = leaf_of_point(G, xp[0], xp[1], xp[2]);
-  keys[p] = (uint64_t(e) << kSubBits) | morton(sc[0], sc[1], sc[2]);
-  idx[p] = p;
+  int64_t e = leaf_of_point(G, xp[0], xp[1], xp[2]);
+  if (e < 0 || e >= G.n_leaf) {  // the leaves tile the box: never taken for a consistent tree
+    if (atomicCAS(&err->code, 0, MPM_ETREE) == 0) err->index = p;
+    e = 0;
+  }
+  const uint64_t mask = (uint64_t(1) << sub_bits) - 1;
+  keys[p] = (uint64_t(e) << sub_bits) | (morton(sc[0], sc[1], sc[2]) & mask);
+}
+
+// leaf rank of every finest lattice cell: one workgroup per leaf fills its block
+__global__ __launch_bounds__(256) void k_fill_cellmap(const int32_t* __restrict__ leaf, int lmax, int nx, int ny,
+                                                      int32_t* __restrict__ map) {
+  const int64_t e = blockIdx.x;
+  const int32_t* q = leaf + 4 * e;
+  const int s = 1 << (lmax - q[3]);
+  const int64_t cells = int64_t(s) * s * s;
+  for (int64_t c = threadIdx.x; c < cells; c += blockDim.x) {
+    const int cx = int(c % s), cy = int((c / s) % s), cz = int(c / (int64_t(s) * s));
+    map[(int64_t(q[2] + cz) * ny + (q[1] + cy)) * nx + (q[0] + cx)] = int32_t(e);
+  }
 }
 
 // ------------------------------------------------------------------ stable LSD radix sort
+// 8-bit digits; 64-bit keys with 32-bit values. Per pass: per-tile digit counts, one scan
+// per digit over the tiles, then a scatter that ranks equal digits inside each wavefront
+// with ballots (stable: tiles, wavefronts and lanes keep their input order).
 constexpr int kRsThreads = 256;
 constexpr int kRsRounds = 16;
 constexpr int kRsTile = kRsThreads * kRsRounds;
@@ -98,8 +121,8 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scan_digit(uint32_t* __restri
 }
 
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t* __restrict__ kin,
-                                                           const int64_t* __restrict__ vin, uint64_t* __restrict__ kout,
-                                                           int64_t* __restrict__ vout, int64_t n, int shift,
+                                                           const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
+                                                           uint32_t* __restrict__ vout, int64_t n, int shift,
                                                            const uint32_t* __restrict__ hist,
                                                            const uint32_t* __restrict__ tot) {
   __shared__ uint32_t run[256];
@@ -122,7 +145,7 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t* __res
     const int64_t j = base + int64_t(r) * kRsThreads + tid;
     const bool valid = j < n;
     const uint64_t k = valid ? kin[j] : 0ull;
-    const int64_t v = valid ? vin[j] : 0;
+    const uint32_t v = valid ? vin[j] : 0u;
     const uint32_t d = uint32_t(k >> shift) & 255u;
     uint64_t peers = __ballot(valid);
     for (int b = 0; b < 8; ++b) {
@@ -147,33 +170,37 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t* __res
   }
 }
 
-// sorts (keys, vals) by the low `bits` bits of keys; result in keys/vals (scratch used)
-static int32_t radix_sort(uint64_t* keys, int64_t* vals, int64_t n, int bits, uint64_t* ktmp, int64_t* vtmp,
-                          uint32_t* hist, uint32_t* tot, hipStream_t st) {
-  if (n <= 1) return MPM_OK;
-  const int nblk = int((n + kRsTile - 1) / kRsTile);
+// sorts (keys, vals) by the low `bits` bits of keys; the result ends in whichever of the
+// two buffers the last pass wrote, returned through *kres / *vres
+static int32_t radix_sort(uint64_t* keys, uint32_t* vals, int64_t n, int bits, uint64_t* ktmp, uint32_t* vtmp,
+                          uint32_t* hist, uint32_t* tot, hipStream_t st, uint64_t** kres, uint32_t** vres) {
   uint64_t *ka = keys, *kb = ktmp;
-  int64_t *va = vals, *vb = vtmp;
-  const int passes = (bits + 7) / 8;
-  for (int ps = 0; ps < passes; ++ps) {
-    const int shift = 8 * ps;
-    hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(kRsThreads), 0, st, ka, n, shift, hist);
-    hipLaunchKernelGGL(k_rs_scan_digit, dim3(256), dim3(kRsThreads), 0, st, hist, nblk, tot);
-    hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(kRsThreads), 0, st, ka, va, kb, vb, n, shift, hist, tot);
-    std::swap(ka, kb);
-    std::swap(va, vb);
+  uint32_t *va = vals, *vb = vtmp;
+  if (n > 1) {
+    const int nblk = int((n + kRsTile - 1) / kRsTile);
+    const int passes = (bits + 7) / 8;
+    for (int ps = 0; ps < passes; ++ps) {
+      const int shift = 8 * ps;
+      hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(kRsThreads), 0, st, ka, n, shift, hist);
+      hipLaunchKernelGGL(k_rs_scan_digit, dim3(256), dim3(kRsThreads), 0, st, hist, nblk, tot);
+      hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(kRsThreads), 0, st, ka, va, kb, vb, n, shift, hist, tot);
+      std::swap(ka, kb);
+      std::swap(va, vb);
+    }
   }
-  if (ka != keys) {
-    MPM_HIP(hipMemcpyAsync(keys, ka, size_t(n) * 8, hipMemcpyDeviceToDevice, st));
-    MPM_HIP(hipMemcpyAsync(vals, va, size_t(n) * 8, hipMemcpyDeviceToDevice, st));
-  }
+  *kres = ka;
+  *vres = va;
   MPM_HIP(hipGetLastError());
   return MPM_OK;
 }
 
-__global__ void k_unpack_keys(const uint64_t* __restrict__ keys, int64_t n, int32_t* __restrict__ leaf) {
+__global__ void k_unpack_keys(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t n,
+                              int sub_bits, int32_t* __restrict__ leaf, int64_t* __restrict__ perm) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) leaf[i] = int32_t(keys[i] >> kSubBits);
+  if (i < n) {
+    leaf[i] = int32_t(keys[i] >> sub_bits);
+    perm[i] = int64_t(vals[i]);
+  }
 }
 
 // overlap classification in sorted order: number of leaves each domain overlaps
@@ -267,6 +294,7 @@ LeafGeo make_geo(const mpm_mesh* m) {
   LeafGeo G;
   G.leaf = m->d_leaf;
   G.leaf_key = m->d_leaf_key;
+  G.cellmap = m->d_cellmap;
   G.n_leaf = m->n_leaf;
   for (int a = 0; a < 3; ++a) G.lo[a] = m->crit.lo[a];
   G.hmin = m->hmin;
@@ -313,9 +341,13 @@ int32_t read_error(mpm_mesh* m, hipStream_t st, const char* what) {
 // sort points (device x [3][n]) into perm / leaf with the mesh's leaves
 int32_t sort_points(const mpm_mesh* m, const double* dx, int64_t n, int64_t* perm, int32_t* leaf, hipStream_t st) {
   if (n == 0) return MPM_OK;
-  const int bits = kSubBits + m->leaf_bits;
+  if (n > int64_t(UINT32_MAX)) {
+    set_error(MPM_EARG, "point sort: more than 2^32 - 1 points");
+    return MPM_EARG;
+  }
+  const int bits = m->sub_bits + m->leaf_bits;
   uint64_t *keys = nullptr, *ktmp = nullptr;
-  int64_t* vtmp = nullptr;
+  uint32_t *vals = nullptr, *vtmp = nullptr;
   uint32_t *hist = nullptr, *tot = nullptr;
   const int nblk = int((n + kRsTile - 1) / kRsTile);
   int32_t rc = MPM_OK;
@@ -323,20 +355,22 @@ int32_t sort_points(const mpm_mesh* m, const double* dx, int64_t n, int64_t* per
   hipError_t e;
   if ((e = hipMallocAsync((void**)&keys, size_t(n) * 8, st)) != hipSuccess) fail(e, "alloc keys");
   if (!rc && (e = hipMallocAsync((void**)&ktmp, size_t(n) * 8, st)) != hipSuccess) fail(e, "alloc keys");
-  if (!rc && (e = hipMallocAsync((void**)&vtmp, size_t(n) * 8, st)) != hipSuccess) fail(e, "alloc vals");
+  if (!rc && (e = hipMallocAsync((void**)&vals, size_t(n) * 4, st)) != hipSuccess) fail(e, "alloc vals");
+  if (!rc && (e = hipMallocAsync((void**)&vtmp, size_t(n) * 4, st)) != hipSuccess) fail(e, "alloc vals");
   if (!rc && (e = hipMallocAsync((void**)&hist, size_t(nblk) * 256 * 4, st)) != hipSuccess) fail(e, "alloc hist");
   if (!rc && (e = hipMallocAsync((void**)&tot, 256 * 4, st)) != hipSuccess) fail(e, "alloc tot");
   if (!rc) {
     const LeafGeo G = make_geo(m);
-    hipLaunchKernelGGL(k_point_keys, dim3((n + 255) / 256), dim3(256), 0, st, dx, n, G, keys, perm, m->d_err);
-    rc = radix_sort(keys, perm, n, bits, ktmp, vtmp, hist, tot, st);
-    if (!rc) hipLaunchKernelGGL(k_unpack_keys, dim3((n + 255) / 256), dim3(256), 0, st, keys, n, leaf);
+    hipLaunchKernelGGL(k_point_keys, dim3((n + 255) / 256), dim3(256), 0, st, dx, n, G, m->sub_bits, keys, vals,
+                       m->d_err);
+    uint64_t* ks = nullptr;
+    uint32_t* vs = nullptr;
+    rc = radix_sort(keys, vals, n, bits, ktmp, vtmp, hist, tot, st, &ks, &vs);
+    if (!rc)
+      hipLaunchKernelGGL(k_unpack_keys, dim3((n + 255) / 256), dim3(256), 0, st, ks, vs, n, m->sub_bits, leaf, perm);
   }
-  hipFreeAsync(keys, st);
-  hipFreeAsync(ktmp, st);
-  hipFreeAsync(vtmp, st);
-  hipFreeAsync(hist, st);
-  hipFreeAsync(tot, st);
+  for (void* p : {(void*)keys, (void*)ktmp, (void*)vals, (void*)vtmp, (void*)hist, (void*)tot})
+    if (p) (void)hipFreeAsync(p, st);
   if (!rc) MPM_HIP(hipGetLastError());
   return rc;
 }
@@ -369,8 +403,8 @@ extern "C" void mpm_mesh_free(mpm_mesh_t* m) {
   void* ptrs[] = {m->d_leaf, m->d_leaf_key, m->d_cell_nodes, m->d_cell_code, m->d_cell_cmat, m->d_node_ijk,
                   m->d_hang_ijk, m->d_hang_sup, m->d_hang_w, m->d_hang_owner, m->d_perm, m->d_pleaf, m->d_pnleaf,
                   m->d_row_ptr, m->d_col, m->d_wave_seg, m->d_leaf_seg0, m->d_leaf_nseg, m->d_con_off, m->d_con_seg, m->d_con_bp, m->d_bpos,
-                  m->d_segK, m->d_segF, m->d_strad, m->d_strad_leaf, m->d_err,
-                  m->d_partial, m->d_scratch};
+                  m->d_segK, m->d_segF, m->d_red1, m->d_red2, m->d_strad, m->d_strad_leaf, m->d_err,
+                  m->d_partial, m->d_scratch, m->d_cellmap};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (hipEvent_t e : m->ev)
@@ -403,8 +437,11 @@ extern "C" int32_t octree_build(const mpm_refine_t* crit, const double* x, const
   m->n_node = int64_t(T.node_ijk.size() / 3);
   m->n_hang = int64_t(T.hang_owner.size());
   while ((int64_t(1) << m->leaf_bits) < m->n_leaf + 1) ++m->leaf_bits;
-  if (kSubBits + m->leaf_bits > 64) {
-    set_error(MPM_ESTENCIL, "octree_build: too many leaves for 64-bit point keys");
+  int lmin = crit->lvl_max;
+  for (int64_t e = 0; e < m->n_leaf; ++e) lmin = std::min(lmin, int(T.leaf[4 * e + 3]));
+  m->sub_bits = 3 * (crit->lvl_max - lmin + 4);
+  if (m->sub_bits > kSubBits || m->sub_bits + m->leaf_bits > 64) {
+    set_error(MPM_ESTENCIL, "octree_build: too many leaves or levels for 64-bit point keys");
     mpm_mesh_free(m);
     return MPM_ESTENCIL;
   }
@@ -423,6 +460,18 @@ extern "C" int32_t octree_build(const mpm_refine_t* crit, const double* x, const
   UP(m->d_hang_sup, T.hang_sup);
   UP(m->d_hang_w, T.hang_w);
   UP(m->d_hang_owner, T.hang_owner);
+  // dense leaf map of the finest cells when it takes at most 1 GiB (else the leaf search
+  // bisects the sorted leaf keys)
+  const int64_t ncell = int64_t(m->nx) * m->ny * m->nz;
+  if (ncell > 0 && ncell <= (int64_t(1) << 28) && m->n_leaf > 0) {
+    if (hipMalloc(&m->d_cellmap, size_t(ncell) * 4) != hipSuccess ||
+        hipMemsetAsync(m->d_cellmap, 0xff, size_t(ncell) * 4, st) != hipSuccess) {
+      mpm_mesh_free(m);
+      return hip_fail(hipErrorOutOfMemory, "octree_build: cell map");
+    }
+    hipLaunchKernelGGL(k_fill_cellmap, dim3(unsigned(m->n_leaf)), dim3(256), 0, st, m->d_leaf, crit->lvl_max, m->nx,
+                       m->ny, m->d_cellmap);
+  }
   if (hipMalloc(&m->d_err, sizeof(DevErr)) != hipSuccess || hipMemsetAsync(m->d_err, 0, sizeof(DevErr), st) != hipSuccess) {
     mpm_mesh_free(m);
     return hip_fail(hipErrorOutOfMemory, "octree_build: error word");
@@ -584,13 +633,40 @@ extern "C" int32_t octree_build(const mpm_refine_t* crit, const double* x, const
     mpm_mesh_free(m);
     return MPM_EARG;
   }
+  // Leaves holding more than kHeavySeg segments (a leaf with many points, which spans
+  // several wavefronts) are summed into one record first, so that every node row gathers a
+  // bounded number of records: chunks of up to kRedChunk segments are summed in parallel,
+  // then the chunk sums of each leaf, always in ascending record order.
+  constexpr int kHeavySeg = 4, kRedChunk = 64;
+  std::vector<int32_t> leaf_rec(nl, -1), red1, red2;
+  int64_t nrec = nseg;
+  for (int64_t e = 0; e < nl; ++e)
+    if (populated[e] && leaf_nseg[e] > kHeavySeg) leaf_rec[e] = int32_t(nrec++);
+  for (int64_t e = 0; e < nl; ++e) {
+    if (leaf_rec[e] < 0) continue;
+    const int32_t ns = leaf_nseg[e];
+    if (ns <= kRedChunk) {
+      red1.insert(red1.end(), {leaf_seg0[e], ns, leaf_rec[e]});
+      continue;
+    }
+    const int32_t first_chunk = int32_t(nrec);
+    const int32_t nch = (ns + kRedChunk - 1) / kRedChunk;
+    for (int32_t c = 0; c < nch; ++c)
+      red1.insert(red1.end(), {leaf_seg0[e] + c * kRedChunk, std::min(kRedChunk, ns - c * kRedChunk),
+                               int32_t(nrec++)});
+    red2.insert(red2.end(), {first_chunk, nch, leaf_rec[e]});
+  }
+  m->n_rec = nrec;
+  m->n_red1 = int64_t(red1.size() / 3);
+  m->n_red2 = int64_t(red2.size() / 3);
+  auto leaf_ncon = [&](int64_t e) -> int32_t { return leaf_rec[e] >= 0 ? 1 : leaf_nseg[e]; };
   std::vector<int32_t> con_off(nn + 1, 0);
   for (int64_t e = 0; e < nl; ++e)
     if (populated[e])
-      for (int a = 0; a < 8; ++a) con_off[T.cell_nodes[8 * e + a] + 1] += leaf_nseg[e];
+      for (int a = 0; a < 8; ++a) con_off[T.cell_nodes[8 * e + a] + 1] += leaf_ncon(e);
   for (int64_t a = 0; a < nn; ++a) con_off[a + 1] += con_off[a];
   m->n_con = con_off[nn];
-  if (m->n_con >= (int64_t(1) << 31) || nseg >= (int64_t(1) << 28)) {
+  if (m->n_con >= (int64_t(1) << 31) || nrec >= (int64_t(1) << 28)) {
     set_error(MPM_EARG, "octree_build: too many segment contributions");
     mpm_mesh_free(m);
     return MPM_EARG;
@@ -603,8 +679,9 @@ extern "C" int32_t octree_build(const mpm_refine_t* crit, const double* x, const
     const int32_t* sl = &T.cell_nodes[8 * e];
     for (int a = 0; a < 8; ++a) {
       const int64_t na = sl[a];
-      for (int g = 0; g < leaf_nseg[e]; ++g) {
-        con_seg[fill[na]] = int32_t((int64_t(leaf_seg0[e] + g) << 3) | a);
+      for (int g = 0; g < leaf_ncon(e); ++g) {
+        const int64_t rec = leaf_rec[e] >= 0 ? leaf_rec[e] : leaf_seg0[e] + g;
+        con_seg[fill[na]] = int32_t((rec << 3) | a);
         con_bp[fill[na]] = int32_t(64 * e + 8 * a);
         fill[na]++;
       }
@@ -631,8 +708,14 @@ extern "C" int32_t octree_build(const mpm_refine_t* crit, const double* x, const
   UP(m->d_con_seg, con_seg);
   UP(m->d_con_bp, con_bp);
   UP(m->d_bpos, bpos);
-  if (hipMalloc(&m->d_segK, size_t(std::max<int64_t>(1, nseg)) * 576 * 8) != hipSuccess ||
-      hipMalloc(&m->d_segF, size_t(std::max<int64_t>(1, nseg)) * 24 * 8) != hipSuccess) {
+  if (!red1.empty()) {
+    UP(m->d_red1, red1);
+  }
+  if (!red2.empty()) {
+    UP(m->d_red2, red2);
+  }
+  if (hipMalloc(&m->d_segK, size_t(std::max<int64_t>(1, nrec)) * 576 * 8) != hipSuccess ||
+      hipMalloc(&m->d_segF, size_t(std::max<int64_t>(1, nrec)) * 24 * 8) != hipSuccess) {
     mpm_mesh_free(m);
     return hip_fail(hipErrorOutOfMemory, "octree_build: segment buffers");
   }

@@ -11,7 +11,8 @@ from workloads.configs import BODY_BOX, BODY_CONE, BODY_NONE, BODY_SPHERE, Workl
 
 def tiny_workload(kind: str = "sphere", lvl_extra: int = 2, E=1e3, nu=0.3, sy=math.inf, Fn_std=0.0,
                   base=(3, 3, 3), ppa=2) -> Workload:
-    """A few-hundred-point mesh with hanging nodes (sphere/cone/box near a corner)."""
+    """A few-hundred-point mesh with hanging nodes (sphere/cone/box near a corner). ppa is the
+    number of points per axis in a leaf, or a function of the leaf level."""
     if kind == "sphere":
         bk, body, dx = BODY_SPHERE, (0.55, 0.45, 0.6, 0.12), 0.08
     elif kind == "cone":
@@ -20,8 +21,9 @@ def tiny_workload(kind: str = "sphere", lvl_extra: int = 2, E=1e3, nu=0.3, sy=ma
         bk, body, dx = BODY_BOX, (0.6, 0.8, 0.3, 0.45, 0.7, 1.0), 0.06
     else:
         bk, body, dx = BODY_NONE, (), 0.0
+    ppa_fn = ppa if callable(ppa) else (lambda lv: ppa)
     return Workload(name=f"tiny_{kind}", lo=(0.0, 0.0, 0.0), base=base, h0=1.0 / base[0], lvl_base=2,
-                    lvl_max=2 + lvl_extra, body_kind=bk, body=body, dx_region=dx, ppa=lambda lv: ppa,
+                    lvl_max=2 + lvl_extra, body_kind=bk, body=body, dx_region=dx, ppa=ppa_fn,
                     E=E, nu=nu, sy=sy, Fn_std=Fn_std, seed_state=7, seed_u=8, seed_lambda=9,
                     drop_inside_body=True)
 

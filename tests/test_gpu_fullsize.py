@@ -1,9 +1,11 @@
-"""Full-size parity on the cone-penetration workload (5.75M points), in the launch
-configuration bench.py times. Integer outputs (leaves, nodes, constraints, point order,
-CSR) are compared whole and bit-exact. Floating-point outputs are compared on samples the
-oracle computes exactly: the f_int entries and K rows of sampled nodes from an oracle run
-over every point whose support holds those nodes, sigma of sampled points, and the adjoint
-gradients of 64 seeded points (against the oracle and central differences)."""
+"""Full-size parity on the cone-penetration workload (5.75M points) and the moving-tool
+trail workload (29.9M points, leaves of up to 262,144 points), in the launch configuration
+bench.py times. Integer outputs (leaves, nodes, constraints, point order, CSR) are compared
+whole and bit-exact. Floating-point outputs are compared on samples the oracle computes
+exactly: the f_int entries and K rows of sampled nodes from an oracle run over every point
+whose support holds those nodes, sigma of sampled points, and the adjoint gradients of 64
+seeded points (against the oracle and central differences); over the whole vectors, the
+internal forces balance and the body forces sum to the total weight."""
 import math
 
 import numpy as np
@@ -159,3 +161,108 @@ def test_c3_adjoint_64_points(c2, prec, tol):
     fd_err = {k: rel_err(np.array(got_all[k]), np.array(fd_all[k])) for k in fd_all if fd_all[k]}
     log("[parity] c3 adjoint vs central differences: " + " ".join(f"{k}={v:.2e}" for k, v in fd_err.items()))
     assert all(v <= 1e-6 for v in fd_err.values()), fd_err
+
+
+# Sums of millions of FP64 terms agree to about sqrt(n) unit roundoffs (~1e-12 here); one
+# point left out would change the total by at least 1/n of it (~1e-7 at these sizes).
+BODY_TOL = 1e-9
+
+
+def _body_force_total(c):
+    m, st = c["m"], c["st"]
+    fe = to_np(m.external_force(dict(c["s_dev"])))
+    tot = fe.reshape(-1, 3).sum(axis=0)
+    ref = st["mass"].sum() * np.array([0.0, 0.0, -9.81])
+    err = np.abs(tot - ref).max() / np.abs(ref).max()
+    log(f"[parity] body force total: rel err {err:.2e}")
+    assert err <= BODY_TOL
+
+
+def test_c2_body_force_total(c2):
+    """Partition of unity: the nodal body forces sum to sum_p m_p g."""
+    _body_force_total(c2)
+
+
+# ---------------------------------------------------------------- moving-tool trail workload
+
+@pytest.fixture(scope="module")
+def c4():
+    from paper_2606_09275_amd.mesh import Mesh
+    w = W.get("c4")
+    o = OracleMesh(w.crit())
+    lv = o.leaves()
+    ps = W.make_points(w, lv[:, :3], lv[:, 3])
+    log(f"[setup] c4 full size: {ps.n} points, {lv.shape[0]} leaves")
+    o.set_points(ps.x, ps.l)
+    m = Mesh(w.crit(), torch.from_numpy(ps.x).cuda(), torch.from_numpy(ps.l).cuda())
+    st = W.make_state(w, ps)
+    nodes = o.nodes()
+    u = W.make_u(w, nodes)
+    s_dev = m.sorted_state(st)
+    log(f"[setup] c4 ready: {m.info['n_node']} nodes, nnz {m.info['nnz']}")
+    return dict(w=w, o=o, m=m, ps=ps, st=st, nodes=nodes, u=u, s_dev=s_dev)
+
+
+def test_c4_mesh_order_csr_bitexact(c4):
+    o, m = c4["o"], c4["m"]
+    a = m.arrays()
+    assert np.array_equal(to_np(a["leaf"]), o.leaves())
+    assert np.array_equal(to_np(a["node_ijk"]), o.nodes())
+    ijk, sup, wt, own = o.hanging()
+    assert np.array_equal(to_np(a["hang_ijk"]), ijk)
+    perm_o, pleaf_o, nleaf_o = o.perm()
+    perm = to_np(a["perm"])
+    assert np.array_equal(perm, perm_o)
+    assert np.array_equal(to_np(a["point_leaf"]), pleaf_o[perm])
+    rp, col = o.csr()
+    assert np.array_equal(to_np(a["row_ptr"]), rp)
+    assert np.array_equal(to_np(a["col"]), col)
+    assert np.bincount(pleaf_o).max() == 262144
+
+
+def test_c4_sampled_rows_heavy_leaves(c4):
+    """Rows of nodes of leaves holding 4^3 points per finest cell (summed segment records,
+    two reduction stages) and of other nodes, FP64 and FP32 tangent, against one oracle run."""
+    m, o = c4["m"], c4["o"]
+    rp, col = o.csr()
+    _, ids, _ = o.cells()
+    perm_o, pleaf_o, _ = o.perm()
+    npts = np.bincount(pleaf_o, minlength=ids.shape[0])
+    rng = np.random.default_rng(12)
+    heavy_leaf = rng.choice(np.nonzero(npts == 262144)[0], 1)[0]
+    mid_leaf = rng.choice(np.nonzero((npts > 256) & (npts < 262144))[0], 2, replace=False)
+    light = np.nonzero(np.diff(rp)[0::3] > 0)[0]
+    nodes = np.unique(np.concatenate([ids[heavy_leaf, :2], ids[mid_leaf, 0], rng.choice(light, 12, replace=False)]))
+    idx = _subset_for_nodes(c4, nodes)
+    log(f"[run] c4 sampled rows: {nodes.size} nodes, oracle subset {idx.size} points")
+    sub, ss = _oracle_subset(c4, idx)
+    ref = sub.assemble(ss, c4["u"])
+    srp, scol = sub.csr()
+    perm = to_np(m.arrays()["perm"])
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(perm.size)
+    for prec, tol in (("f64", TOL64), ("f32k", 2e-5)):
+        out = m.assemble(c4["s_dev"], torch.from_numpy(c4["u"]).cuda(), prec)
+        torch.cuda.synchronize()
+        f = to_np(out["f_int"])
+        K = to_np(out["K"]).astype(np.float64)
+        assert np.abs(f.reshape(-1, 3).sum(axis=0)).max() < (1e-10 if prec == "f64" else 1e-6) * np.abs(f).sum()
+        fscale = np.abs(f).max()
+        ef = ek = 0.0
+        for nd in nodes:
+            ef = max(ef, np.abs(f[3 * nd:3 * nd + 3] - ref["f_int"][3 * nd:3 * nd + 3]).max() / fscale)
+            for r in range(3):
+                row = 3 * nd + r
+                a0, a1 = rp[row], rp[row + 1]
+                b0, b1 = srp[row], srp[row + 1]
+                assert np.array_equal(col[a0:a1], scol[b0:b1])
+                ek = max(ek, np.abs(K[a0:a1] - ref["K"][b0:b1]).max() / np.abs(ref["K"][b0:b1]).max())
+        sig = to_np(out["sigma"])[:, inv[idx]]
+        es = rel_err(sig, ref["sigma"])
+        log(f"[parity] c4 full {prec}: sampled f={ef:.2e} K rows={ek:.2e} sigma={es:.2e}")
+        assert ef <= tol and ek <= tol and es <= tol
+        del out
+
+
+def test_c4_body_force_total(c4):
+    _body_force_total(c4)

@@ -55,14 +55,25 @@ CASES = [
     ("tiny_sphere_jit", "sphere", 0),
     ("tiny_cone_vm_jit", "cone", 1),
     ("tiny_box_vm", "box", None),
+    # coarse leaves holding 12^3 points (27 wavefront segments: one summed record per leaf)
+    ("tiny_sphere_heavy_vm", "sphere", None),
+    # coarse leaves holding 20^3 points (125 segments: chunk sums, then the leaf sum), jittered
+    ("tiny_box_heavy2_jit", "box", 2),
 ]
+
+_HEAVY_PPA = {"heavy": lambda lv: 12 if lv == 2 else 2, "heavy2": lambda lv: 20 if lv == 2 else 3}
 
 
 def _work(tag, kind):
     if kind is None:
         return W.get(tag)
     sy = math.inf if tag.endswith("_el") else (5.0 if "vm" in tag else 40.0)
-    return tiny_workload(kind, E=1e4, nu=0.3, sy=sy, Fn_std=0.03)
+    ppa = 2
+    for key in ("heavy2", "heavy"):
+        if f"_{key}" in tag:
+            ppa = _HEAVY_PPA[key]
+            break
+    return tiny_workload(kind, E=1e4, nu=0.3, sy=sy, Fn_std=0.03, ppa=ppa)
 
 
 @pytest.mark.parametrize("tag,kind,jit", CASES)

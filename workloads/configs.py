@@ -118,7 +118,7 @@ C4 = Workload(
     body_kind=BODY_BOX, body=(3.20, 3.50, 0.95, 1.05, 1.3, 1.5), dx_region=0.05, ppa=_c4_ppa,
     E=5e4, nu=0.3, sy=20.0, Fn_std=0.02, seed_state=4, seed_u=4000, seed_lambda=4,
     note="moving box tool; refined-point trail (never derefined) along the swept path",
-    extra=dict(trail_x=(0.2, 3.2), trail_band=0.075, trail_ppa=4),
+    extra=dict(trail_x=(0.2, 3.2), trail_band=0.075, trail_ppa=4, prev_x_s=3.15),
 )
 
 CONFIGS = {w.name: w for w in (C0, C1, C1B, C2, C3, C4)}

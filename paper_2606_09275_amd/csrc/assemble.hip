@@ -139,6 +139,19 @@ template <typename T>
 __device__ __forceinline__ T seg_sum(const T* row, int len) {
   T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
   int j = 0;
+  for (; j + 8 <= len; j += 8) {  // eight loads in flight per step
+    T t[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) t[q] = row[j + q];
+    s0 += t[0];
+    s1 += t[1];
+    s2 += t[2];
+    s3 += t[3];
+    s0 += t[4];
+    s1 += t[5];
+    s2 += t[6];
+    s3 += t[7];
+  }
   for (; j + 4 <= len; j += 4) {
     s0 += row[j];
     s1 += row[j + 1];
@@ -149,16 +162,36 @@ __device__ __forceinline__ T seg_sum(const T* row, int len) {
   return (s0 + s1) + (s2 + s3);
 }
 
+// Segment sums of one reduction round: the nseg x NV grid of (segment, value) sums is dealt
+// to the lanes in order (value fastest), lane l taking entries l, l + 64, ...; the (segment,
+// value) pair is advanced incrementally. store(sg, v, sum) receives each sum.
+template <typename T, int NV, int NR, typename Store>
+__device__ __forceinline__ void round_sums(const T (*red)[NR], const int32_t* seg_start, int nseg, Store store) {
+  const int lane = threadIdx.x;
+  constexpr int dsg = 64 / NV, dv = 64 % NV;
+  int sg = lane / NV, v = lane % NV;
+  for (int pp = lane; pp < nseg * NV; pp += 64) {
+    const int s0 = seg_start[sg], s1 = seg_start[sg + 1];
+    store(sg, v, seg_sum<T>(&red[v][s0], s1 - s0));
+    v += dv;
+    sg += dsg;
+    if (v >= NV) {
+      v -= NV;
+      ++sg;
+    }
+  }
+}
+
 // LDS rows of the reduction are padded by one element: lanes that sum different values of
 // one segment read one element per row, and a row stride of 65 elements spreads them over
 // the banks (a stride of 64 would put them all in one bank).
 constexpr int kRow = 65;
 
-// Values per reduction round: four 3x3 blocks in FP64; two in FP32, where the smaller LDS
-// footprint lets four wavefronts share a SIMD (the FP64 kernel is register-bound at two).
+// Values per reduction round: four 3x3 blocks (36 values); forces in FP64, 24 per round in
+// the FP64 kernel and 12 in the FP32 kernel, whose LDS then holds four wavefronts per SIMD.
 template <typename T>
 struct Rounds {
-  static constexpr int kBlocks = sizeof(T) == 8 ? 4 : 2;
+  static constexpr int kBlocks = 4;
   static constexpr int kVals = 9 * kBlocks;
   static constexpr int kForce = sizeof(T) == 8 ? 24 : 12;  // force values per round
   static constexpr int kBytes = (kVals * kRow * int(sizeof(T)) > kForce * kRow * 8) ? kVals * kRow * int(sizeof(T))
@@ -184,16 +217,26 @@ __device__ __forceinline__ void wave_segments(int32_t leaf, bool inr, int64_t n,
   }
 }
 
+// Register budget: two wavefronts per SIMD in FP64 (256 registers), four in FP32 (128).
 template <typename T>
-__global__ __launch_bounds__(64) void k_assemble_fast(AsmArgs A) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 4)))
+void k_assemble_fast(AsmArgs A) {
   constexpr int kRound = Rounds<T>::kVals, kBPR = Rounds<T>::kBlocks, kFR = Rounds<T>::kForce;
   __shared__ __align__(16) unsigned char red_raw[Rounds<T>::kBytes];
   __shared__ int32_t seg_start[65];
   __shared__ int32_t seg_cnt;
+  // record offsets of upper-triangle block bi = (a, b): [0] a*72 + b*9, [1] b*72 + a*9 (-1 on
+  // the diagonal)
+  __shared__ int16_t blk_off[2][36];
   T(*red)[kRow] = reinterpret_cast<T(*)[kRow]>(red_raw);
   double(*redd)[kRow] = reinterpret_cast<double(*)[kRow]>(red_raw);
 
   const int lane = threadIdx.x;
+  if (lane < 36) {
+    const int ba = c_blk_a[lane], bb = c_blk_b[lane];
+    blk_off[0][lane] = int16_t(ba * 72 + bb * 9);
+    blk_off[1][lane] = int16_t(ba != bb ? bb * 72 + ba * 9 : -1);
+  }
   const int64_t i = int64_t(blockIdx.x) * 64 + lane;
   const int64_t n = A.n;
   const bool inr = i < n;
@@ -288,28 +331,58 @@ __global__ __launch_bounds__(64) void k_assemble_fast(AsmArgs A) {
         redd[3 * v + r - part * kFR][lane] =
             double(c) * double(P.tau[r][0] * g[v][0] + P.tau[r][1] * g[v][1] + P.tau[r][2] * g[v][2]);
     __syncthreads();
-    for (int pp = lane; pp < nseg * kFR; pp += 64) {
-      const int sg = pp / kFR, v = pp % kFR;
-      const double sum = seg_sum<double>(&redd[v][seg_start[sg]], seg_start[sg + 1] - seg_start[sg]);
+    round_sums<double, kFR>(redd, seg_start, nseg, [&](int sg, int v, double sum) {
       A.segF[(seg0 + sg) * 24 + part * kFR + v] = sum;
-    }
+    });
     __syncthreads();
   }
   if (!A.K) return;
 
   // ---------------- stiffness: K_(a,i)(b,k) = c [ (dtau(b,k) g_a)_i - (tau g_b)_i g_a,k ]
+  // = sum_j X[k][i][j] g_a,j with X[k][i][j] = c dtau(b,k)_ij - (c tau g_b)_i delta_jk.
+  // FP64 forms the 6x9 tangent matrix once (fewer operations); FP32 rotates each direction
+  // from the principal frame (fewer live registers: four wavefronts per SIMD).
+  constexpr bool kMatrix = sizeof(T) == 8;
   T* segK = reinterpret_cast<T*>(A.segK);
+  T C[6][9];
+  if constexpr (kMatrix) spatial_tangent<T>(P, c, C);
+  T tau6[6] = {P.tau[0][0], P.tau[1][1], P.tau[2][2], P.tau[0][1], P.tau[1][2], P.tau[0][2]};
   int blk = 0;
 #pragma unroll
   for (int b = 0; b < 8; ++b) {
-    T gt[3], tg[3];
+    T X[3][3][3];
+    if constexpr (kMatrix) {
 #pragma unroll
-    for (int al = 0; al < 3; ++al) gt[al] = P.N[0][al] * g[b][0] + P.N[1][al] * g[b][1] + P.N[2][al] * g[b][2];
+      for (int k = 0; k < 3; ++k) {
+        T d6[6];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) tg[r] = c * (P.tau[r][0] * g[b][0] + P.tau[r][1] * g[b][1] + P.tau[r][2] * g[b][2]);
-    T dt[3][3][3];
+        for (int q = 0; q < 6; ++q)
+          d6[q] = C[q][3 * k] * g[b][0] + C[q][3 * k + 1] * g[b][1] + C[q][3 * k + 2] * g[b][2];
+        X[k][0][0] = d6[0];
+        X[k][1][1] = d6[1];
+        X[k][2][2] = d6[2];
+        X[k][0][1] = X[k][1][0] = d6[3];
+        X[k][1][2] = X[k][2][1] = d6[4];
+        X[k][0][2] = X[k][2][0] = d6[5];
+      }
+    } else {
+      T gt[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) dtau_rank1<T>(P, k, gt, c, dt[k]);
+      for (int al = 0; al < 3; ++al) gt[al] = P.N[0][al] * g[b][0] + P.N[1][al] * g[b][1] + P.N[2][al] * g[b][2];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) dtau_rank1<T>(P, k, gt, c, X[k]);
+    }
+    {
+      const T tg0 = c * (tau6[0] * g[b][0] + tau6[3] * g[b][1] + tau6[5] * g[b][2]);
+      const T tg1 = c * (tau6[3] * g[b][0] + tau6[1] * g[b][1] + tau6[4] * g[b][2]);
+      const T tg2 = c * (tau6[5] * g[b][0] + tau6[4] * g[b][1] + tau6[2] * g[b][2]);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        X[k][0][k] -= tg0;
+        X[k][1][k] -= tg1;
+        X[k][2][k] -= tg2;
+      }
+    }
 #pragma unroll
     for (int a = 0; a <= b; ++a) {
       const int slotv = (blk % kBPR) * 9;
@@ -317,21 +390,17 @@ __global__ __launch_bounds__(64) void k_assemble_fast(AsmArgs A) {
       for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-          red[slotv + 3 * r + k][lane] =
-              dt[k][r][0] * g[a][0] + dt[k][r][1] * g[a][1] + dt[k][r][2] * g[a][2] - tg[r] * g[a][k];
+          red[slotv + 3 * r + k][lane] = X[k][r][0] * g[a][0] + X[k][r][1] * g[a][1] + X[k][r][2] * g[a][2];
       if (blk % kBPR == kBPR - 1) {
         __syncthreads();
         const int rnd = blk / kBPR;
-        for (int pp = lane; pp < nseg * kRound; pp += 64) {
-          const int sg = pp / kRound, v = pp % kRound;
-          const T sum = seg_sum<T>(&red[v][seg_start[sg]], seg_start[sg + 1] - seg_start[sg]);
+        round_sums<T, kRound>(red, seg_start, nseg, [&](int sg, int v, T sum) {
           // slot-major record [a][b][r][k]: block (a,b) and, off the diagonal, its transpose
-          const int bi = rnd * kBPR + v / 9, r = (v % 9) / 3, k = v % 3;
-          const int ba = c_blk_a[bi], bb = c_blk_b[bi];
+          const int bi = rnd * kBPR + v / 9, rk = v % 9, r = rk / 3, k = rk - 3 * r;
           T* rec = segK + (seg0 + sg) * 576;
-          rec[ba * 72 + bb * 9 + r * 3 + k] = sum;
-          if (ba != bb) rec[bb * 72 + ba * 9 + k * 3 + r] = sum;
-        }
+          rec[blk_off[0][bi] + rk] = sum;
+          if (blk_off[1][bi] >= 0) rec[blk_off[1][bi] + 3 * k + r] = sum;
+        });
         __syncthreads();
       }
       ++blk;
@@ -604,10 +673,8 @@ __global__ __launch_bounds__(64) void k_external_fast(AsmArgs A) {
   __syncthreads();
   const int nseg = seg_cnt;
   const int64_t seg0 = A.wave_seg[blockIdx.x];
-  for (int pp = lane; pp < nseg * 24; pp += 64) {
-    const int sg = pp / 24, v = pp % 24;
-    A.segF[(seg0 + sg) * 24 + v] = seg_sum<double>(&redd[v][seg_start[sg]], seg_start[sg + 1] - seg_start[sg]);
-  }
+  round_sums<double, 24>(redd, seg_start, nseg,
+                         [&](int sg, int v, double sum) { A.segF[(seg0 + sg) * 24 + v] = sum; });
 }
 
 __global__ void k_external_force_general(AsmArgs A) {

@@ -140,12 +140,21 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t* __res
   run[tid] = dbase[tid] + hist[int64_t(tid) * gridDim.x + blockIdx.x];
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t base = int64_t(blockIdx.x) * kRsTile;
+  uint64_t kk[kRsRounds];  // the whole tile is loaded up front: one memory latency per tile
+  uint32_t vv[kRsRounds];
+#pragma unroll
+  for (int r = 0; r < kRsRounds; ++r) {
+    const int64_t j = base + int64_t(r) * kRsThreads + tid;
+    kk[r] = j < n ? kin[j] : 0ull;
+    vv[r] = j < n ? vin[j] : 0u;
+  }
+#pragma unroll
   for (int r = 0; r < kRsRounds; ++r) {
     for (int i = tid; i < (kRsThreads / 64) * 256; i += kRsThreads) (&wcnt[0][0])[i] = 0u;
     const int64_t j = base + int64_t(r) * kRsThreads + tid;
     const bool valid = j < n;
-    const uint64_t k = valid ? kin[j] : 0ull;
-    const uint32_t v = valid ? vin[j] : 0u;
+    const uint64_t k = kk[r];
+    const uint32_t v = vv[r];
     const uint32_t d = uint32_t(k >> shift) & 255u;
     uint64_t peers = __ballot(valid);
     for (int b = 0; b < 8; ++b) {

@@ -283,6 +283,55 @@ __device__ __forceinline__ void dtau_rank1(const PointMat<T>& P, int k, const T 
     for (int j = i; j < 3; ++j) dt[i][j] = dt[j][i] = W[i][0] * P.N[j][0] + W[i][1] * P.N[j][1] + W[i][2] * P.N[j][2];
 }
 
+// The same linearisation as a matrix: for Z = e_k (x) g, dtau_ij = sum_l C[q(i,j)][3k+l] g_l
+// with q = 0..5 for (xx, yy, zz, xy, yz, xz), scaled by sc. With P^a = n_a n_a^T the normal
+// part is sum_ac D_ac P^a_ij P^c_kl; each eigenvector pair (a,b) adds
+// Geff theta_ab (n_a n_b^T + n_b n_a^T)_ij (x_b N_ka N_lb + x_a N_kb N_la). Forming C once
+// per point replaces the per-direction rotations of dtau_rank1 by a 6x3 product per node.
+template <typename T>
+__device__ __forceinline__ void spatial_tangent(const PointMat<T>& P, T sc, T C[6][9]) {
+  constexpr int vi[6] = {0, 1, 2, 0, 1, 0}, vj[6] = {0, 1, 2, 1, 2, 2};
+  T M[6][3];  // M[q][c] = sc sum_a P^a_q D_ac
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    T pa[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) pa[a] = P.N[vi[q]][a] * P.N[vj[q]][a];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) M[q][c] = sc * (pa[0] * P.D[0][c] + pa[1] * P.D[1][c] + pa[2] * P.D[2][c]);
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int l = k; l < 3; ++l) {
+      const T p0 = P.N[k][0] * P.N[l][0], p1 = P.N[k][1] * P.N[l][1], p2 = P.N[k][2] * P.N[l][2];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const T v = M[q][0] * p0 + M[q][1] * p1 + M[q][2] * p2;
+        C[q][3 * k + l] = v;
+        C[q][3 * l + k] = v;
+      }
+    }
+  const int pa_[3] = {0, 0, 1}, pb_[3] = {1, 2, 2};
+  const T th[3] = {P.th01, P.th02, P.th12};
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    const int a = pa_[t], b = pb_[t];
+    const T gs = sc * P.Geff * th[t];
+    T S[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) S[q] = gs * (P.N[vi[q]][a] * P.N[vj[q]][b] + P.N[vi[q]][b] * P.N[vj[q]][a]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        const T R = P.x[b] * P.N[k][a] * P.N[l][b] + P.x[a] * P.N[k][b] * P.N[l][a];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) C[q][3 * k + l] += S[q] * R;
+      }
+  }
+}
+
 // kinematics from nodal displacements: H = sum u (x) dS, dF = I + H, inverse, det
 template <typename T>
 __device__ __forceinline__ T inv3(const T F[3][3], T R[3][3]) {

@@ -128,30 +128,32 @@ typedef struct {
 } mpm_state_t;
 
 /* Build the octree from the criterion, enumerate nodes, hanging nodes and constraints
- * (Section 3.1), sort the points by (leaf containing the centre, Morton code at h_min/16,
- * original index), find the leaves each GIMP domain overlaps with positive volume
+ * (Section 3.1), sort the points by (leaf containing the centre, original index), find the leaves each GIMP domain overlaps with positive volume
  * (Section 3.2; overlaps thinner than 1e-12 of the domain side do not count), and build the
  * CSR pattern: a node pair is coupled iff some point's support holds both; each coupled
  * pair is a dense 3x3 block; rows of unsupported nodes are empty.
  *   x, l: [3][n] host OR device arrays (detected), caller-owned; n may be 0 (mesh only).
  *   *out_mesh: new library-owned handle (free with mpm_mesh_free).
- * Host work: refinement, balance, numbering, CSR pattern. Device work: Morton keys,
- * radix sort, point-to-leaf search and overlap classification. */
+ * Host work: refinement, balance, numbering, CSR pattern. Device work: point-to-leaf search,
+ * radix sort and overlap classification. */
 int32_t octree_build(const mpm_refine_t* crit, const double* x, const double* l, int64_t n, void* stream,
                      mpm_mesh_t** out_mesh);
 int32_t mpm_mesh_info(const mpm_mesh_t* mesh, mpm_mesh_info_t* out);
 int32_t mpm_mesh_arrays(const mpm_mesh_t* mesh, mpm_mesh_arrays_t* out);
 void mpm_mesh_free(mpm_mesh_t* mesh);
 
-/* Re-order points of an existing mesh (device only): Morton keys, radix sort and leaf
- * search for n device points x [3][n] (must equal the mesh's point count). Writes perm_out
- * [n] (sorted position -> original index) and leaf_out [n] (sorted position -> leaf);
- * the mesh's own perm is not changed. Timed as the point-to-cell step of a re-sort. */
+/* Re-order points of an existing mesh (device only): leaf search and a stable radix sort by
+ * leaf rank for n device points x [3][n] (must equal the mesh's point count). Writes
+ * perm_out [n] (sorted position -> original index) and leaf_out [n] (sorted position ->
+ * leaf); the mesh's own perm is not changed. The work buffers (about 16 n bytes) are kept
+ * with the mesh: the first call allocates them, later calls allocate nothing. */
 int32_t mpm_point_sort(const mpm_mesh_t* mesh, const double* x, int64_t n, int64_t* perm_out, int32_t* leaf_out,
                        void* stream);
 
 /* dst[c][p] = src[c][perm[p]] for c < ncomp (device, double): brings original-order state
- * into sorted order. perm = the mesh's perm when NULL. */
+ * into sorted order. perm = the mesh's perm when NULL. For 2 <= ncomp <= 32 the arrays pass
+ * through a record-major staging copy (8 ncomp n bytes, kept with the mesh and grown when a
+ * call needs more); src and dst must not overlap. */
 int32_t mpm_permute(const mpm_mesh_t* mesh, const int64_t* perm, const double* src, double* dst, int32_t ncomp,
                     void* stream);
 

@@ -514,11 +514,10 @@ int orc_point_leaves(const orc_mesh* m, const double x[3], const double l[3], in
   return cnt;
 }
 
-typedef struct { int32_t leaf; uint64_t sub; int64_t idx; } ptkey;
+typedef struct { int32_t leaf; int64_t idx; } ptkey;
 static int cmp_ptkey(const void* a, const void* b) {
   const ptkey *p = (const ptkey*)a, *q = (const ptkey*)b;
   if (p->leaf != q->leaf) return p->leaf < q->leaf ? -1 : 1;
-  if (p->sub != q->sub) return p->sub < q->sub ? -1 : 1;
   return p->idx < q->idx ? -1 : (p->idx > q->idx);
 }
 static int cmp_u64(const void* a, const void* b) {
@@ -541,22 +540,17 @@ int32_t orc_mesh_set_points(orc_mesh* m, const double* x, const double* l, int64
   m->pnleaf = (uint8_t*)malloc((size_t)(n + 1));
   m->sup_off = (int64_t*)malloc((size_t)(n + 1) * sizeof(int64_t));
 
-  /* point order: (leaf containing the centre, Morton code at h_min/16, original index) */
+  /* point order: (leaf containing the centre, original index) */
   int lim[3] = {m->nx, m->ny, m->nz};
   ptkey* pk = (ptkey*)malloc((size_t)(n + 1) * sizeof(ptkey));
-  double hsub = m->hmin / 16.0;
   for (int64_t p = 0; p < n; p++) {
     int q[3];
-    uint64_t sc[3];
     for (int a = 0; a < 3; a++) {
       double xa = x[a * n + p];
       if (!isfinite(xa) || !isfinite(l[a * n + p]) || !(l[a * n + p] > 0)) { *bad = p; free(pk); return ORC_ENONFINITE; }
       q[a] = clampi((int)floor((xa - m->c.lo[a]) / m->hmin), 0, lim[a] - 1);
-      double sfl = floor((xa - m->c.lo[a]) / hsub);
-      sc[a] = sfl < 0 ? 0 : (uint64_t)sfl;
     }
     pk[p].leaf = m->leafmap[cidx(m, q[0], q[1], q[2])];
-    pk[p].sub = orc_morton3(sc[0], sc[1], sc[2]);
     pk[p].idx = p;
     m->pleaf[p] = pk[p].leaf;
   }

@@ -455,70 +455,88 @@ static void launch_rec_reduce(const mpm_mesh* m, hipStream_t st, bool wantK) {
 // One workgroup per independent node n: the three CSR rows of n are accumulated in LDS from
 // the reduced segment blocks of every (populated leaf, slot a) incidence of n, in ascending
 // leaf order, and written once. A contribution is the contiguous [a][0..7][r][k] slab of a
-// segment record. Rows and f_int are overwritten.
-template <typename T>
+// segment record. Rows and f_int are overwritten. The loads of a batch of contributions are
+// issued without branches (indices past the end repeat the last one and are not added), so
+// that they are all in flight together.
+template <typename T, bool WANTK>
 __global__ __launch_bounds__(64) void k_gather(AsmArgs A, int64_t n_node) {
   extern __shared__ __align__(16) unsigned char gsm[];
   T* acc = reinterpret_cast<T*>(gsm);
-  constexpr int kBatch = 8;  // contributions whose loads are in flight together
+  constexpr int kBatch = 8;
   const int64_t nd = blockIdx.x;
   const int lane = threadIdx.x;
   const int64_t base = A.row_ptr[3 * nd];
   const int deg = int((A.row_ptr[3 * nd + 1] - base) / 3);
   const int len = 9 * deg;
-  const bool wantK = A.K != nullptr;
-  for (int j = lane; j < len; j += 64) acc[j] = T(0);
+  if (WANTK)
+    for (int j = lane; j < len; j += 64) acc[j] = T(0);
   double fsum = 0.0;
   __syncthreads();
   const T* segK = reinterpret_cast<const T*>(A.segK);
   // lane -> (b, r, k) of the 72 values a contribution adds; lanes 0..7 also take values 64..71
-  const int v0 = lane, v1 = lane + 64;
+  // (the other lanes load a duplicate of their first value and do not add it)
+  const bool has1 = lane < 8;
+  const int v0 = lane, v1 = has1 ? lane + 64 : lane;
   const int b0 = v0 / 9, r0 = (v0 % 9) / 3, k0 = v0 % 3;
   const int b1 = v1 / 9, r1 = (v1 % 9) / 3, k1 = v1 % 3;
-  const bool has1 = v1 < 72;
+  const int fl = lane < 3 ? lane : 0;
   const int c0 = A.con_off[nd], c1 = A.con_off[nd + 1];
   for (int cb = c0; cb < c1; cb += kBatch) {
     const int nb = c1 - cb < kBatch ? c1 - cb : kBatch;
+    // lane j < kBatch loads contribution j; every lane then reads them back as uniform values
+    const int jl = cb + (lane < nb ? lane : nb - 1);
+    const int32_t my_cs = A.con_seg[jl], my_cp = A.con_bp[jl];  // record * 8 + slot, bpos offset
+    int32_t cs[kBatch], cp[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      cs[j] = __builtin_amdgcn_readlane(my_cs, j);
+      cp[j] = __builtin_amdgcn_readlane(my_cp, j);
+    }
     T val0[kBatch], val1[kBatch];
-    int d0[kBatch], d1[kBatch];
+    int16_t p0[kBatch], p1[kBatch];
     double fv[kBatch];
 #pragma unroll
     for (int j = 0; j < kBatch; ++j) {
-      val0[j] = val1[j] = T(0);
-      d0[j] = d1[j] = 0;
-      fv[j] = 0.0;
-      if (j >= nb) continue;
-      const int32_t cs = A.con_seg[cb + j];   // segment * 8 + slot
-      const int16_t* bp = A.bpos + A.con_bp[cb + j];
-      const T* src = segK + int64_t(cs >> 3) * 576 + (cs & 7) * 72;  // slot a's 72 values
-      if (wantK) {
+      const int64_t rec = cs[j] >> 3;
+      const int slot = cs[j] & 7;
+      if (WANTK) {
+        const T* src = segK + rec * 576 + slot * 72;  // slot a's 72 values
+        const int16_t* bp = A.bpos + cp[j];
         val0[j] = src[v0];
-        d0[j] = r0 * 3 * deg + 3 * bp[b0] + k0;
-        if (has1) {
-          val1[j] = src[v1];
-          d1[j] = r1 * 3 * deg + 3 * bp[b1] + k1;
-        }
+        val1[j] = src[v1];
+        p0[j] = bp[b0];
+        p1[j] = bp[b1];
       }
-      if (lane < 3) fv[j] = A.segF[int64_t(cs >> 3) * 24 + 3 * (cs & 7) + lane];
+      fv[j] = A.segF[rec * 24 + 3 * slot + fl];
     }
     // accumulate in contribution order; the 72 destinations of one contribution are distinct
     // and a single wavefront executes its LDS operations in program order
 #pragma unroll
     for (int j = 0; j < kBatch; ++j) {
       if (j >= nb) break;
-      if (wantK) {
-        acc[d0[j]] += val0[j];
-        if (has1) acc[d1[j]] += val1[j];
+      if (WANTK) {
+        acc[r0 * 3 * deg + 3 * p0[j] + k0] += val0[j];
+        if (has1) acc[r1 * 3 * deg + 3 * p1[j] + k1] += val1[j];
       }
       fsum += fv[j];
     }
   }
   __syncthreads();
-  if (wantK) {
+  if (WANTK) {
     T* Kout = reinterpret_cast<T*>(A.K);
     for (int j = lane; j < len; j += 64) Kout[base + j] = acc[j];
   }
   if (lane < 3) A.f[3 * nd + lane] = fsum;
+}
+
+template <typename T>
+static void launch_gather(const mpm_mesh* m, hipStream_t st, const AsmArgs& A) {
+  if (!m->n_node) return;
+  const dim3 grid(unsigned(m->n_node));
+  if (A.K)
+    hipLaunchKernelGGL((k_gather<T, true>), grid, dim3(64), size_t(9) * m->max_deg * sizeof(T), st, A, m->n_node);
+  else
+    hipLaunchKernelGGL((k_gather<T, false>), grid, dim3(64), 0, st, A, m->n_node);
 }
 
 // ------------------------------------------------------------------ general path
@@ -738,13 +756,22 @@ __global__ __launch_bounds__(256) void k_norm_final(const double* __restrict__ p
 template <typename T, int NS>
 __device__ __forceinline__ void adjoint_point(const AsmArgs& A, int64_t i, int ns, const int32_t* nd, const T (*dS)[3]) {
   const int64_t n = A.n;
+  // H = sum_v u_v (x) dS_v and Gp = sum_v lambda_v (x) dS_v together (G = Gp dF^-1 below),
+  // so that the basis gradients are dead before the material update
   T H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  T Gp[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
 #pragma unroll
   for (int v = 0; v < NS; ++v) {
     if (v >= ns) break;
     const double* uv = A.u + 3 * int64_t(nd[v]);
-    for (int r = 0; r < 3; ++r)
-      for (int q = 0; q < 3; ++q) H[r][q] += T(uv[r]) * dS[v][q];
+    const double* lv = A.lam + 3 * int64_t(nd[v]);
+    for (int r = 0; r < 3; ++r) {
+      const T ur = T(uv[r]), lr = T(lv[r]);
+      for (int q = 0; q < 3; ++q) {
+        H[r][q] += ur * dS[v][q];
+        Gp[r][q] += lr * dS[v][q];
+      }
+    }
   }
   T F[3][3], Fi[3][3];
   for (int r = 0; r < 3; ++r)
@@ -768,16 +795,9 @@ __device__ __forceinline__ void adjoint_point(const AsmArgs& A, int64_t i, int n
     raise(A.err, st, i);
     return;
   }
-  T Gm[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-#pragma unroll
-  for (int v = 0; v < NS; ++v) {
-    if (v >= ns) break;
-    T gv[3];
-    for (int q = 0; q < 3; ++q) gv[q] = Fi[0][q] * dS[v][0] + Fi[1][q] * dS[v][1] + Fi[2][q] * dS[v][2];
-    const double* lv = A.lam + 3 * int64_t(nd[v]);
-    for (int r = 0; r < 3; ++r)
-      for (int q = 0; q < 3; ++q) Gm[r][q] += T(lv[r]) * gv[q];
-  }
+  T Gm[3][3];  // G = sum_v lambda_v (x) grad_x S_v, grad_x S_v = dF^-T dS_v
+  for (int r = 0; r < 3; ++r)
+    for (int q = 0; q < 3; ++q) Gm[r][q] = Gp[r][0] * Fi[0][q] + Gp[r][1] * Fi[1][q] + Gp[r][2] * Fi[2][q];
   double Ga[3], tauG = 0;
   for (int a = 0; a < 3; ++a) {
     T v = 0;
@@ -898,9 +918,7 @@ extern "C" int32_t mpm_external_force(const mpm_mesh_t* m, const mpm_state_t* s,
     launch_rec_reduce<double>(m, st, false);
   }
   // every f_ext entry is written by the gather (zero where no point contributes)
-  if (m->n_node)
-    hipLaunchKernelGGL(k_gather<double>, dim3(unsigned(m->n_node)), dim3(64), size_t(9) * m->max_deg * 8, st, A,
-                       m->n_node);
+  launch_gather<double>(m, st, A);
   if (m->n_straddle)
     hipLaunchKernelGGL(k_external_force_general, dim3((m->n_straddle + 63) / 64), dim3(64), 0, st, A);
   MPM_HIP(hipGetLastError());
@@ -939,13 +957,8 @@ extern "C" int32_t mpm_assemble(const mpm_mesh_t* m, const mpm_state_t* s, const
     else launch_rec_reduce<float>(m, st, K_vals != nullptr);
   }
   // f_int and every CSR value are written by the gather (zero where no point contributes)
-  if (m->n_node) {
-    const dim3 grid(unsigned(m->n_node));
-    if (precision == MPM_F64)
-      hipLaunchKernelGGL(k_gather<double>, grid, dim3(64), size_t(9) * m->max_deg * 8, st, A, m->n_node);
-    else
-      hipLaunchKernelGGL(k_gather<float>, grid, dim3(64), size_t(9) * m->max_deg * 4, st, A, m->n_node);
-  }
+  if (precision == MPM_F64) launch_gather<double>(m, st, A);
+  else launch_gather<float>(m, st, A);
   if (timed) MPM_HIP(hipEventRecord(mm->ev[4], st));
   if (m->n_straddle) {
     const dim3 grid(unsigned((m->n_straddle + 63) / 64));

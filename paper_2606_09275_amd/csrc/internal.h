@@ -42,8 +42,6 @@ __host__ __device__ inline uint64_t morton(uint64_t x, uint64_t y, uint64_t z) {
   return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
 }
 
-constexpr int kSubBits = 42;       // bits of the within-leaf sub-key in a point sort key
-constexpr int kSubRes = 16;        // sub-key resolution: h_min / 16
 constexpr int kMaxPointLeaves = 8; // leaves a point domain may overlap (one boundary per axis)
 
 // per-leaf constraint code: bits 0..7 hanging vertices, bits 8..10 child index in the parent
@@ -71,7 +69,6 @@ struct mpm_mesh {
   int64_t n_leaf = 0, n_node = 0, n_hang = 0, n_point = 0, nnz = 0, n_straddle = 0, n_active_rows = 0;
   int32_t max_support = 0;
   int leaf_bits = 1;            // bits needed for a leaf rank
-  int sub_bits = 0;             // bits of a point's position key inside its leaf
   int32_t* d_cellmap = nullptr; // nx*ny*nz leaf ranks of the finest cells (x fastest), if not too large
   // device arrays (owned)
   int32_t* d_leaf = nullptr;        // n_leaf x 4
@@ -116,8 +113,12 @@ struct mpm_mesh {
   mpm::DevErr* h_err = nullptr;     // pinned host copy of the error word
   hipEvent_t err_ev = nullptr;      // marks the error-word copy (polled, no blocking sync)
   double* d_partial = nullptr;      // residual partial sums
-  void* d_scratch = nullptr;        // radix sort scratch
+  // work buffers of the point sort and of the state permutation, kept between calls (grown
+  // on demand) so that the per-step calls allocate nothing
+  void* d_scratch = nullptr;        // radix sort keys, values, per-tile counts
   size_t scratch_bytes = 0;
+  void* d_stage = nullptr;          // record-major staging copy of permuted arrays
+  size_t stage_bytes = 0;
   // kernel timing (measurement)
   bool timing = false;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};

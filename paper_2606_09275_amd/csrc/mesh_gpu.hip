@@ -26,29 +26,21 @@ int32_t hip_fail(hipError_t e, const char* what) {
 int32_t build_tree(const mpm_refine_t& c, HostTree& T, int lat_out[3], double* hmin_out);
 
 // ------------------------------------------------------------------ point keys
-// key = leaf rank << sub_bits | Morton code of the point's h_min/16 sub-cell, masked to the
-// low sub_bits bits. A leaf is an aligned Morton block of sub-cells, so inside one leaf the
-// masked code orders points exactly as the full code does; value = original index.
-__global__ void k_point_keys(const double* __restrict__ x, int64_t n, LeafGeo G, int sub_bits,
-                             uint64_t* __restrict__ keys, uint32_t* __restrict__ idx, DevErr* err) {
-#pragma clang fp contract(off)
+// key = rank of the leaf containing the point's centre, value = original index; a stable
+// sort by key gives the point order (leaf, original index).
+__global__ void k_point_keys(const double* __restrict__ x, int64_t n, LeafGeo G, uint32_t* __restrict__ keys,
+                             uint32_t* __restrict__ idx, DevErr* err) {
   const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= n) return;
-  const double hsub = G.hmin / double(kSubRes);
-  uint64_t sc[3];
   double xp[3];
-  bool bad = false, big = false;
+  bool bad = false;
   for (int a = 0; a < 3; ++a) {
     xp[a] = x[a * n + p];
     bad |= !isfinite(xp[a]);
-    const double t = floor((xp[a] - G.lo[a]) / hsub);
-    const double tc = t < 0.0 ? 0.0 : t;
-    big |= tc >= double(1 << 14);
-    sc[a] = bad || big ? 0 : uint64_t(tc);
   }
   idx[p] = uint32_t(p);
-  if (bad || big) {
-    if (atomicCAS(&err->code, 0, bad ? MPM_ENONFINITE : MPM_ESTENCIL) == 0) err->index = p;
+  if (bad) {
+    if (atomicCAS(&err->code, 0, MPM_ENONFINITE) == 0) err->index = p;
     keys[p] = 0;
     return;
   }
@@ -57,8 +49,7 @@ __global__ void k_point_keys(const double* __restrict__ x, int64_t n, LeafGeo G,
     if (atomicCAS(&err->code, 0, MPM_ETREE) == 0) err->index = p;
     e = 0;
   }
-  const uint64_t mask = (uint64_t(1) << sub_bits) - 1;
-  keys[p] = (uint64_t(e) << sub_bits) | (morton(sc[0], sc[1], sc[2]) & mask);
+  keys[p] = uint32_t(e);
 }
 
 // leaf rank of every finest lattice cell: one workgroup per leaf fills its block
@@ -75,14 +66,14 @@ __global__ __launch_bounds__(256) void k_fill_cellmap(const int32_t* __restrict_
 }
 
 // ------------------------------------------------------------------ stable LSD radix sort
-// 8-bit digits; 64-bit keys with 32-bit values. Per pass: per-tile digit counts, one scan
+// 8-bit digits; 32-bit keys with 32-bit values. Per pass: per-tile digit counts, one scan
 // per digit over the tiles, then a scatter that ranks equal digits inside each wavefront
 // with ballots (stable: tiles, wavefronts and lanes keep their input order).
 constexpr int kRsThreads = 256;
 constexpr int kRsRounds = 16;
 constexpr int kRsTile = kRsThreads * kRsRounds;
 
-__global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t* __restrict__ keys, int64_t n, int shift,
+__global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
                                                         uint32_t* __restrict__ hist) {
   __shared__ uint32_t h[256];
   h[threadIdx.x] = 0;
@@ -120,8 +111,8 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scan_digit(uint32_t* __restri
   if (threadIdx.x == 0) tot[blockIdx.x] = carry;
 }
 
-__global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t* __restrict__ kin,
-                                                           const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
+__global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* __restrict__ kin,
+                                                           const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
                                                            uint32_t* __restrict__ vout, int64_t n, int shift,
                                                            const uint32_t* __restrict__ hist,
                                                            const uint32_t* __restrict__ tot) {
@@ -140,12 +131,12 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t* __res
   run[tid] = dbase[tid] + hist[int64_t(tid) * gridDim.x + blockIdx.x];
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t base = int64_t(blockIdx.x) * kRsTile;
-  uint64_t kk[kRsRounds];  // the whole tile is loaded up front: one memory latency per tile
+  uint32_t kk[kRsRounds];  // the whole tile is loaded up front: one memory latency per tile
   uint32_t vv[kRsRounds];
 #pragma unroll
   for (int r = 0; r < kRsRounds; ++r) {
     const int64_t j = base + int64_t(r) * kRsThreads + tid;
-    kk[r] = j < n ? kin[j] : 0ull;
+    kk[r] = j < n ? kin[j] : 0u;
     vv[r] = j < n ? vin[j] : 0u;
   }
 #pragma unroll
@@ -153,7 +144,7 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t* __res
     for (int i = tid; i < (kRsThreads / 64) * 256; i += kRsThreads) (&wcnt[0][0])[i] = 0u;
     const int64_t j = base + int64_t(r) * kRsThreads + tid;
     const bool valid = j < n;
-    const uint64_t k = kk[r];
+    const uint32_t k = kk[r];
     const uint32_t v = vv[r];
     const uint32_t d = uint32_t(k >> shift) & 255u;
     uint64_t peers = __ballot(valid);
@@ -181,9 +172,9 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t* __res
 
 // sorts (keys, vals) by the low `bits` bits of keys; the result ends in whichever of the
 // two buffers the last pass wrote, returned through *kres / *vres
-static int32_t radix_sort(uint64_t* keys, uint32_t* vals, int64_t n, int bits, uint64_t* ktmp, uint32_t* vtmp,
-                          uint32_t* hist, uint32_t* tot, hipStream_t st, uint64_t** kres, uint32_t** vres) {
-  uint64_t *ka = keys, *kb = ktmp;
+static int32_t radix_sort(uint32_t* keys, uint32_t* vals, int64_t n, int bits, uint32_t* ktmp, uint32_t* vtmp,
+                          uint32_t* hist, uint32_t* tot, hipStream_t st, uint32_t** kres, uint32_t** vres) {
+  uint32_t *ka = keys, *kb = ktmp;
   uint32_t *va = vals, *vb = vtmp;
   if (n > 1) {
     const int nblk = int((n + kRsTile - 1) / kRsTile);
@@ -203,11 +194,11 @@ static int32_t radix_sort(uint64_t* keys, uint32_t* vals, int64_t n, int bits, u
   return MPM_OK;
 }
 
-__global__ void k_unpack_keys(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t n,
-                              int sub_bits, int32_t* __restrict__ leaf, int64_t* __restrict__ perm) {
+__global__ void k_unpack_keys(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals, int64_t n,
+                              int32_t* __restrict__ leaf, int64_t* __restrict__ perm) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) {
-    leaf[i] = int32_t(keys[i] >> sub_bits);
+    leaf[i] = int32_t(keys[i]);
     perm[i] = int64_t(vals[i]);
   }
 }
@@ -347,39 +338,50 @@ int32_t read_error(mpm_mesh* m, hipStream_t st, const char* what) {
   return MPM_OK;
 }
 
+// Grows a work buffer of the mesh to at least `bytes` (the old contents are dropped). The
+// stream is drained first: work already queued may still read the old buffer.
+static int32_t ensure_buffer(void** buf, size_t* have, size_t bytes, hipStream_t st, const char* what) {
+  if (*have >= bytes && *buf) return MPM_OK;
+  MPM_HIP(hipStreamSynchronize(st));
+  if (*buf) MPM_HIP(hipFree(*buf));
+  *buf = nullptr;
+  *have = 0;
+  const hipError_t e = hipMalloc(buf, bytes);
+  if (e != hipSuccess) {
+    *buf = nullptr;
+    return hip_fail(e, what);
+  }
+  *have = bytes;
+  return MPM_OK;
+}
+
 // sort points (device x [3][n]) into perm / leaf with the mesh's leaves
-int32_t sort_points(const mpm_mesh* m, const double* dx, int64_t n, int64_t* perm, int32_t* leaf, hipStream_t st) {
+int32_t sort_points(const mpm_mesh* mc, const double* dx, int64_t n, int64_t* perm, int32_t* leaf, hipStream_t st) {
   if (n == 0) return MPM_OK;
   if (n > int64_t(UINT32_MAX)) {
     set_error(MPM_EARG, "point sort: more than 2^32 - 1 points");
     return MPM_EARG;
   }
-  const int bits = m->sub_bits + m->leaf_bits;
-  uint64_t *keys = nullptr, *ktmp = nullptr;
-  uint32_t *vals = nullptr, *vtmp = nullptr;
-  uint32_t *hist = nullptr, *tot = nullptr;
+  mpm_mesh* m = const_cast<mpm_mesh*>(mc);
+  const int bits = m->leaf_bits;
   const int nblk = int((n + kRsTile - 1) / kRsTile);
-  int32_t rc = MPM_OK;
-  auto fail = [&](hipError_t e, const char* w) { rc = hip_fail(e, w); };
-  hipError_t e;
-  if ((e = hipMallocAsync((void**)&keys, size_t(n) * 8, st)) != hipSuccess) fail(e, "alloc keys");
-  if (!rc && (e = hipMallocAsync((void**)&ktmp, size_t(n) * 8, st)) != hipSuccess) fail(e, "alloc keys");
-  if (!rc && (e = hipMallocAsync((void**)&vals, size_t(n) * 4, st)) != hipSuccess) fail(e, "alloc vals");
-  if (!rc && (e = hipMallocAsync((void**)&vtmp, size_t(n) * 4, st)) != hipSuccess) fail(e, "alloc vals");
-  if (!rc && (e = hipMallocAsync((void**)&hist, size_t(nblk) * 256 * 4, st)) != hipSuccess) fail(e, "alloc hist");
-  if (!rc && (e = hipMallocAsync((void**)&tot, 256 * 4, st)) != hipSuccess) fail(e, "alloc tot");
-  if (!rc) {
-    const LeafGeo G = make_geo(m);
-    hipLaunchKernelGGL(k_point_keys, dim3((n + 255) / 256), dim3(256), 0, st, dx, n, G, m->sub_bits, keys, vals,
-                       m->d_err);
-    uint64_t* ks = nullptr;
-    uint32_t* vs = nullptr;
-    rc = radix_sort(keys, vals, n, bits, ktmp, vtmp, hist, tot, st, &ks, &vs);
-    if (!rc)
-      hipLaunchKernelGGL(k_unpack_keys, dim3((n + 255) / 256), dim3(256), 0, st, ks, vs, n, m->sub_bits, leaf, perm);
-  }
-  for (void* p : {(void*)keys, (void*)ktmp, (void*)vals, (void*)vtmp, (void*)hist, (void*)tot})
-    if (p) (void)hipFreeAsync(p, st);
+  const size_t na = (size_t(n) * 4 + 255) / 256 * 256;  // one 32-bit array, 256-byte aligned
+  const size_t need = 4 * na + size_t(nblk) * 256 * 4 + 256 * 4;
+  int32_t rc = ensure_buffer(&m->d_scratch, &m->scratch_bytes, need, st, "point sort: work buffer");
+  if (rc) return rc;
+  char* w = static_cast<char*>(m->d_scratch);
+  uint32_t* keys = reinterpret_cast<uint32_t*>(w);
+  uint32_t* ktmp = reinterpret_cast<uint32_t*>(w + na);
+  uint32_t* vals = reinterpret_cast<uint32_t*>(w + 2 * na);
+  uint32_t* vtmp = reinterpret_cast<uint32_t*>(w + 3 * na);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(w + 4 * na);
+  uint32_t* tot = hist + size_t(nblk) * 256;
+  const LeafGeo G = make_geo(m);
+  hipLaunchKernelGGL(k_point_keys, dim3((n + 255) / 256), dim3(256), 0, st, dx, n, G, keys, vals, m->d_err);
+  uint32_t* ks = nullptr;
+  uint32_t* vs = nullptr;
+  rc = radix_sort(keys, vals, n, bits, ktmp, vtmp, hist, tot, st, &ks, &vs);
+  if (!rc) hipLaunchKernelGGL(k_unpack_keys, dim3((n + 255) / 256), dim3(256), 0, st, ks, vs, n, leaf, perm);
   if (!rc) MPM_HIP(hipGetLastError());
   return rc;
 }
@@ -413,7 +415,7 @@ extern "C" void mpm_mesh_free(mpm_mesh_t* m) {
                   m->d_hang_ijk, m->d_hang_sup, m->d_hang_w, m->d_hang_owner, m->d_perm, m->d_pleaf, m->d_pnleaf,
                   m->d_row_ptr, m->d_col, m->d_wave_seg, m->d_leaf_seg0, m->d_leaf_nseg, m->d_con_off, m->d_con_seg, m->d_con_bp, m->d_bpos,
                   m->d_segK, m->d_segF, m->d_red1, m->d_red2, m->d_strad, m->d_strad_leaf, m->d_err,
-                  m->d_partial, m->d_scratch, m->d_cellmap};
+                  m->d_partial, m->d_scratch, m->d_stage, m->d_cellmap};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (hipEvent_t e : m->ev)
@@ -446,11 +448,8 @@ extern "C" int32_t octree_build(const mpm_refine_t* crit, const double* x, const
   m->n_node = int64_t(T.node_ijk.size() / 3);
   m->n_hang = int64_t(T.hang_owner.size());
   while ((int64_t(1) << m->leaf_bits) < m->n_leaf + 1) ++m->leaf_bits;
-  int lmin = crit->lvl_max;
-  for (int64_t e = 0; e < m->n_leaf; ++e) lmin = std::min(lmin, int(T.leaf[4 * e + 3]));
-  m->sub_bits = 3 * (crit->lvl_max - lmin + 4);
-  if (m->sub_bits > kSubBits || m->sub_bits + m->leaf_bits > 64) {
-    set_error(MPM_ESTENCIL, "octree_build: too many leaves or levels for 64-bit point keys");
+  if (m->leaf_bits > 31) {
+    set_error(MPM_ESTENCIL, "octree_build: too many leaves for 32-bit point keys");
     mpm_mesh_free(m);
     return MPM_ESTENCIL;
   }
@@ -805,12 +804,13 @@ extern "C" int32_t mpm_permute(const mpm_mesh_t* m, const int64_t* perm, const d
   if (n == 0) return MPM_OK;
   hipStream_t st = (hipStream_t)stream;
   const int64_t* pm = perm ? perm : m->d_perm;
-  double* aos = nullptr;
-  if (ncomp >= 2 && ncomp <= kPermMaxComp && hipMallocAsync((void**)&aos, size_t(n) * ncomp * 8, st) == hipSuccess) {
+  mpm_mesh* mm = const_cast<mpm_mesh*>(m);
+  if (ncomp >= 2 && ncomp <= kPermMaxComp &&
+      ensure_buffer(&mm->d_stage, &mm->stage_bytes, size_t(n) * ncomp * 8, st, "mpm_permute: staging") == MPM_OK) {
+    double* aos = static_cast<double*>(mm->d_stage);
     hipLaunchKernelGGL(k_soa_to_aos, dim3((n + kPermTile - 1) / kPermTile), dim3(kPermTile), 0, st, src, aos, n,
                        ncomp);
     hipLaunchKernelGGL(k_aos_gather, dim3((n + 255) / 256), dim3(256), 0, st, pm, aos, dst, n, ncomp);
-    MPM_HIP(hipFreeAsync(aos, st));
   } else {
     (void)hipGetLastError();
     hipLaunchKernelGGL(k_permute, dim3((n + 255) / 256), dim3(256), 0, st, pm, src, dst, n, ncomp);

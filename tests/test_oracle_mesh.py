@@ -183,15 +183,13 @@ def test_point_order_and_csr_bruteforce(kind, jit):
     w = tiny_workload(kind)
     m, ps = setup(w, jitter=jit)
     lv = m.leaves()
-    # point order: (leaf containing the centre, Morton code at h_min/16, original index)
+    # point order: (leaf containing the centre, original index)
     keys = morton3_np(lv[:, 0], lv[:, 1], lv[:, 2])
     q = np.floor((ps.x - np.asarray(w.lo)[:, None]) / w.h_min).astype(np.int64)
     for a, d in enumerate(w.lattice_dims()):
         q[a] = np.clip(q[a], 0, d - 1)
     leaf = np.searchsorted(keys, morton3_np(q[0], q[1], q[2]), side="right") - 1
-    sub = np.floor((ps.x - np.asarray(w.lo)[:, None]) / (w.h_min / 16)).astype(np.int64)
-    subk = morton3_np(sub[0], sub[1], sub[2])
-    order = np.lexsort((np.arange(ps.n), subk, leaf))
+    order = np.lexsort((np.arange(ps.n), leaf))
     perm, pleaf, nleaf = m.perm()
     assert np.array_equal(pleaf, leaf)
     assert np.array_equal(perm, order)

@@ -111,6 +111,9 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scan_digit(uint32_t* __restri
   if (threadIdx.x == 0) tot[blockIdx.x] = carry;
 }
 
+// Ranks each element among equal digits of its tile (ballots per wavefront, counts per
+// wavefront in LDS), stages the tile in LDS in digit order, then writes it out: the elements
+// of one digit leave the tile as one contiguous run.
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* __restrict__ kin,
                                                            const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
                                                            uint32_t* __restrict__ vout, int64_t n, int shift,
@@ -119,7 +122,11 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* __res
   __shared__ uint32_t run[256];
   __shared__ uint32_t wcnt[kRsThreads / 64][256];
   __shared__ uint32_t dbase[256];
+  __shared__ uint32_t start[256];  // first output position of the tile's elements of digit d
+  __shared__ uint32_t lbase[256];  // first staging slot of digit d in the tile
+  __shared__ uint32_t lk[kRsTile], lv[kRsTile];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int64_t nblk = gridDim.x, blk = blockIdx.x;
   if (tid == 0) {
     uint32_t acc = 0;
     for (int d = 0; d < 256; ++d) {
@@ -128,9 +135,24 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* __res
     }
   }
   __syncthreads();
-  run[tid] = dbase[tid] + hist[int64_t(tid) * gridDim.x + blockIdx.x];
+  {
+    const uint32_t h0 = hist[int64_t(tid) * nblk + blk];
+    const uint32_t h1 = blk + 1 < nblk ? hist[int64_t(tid) * nblk + blk + 1] : tot[tid];
+    start[tid] = dbase[tid] + h0;
+    run[tid] = start[tid];
+    lbase[tid] = h1 - h0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t acc = 0;
+    for (int d = 0; d < 256; ++d) {
+      const uint32_t c = lbase[d];
+      lbase[d] = acc;
+      acc += c;
+    }
+  }
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int64_t base = int64_t(blockIdx.x) * kRsTile;
+  const int64_t base = blk * kRsTile;
   uint32_t kk[kRsRounds];  // the whole tile is loaded up front: one memory latency per tile
   uint32_t vv[kRsRounds];
 #pragma unroll
@@ -159,14 +181,24 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* __res
     if (valid) {
       uint32_t off = run[d] + rank;
       for (int w = 0; w < wave; ++w) off += wcnt[w][d];
-      kout[off] = k;
-      vout[off] = v;
+      const uint32_t slot = off - start[d] + lbase[d];
+      lk[slot] = k;
+      lv[slot] = v;
     }
     __syncthreads();
     uint32_t add = 0;
     for (int w = 0; w < kRsThreads / 64; ++w) add += wcnt[w][tid];
     run[tid] += add;
     __syncthreads();
+  }
+  const int64_t rem = n - base;
+  const int cnt = int(rem < kRsTile ? rem : kRsTile);
+  for (int i = tid; i < cnt; i += kRsThreads) {
+    const uint32_t k = lk[i];
+    const uint32_t d = (k >> shift) & 255u;
+    const uint32_t out = start[d] + (uint32_t(i) - lbase[d]);
+    kout[out] = k;
+    vout[out] = lv[i];
   }
 }
 

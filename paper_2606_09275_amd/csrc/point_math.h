@@ -63,39 +63,47 @@ __device__ __forceinline__ void slot_basis(const T xi[3], T inv_h, int32_t code,
     g1[v] = w[0][b0] * s1 * w[2][b2];
     g2[v] = w[0][b0] * w[1][b1] * s2;
   }
+  // Constraint map (Section 3.1, hanging node basis). A hanging vertex j of a child leaf
+  // (child index cc in its parent) lies at the midpoint of a parent edge or face; its value
+  // is the average of the 2^m parent corners of that edge or face, m = |j ^ cc|. Relative to
+  // cc (j' = j ^ cc) those corners are the slots k with k' a subset of j'. So
+  //   S[k] = [k not hanging] ph[k] + sum over hanging j with j' containing k' of ph[j] / 2^m_j,
+  // a sum over supersets taken axis by axis (three passes of eight fused adds).
   const int hm = code_hmask(code);
-  if (hm == 0) {
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      S[k] = ph[k] * wgt;
-      dS[k][0] = g0[k] * wgt;
-      dS[k][1] = g1[k] * wgt;
-      dS[k][2] = g2[k] * wgt;
-    }
-    return;
-  }
   const int cc = code_child(code);
+  T wj[8], nh[8];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    T s = 0, d0 = 0, d1 = 0, d2 = 0;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int M = (j ^ cc) & 7;
-      const int nm = (M & 1) + ((M >> 1) & 1) + ((M >> 2) & 1);
-      const bool hj = (hm >> j) & 1;
-      T c;
-      if (hj) c = (((j ^ k) & ~M & 7) == 0) ? (nm == 1 ? T(0.5) : T(0.25)) : T(0);
-      else c = (j == k) ? T(1) : T(0);
-      s += c * ph[j];
-      d0 += c * g0[j];
-      d1 += c * g1[j];
-      d2 += c * g2[j];
-    }
-    S[k] = s * wgt;
-    dS[k][0] = d0 * wgt;
-    dS[k][1] = d1 * wgt;
-    dS[k][2] = d2 * wgt;
+  for (int j = 0; j < 8; ++j) {
+    const bool hj = (hm >> j) & 1;
+    const int m = __builtin_popcount((j ^ cc) & 7);
+    wj[j] = hj ? (m == 1 ? T(0.5) : (m == 2 ? T(0.25) : T(0.125))) : T(0);
+    nh[j] = hj ? T(0) : T(1);
   }
+  T ax[3];  // 1 where slot k agrees with cc on the axis (it receives in that pass), else 0
+#pragma unroll
+  for (int a = 0; a < 3; ++a) ax[a] = ((cc >> a) & 1) ? T(1) : T(0);
+  auto constrain = [&](const T* q, T* out, int stride) {
+    T t[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) t[j] = wj[j] * q[j];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int bit = 1 << a;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        if (k & bit) continue;  // pair (k, k | bit): the member that agrees with cc receives
+        const T lo = t[k], hi = t[k | bit];
+        t[k] = lo + (T(1) - ax[a]) * hi;
+        t[k | bit] = hi + ax[a] * lo;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) out[k * stride] = (nh[k] * q[k] + t[k]) * wgt;
+  };
+  constrain(ph, S, 1);
+  constrain(g0, &dS[0][0], 3);
+  constrain(g1, &dS[0][1], 3);
+  constrain(g2, &dS[0][2], 3);
 }
 
 // one Jacobi rotation annihilating the (p,q) entry of the symmetric A (storage a[p][q]),

@@ -777,6 +777,9 @@ __device__ __forceinline__ void adjoint_point(const AsmArgs& A, int64_t i, int n
   for (int r = 0; r < 3; ++r)
     for (int q = 0; q < 3; ++q) F[r][q] = H[r][q] + (r == q ? T(1) : T(0));
   const T Jd = inv3(F, Fi);
+  T Gm[3][3];  // G = sum_v lambda_v (x) grad_x S_v, grad_x S_v = dF^-T dS_v
+  for (int r = 0; r < 3; ++r)
+    for (int q = 0; q < 3; ++q) Gm[r][q] = Gp[r][0] * Fi[0][q] + Gp[r][1] * Fi[1][q] + Gp[r][2] * Fi[2][q];
   const double Jn = A.s.Jn[i];
   if (!isfinite(double(Jd)) || !isfinite(Jn)) {
     raise(A.err, MPM_ENONFINITE, i);
@@ -795,9 +798,6 @@ __device__ __forceinline__ void adjoint_point(const AsmArgs& A, int64_t i, int n
     raise(A.err, st, i);
     return;
   }
-  T Gm[3][3];  // G = sum_v lambda_v (x) grad_x S_v, grad_x S_v = dF^-T dS_v
-  for (int r = 0; r < 3; ++r)
-    for (int q = 0; q < 3; ++q) Gm[r][q] = Gp[r][0] * Fi[0][q] + Gp[r][1] * Fi[1][q] + Gp[r][2] * Fi[2][q];
   double Ga[3], tauG = 0;
   for (int a = 0; a < 3; ++a) {
     T v = 0;

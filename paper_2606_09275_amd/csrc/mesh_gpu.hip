@@ -1,6 +1,7 @@
 // Mesh construction entry points: octree (host), point keys + LSD radix sort + leaf search
 // and overlap classification (device), CSR pattern and per-element slot map (host).
 #include <algorithm>
+#include <utility>
 #include <cstring>
 #include <mutex>
 
@@ -289,37 +290,77 @@ __global__ void k_permute(const int64_t* __restrict__ perm, const double* __rest
 }
 
 // A random permutation of a [ncomp][n] array touches one cache line per component and
-// point; staging an AoS copy makes each point's record one contiguous read. Step 1: tiled
-// SoA -> AoS transpose through LDS (coalesced on both sides).
+// point; staging a record-major copy makes each point's record one contiguous read. Both
+// steps are instantiated per component count so that all loads of a thread are issued
+// before the first wait.
+// Step 1: tiled [ncomp][n] -> [n][ncomp] transpose through LDS (coalesced on both sides).
 constexpr int kPermTile = 128, kPermMaxComp = 32;
+template <int NC>
 __global__ __launch_bounds__(kPermTile) void k_soa_to_aos(const double* __restrict__ src, double* __restrict__ aos,
-                                                          int64_t n, int ncomp) {
-  __shared__ double tile[kPermMaxComp * kPermTile];
+                                                          int64_t n) {
+  __shared__ double tile[NC * kPermTile];
   const int64_t p0 = int64_t(blockIdx.x) * kPermTile;
   const int t = threadIdx.x;
   const int cnt = int(n - p0 < kPermTile ? n - p0 : kPermTile);
-  for (int c = 0; c < ncomp; ++c)
-    if (t < cnt) tile[t * ncomp + c] = src[c * n + p0 + t];
+  if (t < cnt) {
+    double v[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) v[c] = src[c * n + p0 + t];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) tile[t * NC + c] = v[c];
+  }
   __syncthreads();
-  double* out = aos + p0 * ncomp;
-  for (int j = t; j < cnt * ncomp; j += kPermTile) out[j] = tile[j];
+  double* out = aos + p0 * NC;
+  if (cnt == kPermTile) {
+    double v[NC];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) v[q] = tile[q * kPermTile + t];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) out[q * kPermTile + t] = v[q];
+  } else {
+    for (int j = t; j < cnt * NC; j += kPermTile) out[j] = tile[j];
+  }
 }
 // Step 2: gather one record per sorted position, write component rows (coalesced).
+template <int NC>
 __global__ __launch_bounds__(256) void k_aos_gather(const int64_t* __restrict__ perm, const double* __restrict__ aos,
-                                                    double* __restrict__ dst, int64_t n, int ncomp) {
+                                                    double* __restrict__ dst, int64_t n) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const double* r = aos + perm[i] * ncomp;
-  if ((ncomp & 1) == 0) {  // records start on 16-byte boundaries: 16-byte loads
+  const double* r = aos + perm[i] * NC;
+  if constexpr (NC % 2 == 0) {  // records start on 16-byte boundaries: 16-byte loads
     const double2* r2 = reinterpret_cast<const double2*>(r);
-    for (int c = 0; c < ncomp / 2; ++c) {
-      const double2 v = r2[c];
-      dst[(2 * c) * n + i] = v.x;
-      dst[(2 * c + 1) * n + i] = v.y;
+    double2 v[NC / 2];
+#pragma unroll
+    for (int c = 0; c < NC / 2; ++c) v[c] = r2[c];
+#pragma unroll
+    for (int c = 0; c < NC / 2; ++c) {
+      dst[(2 * c) * n + i] = v[c].x;
+      dst[(2 * c + 1) * n + i] = v[c].y;
     }
   } else {
-    for (int c = 0; c < ncomp; ++c) dst[c * n + i] = r[c];
+    double v[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) v[c] = r[c];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) dst[c * n + i] = v[c];
   }
+}
+
+template <int NC>
+static void launch_permute(const int64_t* pm, const double* src, double* aos, double* dst, int64_t n,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_soa_to_aos<NC>, dim3(unsigned((n + kPermTile - 1) / kPermTile)), dim3(kPermTile), 0, st, src,
+                     aos, n);
+  hipLaunchKernelGGL(k_aos_gather<NC>, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, pm, aos, dst, n);
+}
+
+template <int... NC>
+static bool dispatch_permute(int ncomp, const int64_t* pm, const double* src, double* aos, double* dst, int64_t n,
+                             hipStream_t st, std::integer_sequence<int, NC...>) {
+  bool done = false;
+  ((ncomp == NC + 2 ? (launch_permute<NC + 2>(pm, src, aos, dst, n, st), done = true) : false), ...);
+  return done;
 }
 
 LeafGeo make_geo(const mpm_mesh* m) {
@@ -839,10 +880,8 @@ extern "C" int32_t mpm_permute(const mpm_mesh_t* m, const int64_t* perm, const d
   mpm_mesh* mm = const_cast<mpm_mesh*>(m);
   if (ncomp >= 2 && ncomp <= kPermMaxComp &&
       ensure_buffer(&mm->d_stage, &mm->stage_bytes, size_t(n) * ncomp * 8, st, "mpm_permute: staging") == MPM_OK) {
-    double* aos = static_cast<double*>(mm->d_stage);
-    hipLaunchKernelGGL(k_soa_to_aos, dim3((n + kPermTile - 1) / kPermTile), dim3(kPermTile), 0, st, src, aos, n,
-                       ncomp);
-    hipLaunchKernelGGL(k_aos_gather, dim3((n + 255) / 256), dim3(256), 0, st, pm, aos, dst, n, ncomp);
+    dispatch_permute(ncomp, pm, src, static_cast<double*>(mm->d_stage), dst, n, st,
+                     std::make_integer_sequence<int, kPermMaxComp - 1>{});
   } else {
     (void)hipGetLastError();
     hipLaunchKernelGGL(k_permute, dim3((n + 255) / 256), dim3(256), 0, st, pm, src, dst, n, ncomp);

@@ -86,6 +86,11 @@ typedef struct {
 int32_t orc_assemble(const orc_mesh* m, const orc_state* s, const double* u, double* f_int, double* K,
                      double* sigma6, double* Fnew9, double* be6, uint8_t* plastic, int64_t* bad_index);
 int32_t orc_external_force(const orc_mesh* m, const orc_state* s, double* f_ext);
+/* Newmark (gamma = 1, beta = 1/2) inertia term: f_iner over 3*n_indep DOFs, (2/dt^2) x the
+ * consistent mass added into K (CSR pattern; may be NULL), point acceleration and updated
+ * velocity [3][n] (may be NULL); vel = point velocities at the start of the step [3][n]. */
+int32_t orc_inertia(const orc_mesh* m, const orc_state* s, const double* u, const double* vel, double dt,
+                    double* f_iner, double* K, double* a_new, double* v_new, int64_t* bad_index);
 /* r = f_int - f_ext with dirichlet DOFs zeroed; returns ||r||_2 in *rnorm */
 void orc_residual(int64_t ndof, const double* f_int, const double* f_ext, const uint8_t* dirichlet,
                   double* r, double* rnorm);

@@ -72,6 +72,8 @@ def lib():
         L.orc_assemble.argtypes = [vp, C.POINTER(_State), vp, vp, vp, vp, vp, vp, vp, i64p]
         L.orc_external_force.restype = C.c_int32
         L.orc_external_force.argtypes = [vp, C.POINTER(_State), vp]
+        L.orc_inertia.restype = C.c_int32
+        L.orc_inertia.argtypes = [vp, C.POINTER(_State), vp, vp, C.c_double, vp, vp, vp, vp, i64p]
         L.orc_residual.argtypes = [C.c_int64, vp, vp, vp, vp, vp]
         L.orc_adjoint.restype = C.c_int32
         L.orc_adjoint.argtypes = [vp, C.POINTER(_State), vp, vp, vp, vp, vp, vp, i64p]
@@ -225,6 +227,25 @@ class OracleMesh:
         if code != 0:
             raise OracleError(code)
         return f
+
+    def inertia(self, s: dict, u: np.ndarray, vel: np.ndarray, dt: float, want_K: bool = True) -> dict:
+        """Newmark (gamma = 1, beta = 1/2) inertia force, (2/dt^2) x consistent mass on the CSR
+        pattern, point accelerations and updated velocities ([3][n], original order)."""
+        c = self.counts()
+        n = self.n_point
+        st = self._state(s)
+        u = np.ascontiguousarray(u, dtype=_f64)
+        vel = np.ascontiguousarray(vel, dtype=_f64)
+        f = np.zeros(3 * c["n_node"], _f64)
+        K = np.zeros(c["nnz"], _f64) if want_K else None
+        a = np.zeros((3, n), _f64)
+        v = np.zeros((3, n), _f64)
+        bad = C.c_int64(-1)
+        code = lib().orc_inertia(self.h, C.byref(st), _p(u), _p(vel), C.c_double(dt), _p(f), _p(K), _p(a), _p(v),
+                                 C.byref(bad))
+        if code != 0:
+            raise OracleError(code, bad.value)
+        return dict(f_iner=f, K_mass=K, a=a, v=v)
 
     def adjoint(self, s: dict, u: np.ndarray, lam: np.ndarray) -> dict:
         n = self.n_point

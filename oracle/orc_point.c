@@ -364,6 +364,49 @@ int32_t orc_external_force(const orc_mesh* m, const orc_state* s, double* f_ext)
   return ORC_OK;
 }
 
+/* Inertia term of the weak form (Section 2.1, eq. MPMweak: sum_p S_vp m_p a_p) with Newmark's
+ * method at gamma = 1, beta = 1/2 (Section 2.4). Over a step with nodal displacement u the
+ * point displacement is du_p = sum_v S_vp u_v (basis frozen at the start of the step); the
+ * Newmark relations du = dt v_n + dt^2 ((1/2 - beta) a_n + beta a_{n+1}) and
+ * v_{n+1} = v_n + dt ((1 - gamma) a_n + gamma a_{n+1}) give, at these parameters,
+ *   a_p = 2 (du_p - dt v_p) / dt^2   and   v_p,new = v_p + dt a_p.
+ * f_iner,v = sum_p S_vp m_p a_p; its derivative with respect to u is (2/dt^2) M with the
+ * consistent mass M_vw = sum_p m_p S_vp S_wp (times the 3x3 identity), added into K when K is
+ * given. vel, a_new, v_new are [3][n] in original point order. */
+int32_t orc_inertia(const orc_mesh* m, const orc_state* s, const double* u, const double* vel, double dt,
+                    double* f_iner, double* K, double* a_new, double* v_new, int64_t* bad) {
+  *bad = -1;
+  int64_t n = m->np;
+  memset(f_iner, 0, (size_t)(3 * m->nindep) * sizeof(double));
+  static int32_t node[ORC_MAXS];
+  static double S[ORC_MAXS], dS[3 * ORC_MAXS];
+  const double c2 = 2.0 / (dt * dt);
+  for (int64_t p = 0; p < n; p++) {
+    double x[3] = {s->x[p], s->x[n + p], s->x[2 * n + p]}, l[3] = {s->l[p], s->l[n + p], s->l[2 * n + p]};
+    int ns = orc_point_basis(m, x, l, node, S, dS);
+    if (ns < 0) { *bad = p; return ns; }
+    double acc[3];
+    for (int i = 0; i < 3; i++) {
+      double du = 0;
+      for (int v = 0; v < ns; v++) du += S[v] * u[3 * node[v] + i];
+      acc[i] = c2 * (du - dt * vel[i * n + p]);
+      if (a_new) a_new[i * n + p] = acc[i];
+      if (v_new) v_new[i * n + p] = vel[i * n + p] + dt * acc[i];
+    }
+    for (int v = 0; v < ns; v++)
+      for (int i = 0; i < 3; i++) f_iner[3 * node[v] + i] += S[v] * s->mass[p] * acc[i];
+    if (!K) continue;
+    for (int va = 0; va < ns; va++)
+      for (int vb = 0; vb < ns; vb++)
+        for (int i = 0; i < 3; i++) {
+          int64_t pos = csr_find(m, 3 * (int64_t)node[va] + i, 3 * node[vb] + i);
+          if (pos < 0) { *bad = p; return ORC_ESTENCIL; }
+          K[pos] += c2 * s->mass[p] * S[va] * S[vb];
+        }
+  }
+  return ORC_OK;
+}
+
 void orc_residual(int64_t ndof, const double* f_int, const double* f_ext, const uint8_t* dir, double* r,
                   double* rnorm) {
   double acc = 0;

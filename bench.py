@@ -245,12 +245,42 @@ def main():
                                                          "adjoint_points_per_s", "assemble_kernel_ms",
                                                          "adjoint_kernel_ms")}
         out["fp32k"]["speedup_assembly_vs_fp64"] = results["f32k"]["assembly_points_per_s"] / R["assembly_points_per_s"]
+    if not args.only:
+        out["dynamic"] = dynamic_assembly(mesh, w, ps, views, u, f_ext, dirichlet, n)
     if "prev_x_s" in w.extra:
         out["protocol"] = tool_protocol(mesh, w, nodes, views, x_dev, perm_buf, leaf_buf, packed, sorted_buf,
                                         f_ext, dirichlet, lam)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, ps, st, nodes, args.cpu_sample)
     print(json.dumps(out), flush=True)
+
+
+def dynamic_assembly(mesh, w, ps, views, u, f_ext, dirichlet, n, reps=10, dt=1e-3):
+    """The Newmark (gamma = 1, beta = 1/2) dynamic assembly on the sorted state: mean ms of the
+    call and of its fused kernel, per precision (same u, point velocities N(0, 0.1^2))."""
+    import torch
+    import workloads as W
+    vel = torch.from_numpy(W.make_velocity(w, ps)).cuda()  # order does not matter for timing
+    res = {}
+    for prec in ("f64", "f32k"):
+        outs = {}
+        mesh.assemble_dynamic(views, u, vel, dt, prec, f_ext=f_ext, dirichlet=dirichlet, out=outs)
+        torch.cuda.synchronize()
+        mesh.kernel_timing(1)
+        mesh.kernel_timing(-1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            mesh.assemble_dynamic(views, u, vel, dt, prec, f_ext=f_ext, dirichlet=dirichlet, out=outs)
+        e1.record()
+        torch.cuda.synchronize()
+        kt = mesh.kernel_timing(0)
+        ms = e0.elapsed_time(e1) / reps
+        res[prec] = {"assembly_ms": ms, "assemble_kernel_ms": kt[0] / max(kt[1], 1),
+                     "gather_kernel_ms": kt[4] / max(kt[5], 1), "assembly_points_per_s": n / (ms * 1e-3)}
+    log(f"[bench] dynamic assembly: f64 {res['f64']['assembly_ms']:.3f} ms (kernel "
+        f"{res['f64']['assemble_kernel_ms']:.3f}), f32k {res['f32k']['assembly_ms']:.3f} ms")
+    return res
 
 
 def tool_protocol(mesh, w, nodes, views, x_dev, perm_buf, leaf_buf, packed, sorted_buf, f_ext, dirichlet, lam):

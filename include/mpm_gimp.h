@@ -180,6 +180,22 @@ int32_t mpm_assemble(const mpm_mesh_t* mesh, const mpm_state_t* s, const double*
                      const double* f_ext, const uint8_t* dirichlet, double* f_int, void* K_vals, double* sigma6,
                      double* r, double* rnorm, double* F_new, double* be_new, void* stream);
 
+/* Dynamic Newton-iteration assembly: mpm_assemble plus the inertia term of the weak form
+ * (Section 2.1, eq. MPMweak: sum_p S_vp m_p a_p) under Newmark's method with gamma = 1,
+ * beta = 1/2 (Section 2.4). With du_p = sum_v S_vp u_v (basis frozen at the start of the
+ * step) the point acceleration is a_p = 2 (du_p - dt v_n,p) / dt^2 and the updated velocity
+ * v_n,p + dt a_p; the inertia force adds sum_p S_vp m_p a_p to f_int and its derivative
+ * (2 / dt^2) M, M_vw = sum_p m_p S_vp S_wp (consistent mass, times the 3x3 identity), to K.
+ *   v_n: [3][n] device point velocities at the start of the step (sorted order, FP64);
+ *   dt > 0: step size; s->mass must be set.
+ *   f_int receives f_int + f_inertia; r = that - f_ext (Dirichlet DOFs zeroed);
+ *   a_new, v_new: [3][n] device, may be NULL. Other arguments and errors as mpm_assemble;
+ *   MPM_EARG also for dt <= 0 or non-finite, or a missing v_n or mass. */
+int32_t mpm_assemble_dynamic(const mpm_mesh_t* mesh, const mpm_state_t* s, const double* u, const double* v_n,
+                             double dt, int32_t precision, const double* f_ext, const uint8_t* dirichlet,
+                             double* f_int, void* K_vals, double* sigma6, double* r, double* rnorm, double* a_new,
+                             double* v_new, void* stream);
+
 /* Adjoint of the assembly for L = lambda . f_int(u) (lambda: device [n_dof]): per point
  * dL/dE, dL/dnu, dL/dsy, dL/dV_n (device [n] FP64 each, caller-owned). Gather only (no
  * atomics); the return map is recomputed, nothing is stored by the forward pass. */

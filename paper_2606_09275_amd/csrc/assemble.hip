@@ -4,6 +4,7 @@
 // values; a general kernel with atomics for domains overlapping several leaves; body force;
 // residual and its FP64 norm; the adjoint gather.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 
 #include "point_math.h"
@@ -42,6 +43,12 @@ struct AsmArgs {
   double* Fnew;
   double* be;
   double *dE, *dnu, *dsy, *dV;
+  // Newmark inertia (gamma = 1, beta = 1/2): point velocities at the start of the step [3][n]
+  // (null: quasi-static), step size, optional point accelerations / velocities out [3][n]
+  const double* vel;
+  double dt;
+  double* a_new;
+  double* v_new;
   DevErr* err;
 };
 
@@ -218,7 +225,9 @@ __device__ __forceinline__ void wave_segments(int32_t leaf, bool inr, int64_t n,
 }
 
 // Register budget: two wavefronts per SIMD in FP64 (256 registers), four in FP32 (128).
-template <typename T>
+// DYN adds the Newmark inertia term: f_v += S_v m_p a_p and (2 m_p / dt^2) S_a S_b on the
+// diagonal of every block.
+template <typename T, bool DYN>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 4)))
 void k_assemble_fast(AsmArgs A) {
   constexpr int kRound = Rounds<T>::kVals, kBPR = Rounds<T>::kBlocks, kFR = Rounds<T>::kForce;
@@ -250,6 +259,7 @@ void k_assemble_fast(AsmArgs A) {
   T c = 0;
   T F[3][3];
   int32_t nodes[8];
+  double acc[3] = {0.0, 0.0, 0.0}, mp = 0.0;  // inertia: point acceleration, mass
   if (act) {
     const int32_t code = A.cell_code[leaf];
     for (int v = 0; v < 8; ++v) nodes[v] = A.cell_nodes[8 * int64_t(leaf) + v];
@@ -262,6 +272,7 @@ void k_assemble_fast(AsmArgs A) {
     T H[3][3];
     for (int r = 0; r < 3; ++r)
       for (int q = 0; q < 3; ++q) H[r][q] = 0;
+    double du[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
       const double* uv = A.u + 3 * int64_t(nodes[v]);
@@ -271,6 +282,22 @@ void k_assemble_fast(AsmArgs A) {
         H[0][q] += u0 * dS[v][q];
         H[1][q] += u1 * dS[v][q];
         H[2][q] += u2 * dS[v][q];
+      }
+      if constexpr (DYN) {
+        du[0] += double(S[v]) * uv[0];
+        du[1] += double(S[v]) * uv[1];
+        du[2] += double(S[v]) * uv[2];
+      }
+    }
+    if constexpr (DYN) {
+      // Newmark, gamma = 1, beta = 1/2: a = 2 (du - dt v_n) / dt^2, v_new = v_n + dt a
+      const double c2 = 2.0 / (A.dt * A.dt);
+      mp = A.s.mass[i];
+      for (int r = 0; r < 3; ++r) {
+        const double vr = A.vel[r * n + i];
+        acc[r] = c2 * (du[r] - A.dt * vr);
+        if (A.a_new) A.a_new[r * n + i] = acc[r];
+        if (A.v_new) A.v_new[r * n + i] = vr + A.dt * acc[r];
       }
     }
     for (int r = 0; r < 3; ++r)
@@ -304,8 +331,10 @@ void k_assemble_fast(AsmArgs A) {
   }
   if (!act) {
     c = 0;
+    mp = 0.0;
     for (int v = 0; v < 8; ++v) {
       nodes[v] = 0;
+      S[v] = 0;
       for (int q = 0; q < 3; ++q) g[v][q] = 0;
     }
     for (int r = 0; r < 3; ++r)
@@ -329,7 +358,8 @@ void k_assemble_fast(AsmArgs A) {
 #pragma unroll
       for (int r = 0; r < 3; ++r)
         redd[3 * v + r - part * kFR][lane] =
-            double(c) * double(P.tau[r][0] * g[v][0] + P.tau[r][1] * g[v][1] + P.tau[r][2] * g[v][2]);
+            double(c) * double(P.tau[r][0] * g[v][0] + P.tau[r][1] * g[v][1] + P.tau[r][2] * g[v][2]) +
+            (DYN ? double(S[v]) * mp * acc[r] : 0.0);
     __syncthreads();
     round_sums<double, kFR>(redd, seg_start, nseg, [&](int sg, int v, double sum) {
       A.segF[(seg0 + sg) * 24 + part * kFR + v] = sum;
@@ -383,14 +413,19 @@ void k_assemble_fast(AsmArgs A) {
         X[k][2][k] -= tg2;
       }
     }
+    const T msb = DYN ? T(2.0 * mp / (A.dt * A.dt)) * S[b] : T(0);  // inertia: (2 m / dt^2) S_b
 #pragma unroll
     for (int a = 0; a <= b; ++a) {
       const int slotv = (blk % kBPR) * 9;
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
-          red[slotv + 3 * r + k][lane] = X[k][r][0] * g[a][0] + X[k][r][1] * g[a][1] + X[k][r][2] * g[a][2];
+        for (int k = 0; k < 3; ++k) {
+          T val = X[k][r][0] * g[a][0] + X[k][r][1] * g[a][1] + X[k][r][2] * g[a][2];
+          if constexpr (DYN)
+            if (r == k) val += msb * S[a];
+          red[slotv + 3 * r + k][lane] = val;
+        }
       if (blk % kBPR == kBPR - 1) {
         __syncthreads();
         const int rnd = blk / kBPR;
@@ -630,10 +665,24 @@ __global__ __launch_bounds__(64) void k_assemble_general(AsmArgs A) {
   T g[kMaxSup][3];
   for (int v = 0; v < ns; ++v)
     for (int q = 0; q < 3; ++q) g[v][q] = Fi[0][q] * dS[v][0] + Fi[1][q] * dS[v][1] + Fi[2][q] * dS[v][2];
+  double acc[3] = {0.0, 0.0, 0.0}, mp = 0.0;
+  if (A.vel) {  // Newmark inertia, gamma = 1, beta = 1/2
+    const double c2 = 2.0 / (A.dt * A.dt);
+    mp = A.s.mass[i];
+    for (int r = 0; r < 3; ++r) {
+      double du = 0.0;
+      for (int v = 0; v < ns; ++v) du += double(S[v]) * A.u[3 * int64_t(nd[v]) + r];
+      const double vr = A.vel[r * n + i];
+      acc[r] = c2 * (du - A.dt * vr);
+      if (A.a_new) A.a_new[r * n + i] = acc[r];
+      if (A.v_new) A.v_new[r * n + i] = vr + A.dt * acc[r];
+    }
+  }
   for (int v = 0; v < ns; ++v)
     for (int r = 0; r < 3; ++r)
       atomicAdd(A.f + 3 * int64_t(nd[v]) + r,
-                double(c) * double(P.tau[r][0] * g[v][0] + P.tau[r][1] * g[v][1] + P.tau[r][2] * g[v][2]));
+                double(c) * double(P.tau[r][0] * g[v][0] + P.tau[r][1] * g[v][1] + P.tau[r][2] * g[v][2]) +
+                    double(S[v]) * mp * acc[r]);
   if (!A.K) return;
   T* Kout = reinterpret_cast<T*>(A.K);
   for (int b = 0; b < ns; ++b) {
@@ -652,7 +701,9 @@ __global__ __launch_bounds__(64) void k_assemble_general(AsmArgs A) {
         }
         for (int k = 0; k < 3; ++k) {
           const T m = dt[k][r][0] * g[a][0] + dt[k][r][1] * g[a][1] + dt[k][r][2] * g[a][2] - tg[r] * g[a][k];
-          atomic_add_val<T>(Kout + p0 + k, c * m);
+          T val = c * m;
+          if (A.vel && r == k) val += T(2.0 * mp / (A.dt * A.dt)) * S[a] * S[b];
+          atomic_add_val<T>(Kout + p0 + k, val);
         }
       }
     }
@@ -925,6 +976,11 @@ extern "C" int32_t mpm_external_force(const mpm_mesh_t* m, const mpm_state_t* s,
   return read_error(const_cast<mpm_mesh*>(m), st, "mpm_external_force");
 }
 
+namespace mpm {
+static int32_t assemble_impl(const mpm_mesh_t* m, const AsmArgs& A, int32_t precision, const double* f_ext,
+                             const uint8_t* dirichlet, double* r, double* rnorm, hipStream_t st, const char* what);
+}
+
 extern "C" int32_t mpm_assemble(const mpm_mesh_t* m, const mpm_state_t* s, const double* u, int32_t precision,
                                 const double* f_ext, const uint8_t* dirichlet, double* f_int, void* K_vals,
                                 double* sigma6, double* r, double* rnorm, double* F_new, double* be_new,
@@ -934,7 +990,6 @@ extern "C" int32_t mpm_assemble(const mpm_mesh_t* m, const mpm_state_t* s, const
     set_error(MPM_EARG, "mpm_assemble: null argument, bad precision or F_new without F_n");
     return MPM_EARG;
   }
-  hipStream_t st = (hipStream_t)stream;
   AsmArgs A = make_args(m, s);
   A.u = u;
   A.f = f_int;
@@ -942,14 +997,48 @@ extern "C" int32_t mpm_assemble(const mpm_mesh_t* m, const mpm_state_t* s, const
   A.sigma = sigma6;
   A.Fnew = F_new;
   A.be = be_new;
+  return assemble_impl(m, A, precision, f_ext, dirichlet, r, rnorm, (hipStream_t)stream, "mpm_assemble");
+}
+
+extern "C" int32_t mpm_assemble_dynamic(const mpm_mesh_t* m, const mpm_state_t* s, const double* u,
+                                        const double* v_n, double dt, int32_t precision, const double* f_ext,
+                                        const uint8_t* dirichlet, double* f_int, void* K_vals, double* sigma6,
+                                        double* r, double* rnorm, double* a_new, double* v_new, void* stream) {
+  if (!m || !state_ok(s) || !s->mass || !u || !v_n || !f_int || !(dt > 0.0) || !std::isfinite(dt) ||
+      (precision != MPM_F64 && precision != MPM_F32K)) {
+    set_error(MPM_EARG, "mpm_assemble_dynamic: null argument, no mass, bad step size or bad precision");
+    return MPM_EARG;
+  }
+  AsmArgs A = make_args(m, s);
+  A.u = u;
+  A.f = f_int;
+  A.K = K_vals;
+  A.sigma = sigma6;
+  A.vel = v_n;
+  A.dt = dt;
+  A.a_new = a_new;
+  A.v_new = v_new;
+  return assemble_impl(m, A, precision, f_ext, dirichlet, r, rnorm, (hipStream_t)stream, "mpm_assemble_dynamic");
+}
+
+namespace mpm {
+static int32_t assemble_impl(const mpm_mesh_t* m, const AsmArgs& A, int32_t precision, const double* f_ext,
+                             const uint8_t* dirichlet, double* r, double* rnorm, hipStream_t st, const char* what) {
+  double* f_int = A.f;
+  void* K_vals = A.K;
   const int64_t n = m->n_point;
   mpm_mesh* mm = const_cast<mpm_mesh*>(m);
   const bool timed = mm->timing && n;
   if (timed) MPM_HIP(hipEventRecord(mm->ev[0], st));
   if (n) {
     const dim3 grid(unsigned((n + 63) / 64));
-    if (precision == MPM_F64) hipLaunchKernelGGL(k_assemble_fast<double>, grid, dim3(64), 0, st, A);
-    else hipLaunchKernelGGL(k_assemble_fast<float>, grid, dim3(64), 0, st, A);
+    if (A.vel) {
+      if (precision == MPM_F64) hipLaunchKernelGGL((k_assemble_fast<double, true>), grid, dim3(64), 0, st, A);
+      else hipLaunchKernelGGL((k_assemble_fast<float, true>), grid, dim3(64), 0, st, A);
+    } else {
+      if (precision == MPM_F64) hipLaunchKernelGGL((k_assemble_fast<double, false>), grid, dim3(64), 0, st, A);
+      else hipLaunchKernelGGL((k_assemble_fast<float, false>), grid, dim3(64), 0, st, A);
+    }
   }
   if (timed) MPM_HIP(hipEventRecord(mm->ev[1], st));
   if (n) {
@@ -973,7 +1062,7 @@ extern "C" int32_t mpm_assemble(const mpm_mesh_t* m, const mpm_state_t* s, const
     if (rnorm) hipLaunchKernelGGL(k_norm_final, dim3(1), dim3(256), 0, st, m->d_partial, nb, rnorm);
   }
   MPM_HIP(hipGetLastError());
-  const int32_t rc = read_error(mm, st, "mpm_assemble");
+  const int32_t rc = read_error(mm, st, what);
   if (timed) {
     float ms = 0, mg = 0;
     MPM_HIP(hipEventElapsedTime(&ms, mm->ev[0], mm->ev[1]));
@@ -985,6 +1074,7 @@ extern "C" int32_t mpm_assemble(const mpm_mesh_t* m, const mpm_state_t* s, const
   }
   return rc;
 }
+}  // namespace mpm
 
 extern "C" int32_t mpm_assemble_adjoint(const mpm_mesh_t* m, const mpm_state_t* s, const double* u,
                                         const double* lambda, int32_t precision, double* dE, double* dnu,

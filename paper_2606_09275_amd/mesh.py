@@ -186,6 +186,40 @@ class Mesh:
                                  _stream()))
         return o
 
+    def assemble_dynamic(self, s: dict, u: torch.Tensor, v_n: torch.Tensor, dt: float, precision="f64", f_ext=None,
+                         dirichlet=None, want_K=True, want_sigma=True, want_residual=True, want_kinematics=False,
+                         out: Optional[dict] = None) -> dict:
+        """mpm_assemble_dynamic: f_int (internal + Newmark inertia force), K (+ 2/dt^2 consistent
+        mass), sigma, residual; v_n [3][n] sorted-order point velocities; optional point
+        accelerations `a_new` and velocities `v_new` [3][n]."""
+        p = PRECISION.get(precision, precision)
+        i = self.info
+        n = i["n_point"]
+        o = {} if out is None else out
+        dev = "cuda"
+        if "f_int" not in o:
+            o["f_int"] = torch.empty(i["n_dof"], dtype=torch.float64, device=dev)
+        if want_K and "K" not in o:
+            o["K"] = torch.empty(i["nnz"], dtype=torch.float64 if p == MPM_F64 else torch.float32, device=dev)
+        if want_sigma and "sigma" not in o:
+            o["sigma"] = torch.empty((6, n), dtype=torch.float64, device=dev)
+        if want_residual:
+            o.setdefault("r", torch.empty(i["n_dof"], dtype=torch.float64, device=dev))
+            o.setdefault("rnorm", torch.empty(1, dtype=torch.float64, device=dev))
+        if want_kinematics:
+            o.setdefault("a_new", torch.empty((3, n), dtype=torch.float64, device=dev))
+            o.setdefault("v_new", torch.empty((3, n), dtype=torch.float64, device=dev))
+        st = self._state(s)
+        check(lib().mpm_assemble_dynamic(self.h, C.byref(st), _ptr(u), _ptr(v_n.contiguous()), float(dt), p,
+                                         _ptr(f_ext), _ptr(dirichlet), _ptr(o["f_int"]),
+                                         _ptr(o.get("K") if want_K else None),
+                                         _ptr(o.get("sigma") if want_sigma else None),
+                                         _ptr(o.get("r") if want_residual else None),
+                                         _ptr(o.get("rnorm") if want_residual else None),
+                                         _ptr(o.get("a_new") if want_kinematics else None),
+                                         _ptr(o.get("v_new") if want_kinematics else None), _stream()))
+        return o
+
     def adjoint(self, s: dict, u: torch.Tensor, lam: torch.Tensor, precision="f64", out: Optional[dict] = None):
         p = PRECISION.get(precision, precision)
         n = self.info["n_point"]

@@ -19,8 +19,7 @@ def _problem(kind, jit):
     w = tiny_workload(kind, E=1e4, nu=0.3, sy=math.inf)
     m, ps = setup(w, jitter=jit)
     s = W.make_state(w, ps)
-    rng = np.random.default_rng(5)
-    vel = rng.normal(0.0, 0.1, size=(3, ps.n))
+    vel = W.make_velocity(w, ps)
     u = W.make_u(w, m.nodes(), amp=1e-4)
     return w, m, ps, s, vel, u
 

@@ -7,5 +7,5 @@ refinement); both the CPU oracle and the HIP library consume what it produces.
 """
 from .configs import CONFIGS, Workload, get  # noqa: F401
 from .generate import (  # noqa: F401
-    PointSet, make_points, make_state, make_u, make_lambda, dirichlet_dofs, jitter_points,
+    PointSet, make_points, make_state, make_u, make_lambda, make_velocity, dirichlet_dofs, jitter_points,
 )

@@ -224,3 +224,9 @@ def make_lambda(w: Workload, node_ijk: np.ndarray) -> np.ndarray:
     lam = rng.normal(0.0, 1.0, size=3 * n)
     lam[dirichlet_dofs(node_ijk).astype(bool)] = 0.0
     return lam
+
+
+def make_velocity(w: Workload, ps: PointSet, std: float = 0.1, seed: int = 6) -> np.ndarray:
+    """Point velocities at the start of a step, [3][n], N(0, std^2) per component (seeded)."""
+    rng = np.random.default_rng([seed, w.seed_state])
+    return rng.normal(0.0, std, size=(3, ps.n))

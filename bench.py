@@ -247,6 +247,7 @@ def main():
         out["fp32k"]["speedup_assembly_vs_fp64"] = results["f32k"]["assembly_points_per_s"] / R["assembly_points_per_s"]
     if not args.only:
         out["dynamic"] = dynamic_assembly(mesh, w, ps, views, u, f_ext, dirichlet, n)
+        out["solve"] = newton_solve(mesh, views, u, f_ext, dirichlet, info)
     if "prev_x_s" in w.extra:
         out["protocol"] = tool_protocol(mesh, w, nodes, views, x_dev, perm_buf, leaf_buf, packed, sorted_buf,
                                         f_ext, dirichlet, lam)
@@ -280,6 +281,56 @@ def dynamic_assembly(mesh, w, ps, views, u, f_ext, dirichlet, n, reps=10, dt=1e-
                      "gather_kernel_ms": kt[4] / max(kt[5], 1), "assembly_points_per_s": n / (ms * 1e-3)}
     log(f"[bench] dynamic assembly: f64 {res['f64']['assembly_ms']:.3f} ms (kernel "
         f"{res['f64']['assemble_kernel_ms']:.3f}), f32k {res['f32k']['assembly_ms']:.3f} ms")
+    return res
+
+
+def newton_solve(mesh, views, u, f_ext, dirichlet, info, iters=100, spmv_reps=20):
+    """Linear solve of the first Newton step of a body-force load step (u = 0, elastic response
+    from an unstrained start, right-hand side f_ext) with Jacobi-preconditioned CG over the free
+    DOFs, on the same mesh and points (the tangent at the randomly strained plastic state of
+    this workload is not positive definite, which ends CG early): ms per CG iteration over a
+    fixed iteration count, iterations to a 1e-6 relative residual (at most 4000), and the SpMV
+    kernel alone against the HBM roofline (bytes: K values, one column index per entry of a
+    node's first row, x and y)."""
+    import torch
+    res = {}
+    # elastic response from an unstrained start (F_n = I): a positive definite tangent
+    bn0 = torch.zeros_like(views["bn"])
+    bn0[:3] = 1.0
+    el = dict(views, sy=torch.full_like(views["sy"], float("inf")), bn=bn0, Jn=torch.ones_like(views["Jn"]))
+    u0 = torch.zeros_like(u)  # first Newton iteration of a step: the load is the body force
+    for prec, tb in (("f64", 8), ("f32k", 4)):
+        outs = {}
+        mesh.assemble(el, u0, prec, f_ext=f_ext, dirichlet=dirichlet, out=outs)
+        K = outs["K"]
+        b = -outs["r"]
+        mesh.solve_cg(K, b, dirichlet, rtol=0.0, max_iter=16)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, it, rel = mesh.solve_cg(K, b, dirichlet, rtol=0.0, max_iter=iters)
+        torch.cuda.synchronize()
+        ms_it = (time.perf_counter() - t0) * 1e3 / max(it, 1)
+        t0 = time.perf_counter()
+        _, it6, rel6 = mesh.solve_cg(K, b, dirichlet, rtol=1e-6, max_iter=4000)
+        torch.cuda.synchronize()
+        solve_ms = (time.perf_counter() - t0) * 1e3
+        y = torch.empty_like(b)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        mesh.spmv(K, x, out=y)
+        e0.record()
+        for _ in range(spmv_reps):
+            mesh.spmv(K, x, out=y)
+        e1.record()
+        torch.cuda.synchronize()
+        spmv_ms = e0.elapsed_time(e1) / spmv_reps
+        nnz, ndof = info["nnz"], info["n_dof"]
+        byts = nnz * tb + (nnz // 3) * 4 + ndof * 8 * 2 + (ndof + 1) * 8
+        res[prec] = {"cg_iteration_ms": ms_it, "iterations_timed": it, "iterations_to_1e-6": it6,
+                     "relres_final": rel6, "solve_to_1e-6_ms": solve_ms, "spmv_ms": spmv_ms,
+                     "spmv_gbs": byts / (spmv_ms * 1e-3) / 1e9, "spmv_bytes": byts,
+                     "spmv_hbm_frac": byts / (spmv_ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+        log(f"[bench] solve {prec}: {ms_it:.3f} ms per CG iteration ({it} timed); to 1e-6: {it6} iterations, "
+            f"{solve_ms:.1f} ms (relres {rel6:.1e}); SpMV {spmv_ms:.3f} ms = {res[prec]['spmv_gbs']:.0f} GB/s")
     return res
 
 

@@ -203,6 +203,28 @@ int32_t mpm_assemble_adjoint(const mpm_mesh_t* mesh, const mpm_state_t* s, const
                              int32_t precision, double* dL_dE, double* dL_dnu, double* dL_dsy, double* dL_dV,
                              void* stream);
 
+/* y = K x for the assembled CSR of the mesh (K_vals [nnz] FP64 for MPM_F64 or FP32 for
+ * MPM_F32K; x, y [n_dof] FP64 device, y overwritten; products and sums in FP64). The three
+ * rows of a node share one column pattern; each node's rows are summed by one wavefront in a
+ * fixed order, so y is reproducible. */
+int32_t mpm_spmv(const mpm_mesh_t* mesh, int32_t precision, const void* K_vals, const double* x, double* y,
+                 void* stream);
+
+/* Linear solve of a Newton step on the assembled tangent: Jacobi-preconditioned conjugate
+ * gradients for K_ff x_f = b_f over the free DOFs (dirichlet[dof] == 0 when dirichlet is not
+ * NULL, row not empty, positive diagonal); x is zero on the other DOFs (the strong Dirichlet
+ * treatment of Section 2.4 applied to the increment) and b there is ignored. Stops when
+ * ||b_f - K_ff x_f|| <= rtol ||b_f|| (recursively updated residual), after max_iter
+ * iterations, or when p.Kp <= 0 (K_ff not positive definite along the search direction).
+ *   K_vals: [nnz] FP64 (MPM_F64) or FP32 (MPM_F32K); b, x: [n_dof] FP64 device (x written);
+ *   iters, relres: host outputs (may be NULL): iterations taken, final ||r|| / ||b_f||.
+ * Vectors, dot products and the preconditioner are FP64; reductions have a fixed order, so
+ * the iterates are reproducible. Work vectors (5 n_dof doubles) are kept with the mesh. The
+ * host reads the convergence flag every 16 iterations (one stream synchronisation each). */
+int32_t mpm_solve_cg(const mpm_mesh_t* mesh, int32_t precision, const void* K_vals, const uint8_t* dirichlet,
+                     const double* b, double* x, double rtol, int32_t max_iter, int32_t* iters, double* relres,
+                     void* stream);
+
 /* Kernel timing for measurement tools. enable = 1: from now on HIP events bracket the fused
  * assembly kernel (single-leaf points), the row-gather kernel that writes f_int and K, and
  * the adjoint kernel on the caller's stream, and their elapsed times accumulate in the handle

@@ -119,6 +119,10 @@ struct mpm_mesh {
   size_t scratch_bytes = 0;
   void* d_stage = nullptr;          // record-major staging copy of permuted arrays
   size_t stage_bytes = 0;
+  void* d_cg = nullptr;             // conjugate-gradient vectors, partial sums, scalars
+  size_t cg_bytes = 0;
+  void* h_cg = nullptr;             // pinned host copy of the solver flags and scalars
+  hipEvent_t cg_ev = nullptr;
   // kernel timing (measurement)
   bool timing = false;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};

@@ -1,0 +1,333 @@
+// Linear solve of a Newton step on the assembled tangent (the solve that consumes K, named by
+// the paper as the cost that dominates its CPU runs): Jacobi-preconditioned conjugate
+// gradients over the free DOFs (not Dirichlet, row not empty), with the fixed DOFs held at
+// zero (the strong Dirichlet treatment of Section 2.4 applied to the increment). K is the CSR
+// of the mesh in FP64 or FP32; vectors and reductions are FP64 and deterministic (fixed
+// two-stage summation order).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+namespace mpm {
+
+int32_t read_error(mpm_mesh* m, hipStream_t st, const char* what);
+
+constexpr int kSpmvNodes = 4;    // nodes per workgroup, one wavefront per node
+constexpr int kDotBlocks = 512;  // partial sums of a dot product
+
+// scalars kept on the device between the kernels of one solve
+enum CgScalar { kRZ = 0, kPQ, kBB, kRR, kRZN, kBeta, kNumScalars };
+struct CgFlags {
+  int done;
+  int iters;
+};
+
+// y = K x on the rows of `fr` (others: y = x). The three rows of node n are 9 deg contiguous
+// values [row][block][k] with one column pattern; one wavefront sums them, then a fixed-order
+// butterfly reduction.
+template <typename T>
+__global__ __launch_bounds__(64 * kSpmvNodes) void k_spmv(const int64_t* __restrict__ row_ptr,
+                                                          const int32_t* __restrict__ col, const T* __restrict__ K,
+                                                          const double* __restrict__ x, double* __restrict__ y,
+                                                          const uint8_t* __restrict__ fr, int64_t n_node,
+                                                          const CgFlags* flags) {
+  if (flags && flags->done) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t nd = int64_t(blockIdx.x) * kSpmvNodes + wave;
+  if (nd >= n_node) return;
+  const int64_t base = row_ptr[3 * nd];
+  const int len3 = int(row_ptr[3 * nd + 1] - base);
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  // lane l takes columns l, l + 64, ... of the three rows, two columns per step so that six
+  // values and two x entries are loaded together
+  for (int c = lane; c < len3; c += 128) {
+    const bool two = c + 64 < len3;
+    const int c1 = two ? c + 64 : c;
+    const double xa = x[col[base + c]], xb = x[col[base + c1]];
+    const double k0a = double(K[base + c]), k1a = double(K[base + len3 + c]), k2a = double(K[base + 2 * len3 + c]);
+    const double k0b = double(K[base + c1]), k1b = double(K[base + len3 + c1]),
+                 k2b = double(K[base + 2 * len3 + c1]);
+    const double wb = two ? xb : 0.0;
+    s0 += k0a * xa + k0b * wb;
+    s1 += k1a * xa + k1b * wb;
+    s2 += k2a * xa + k2b * wb;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    s0 += __shfl_xor(s0, off);
+    s1 += __shfl_xor(s1, off);
+    s2 += __shfl_xor(s2, off);
+  }
+  if (lane < 3) {
+    const int64_t d = 3 * nd + lane;
+    const double s = lane == 0 ? s0 : (lane == 1 ? s1 : s2);
+    y[d] = (!fr || fr[d]) ? s : x[d];
+  }
+}
+
+// block partial sums of a . b (and optionally c . d) in a fixed order
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (int(threadIdx.x) < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_dot_partial(const double* __restrict__ a, const double* __restrict__ b,
+                                                     int64_t n, double* __restrict__ part, const CgFlags* flags) {
+  if (flags && flags->done) return;
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < n; k += int64_t(gridDim.x) * 256) acc += a[k] * b[k];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// one block: scal[dst] = sum of np partials (fixed order)
+__global__ __launch_bounds__(256) void k_dot_final(const double* __restrict__ part, int np, double* scal, int dst,
+                                                   const CgFlags* flags) {
+  if (flags && flags->done) return;
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < np; k += 256) acc += part[k];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) scal[dst] = s;
+}
+
+// free DOFs, inverse diagonal, r = z = p = 0 / b on free DOFs, x = 0
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_init(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                                 const T* __restrict__ K, const uint8_t* __restrict__ dir,
+                                                 const double* __restrict__ b, int64_t ndof, uint8_t* __restrict__ fr,
+                                                 double* __restrict__ dinv, double* __restrict__ x,
+                                                 double* __restrict__ r, double* __restrict__ z,
+                                                 double* __restrict__ p) {
+  const int64_t d = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (d >= ndof) return;
+  double diag = 0.0;
+  const int64_t a0 = row_ptr[d], a1 = row_ptr[d + 1];
+  int64_t lo = a0, hi = a1 - 1;  // columns ascend: bisect for the diagonal
+  while (lo <= hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    const int32_t c = col[mid];
+    if (c == int32_t(d)) {
+      diag = double(K[mid]);
+      break;
+    }
+    if (c < int32_t(d)) lo = mid + 1;
+    else hi = mid - 1;
+  }
+  const bool f = (!dir || !dir[d]) && a1 > a0 && diag > 0.0;
+  fr[d] = f ? 1 : 0;
+  dinv[d] = f ? 1.0 / diag : 0.0;
+  const double bd = f ? b[d] : 0.0;
+  x[d] = 0.0;
+  r[d] = bd;
+  z[d] = dinv[d] * bd;
+  p[d] = z[d];
+}
+
+// alpha = rz / pq; x += alpha p; r -= alpha q; z = dinv r
+__global__ __launch_bounds__(256) void k_cg_update(double* __restrict__ x, double* __restrict__ r,
+                                                   double* __restrict__ z, const double* __restrict__ p,
+                                                   const double* __restrict__ q, const double* __restrict__ dinv,
+                                                   int64_t ndof, const double* scal, const CgFlags* flags) {
+  if (flags->done) return;
+  const double pq = scal[kPQ];
+  if (!(pq > 0.0)) return;  // not positive definite along p: the step kernel stops the solve
+  const double alpha = scal[kRZ] / pq;
+  for (int64_t d = int64_t(blockIdx.x) * 256 + threadIdx.x; d < ndof; d += int64_t(gridDim.x) * 256) {
+    x[d] += alpha * p[d];
+    const double rd = r[d] - alpha * q[d];
+    r[d] = rd;
+    z[d] = dinv[d] * rd;
+  }
+}
+
+// after r.z -> scal[kRZN] and r.r -> scal[kRR]: beta, convergence, iteration count
+__global__ void k_cg_step(double* scal, CgFlags* flags, double rtol2, int max_iter) {
+  if (flags->done) return;
+  if (!(scal[kPQ] > 0.0)) {  // breakdown: the update was skipped
+    flags->done = 2;
+    return;
+  }
+  flags->iters += 1;
+  const double rz_new = scal[kRZN];
+  scal[kBeta] = rz_new / scal[kRZ];
+  scal[kRZ] = rz_new;
+  if (!(scal[kRR] > rtol2 * scal[kBB]) || flags->iters >= max_iter || !(rz_new > 0.0)) flags->done = 1;
+}
+
+// p = z + beta p
+__global__ __launch_bounds__(256) void k_cg_dir(double* __restrict__ p, const double* __restrict__ z, int64_t ndof,
+                                                const double* scal, const CgFlags* flags) {
+  if (flags->done) return;
+  const double beta = scal[kBeta];
+  for (int64_t d = int64_t(blockIdx.x) * 256 + threadIdx.x; d < ndof; d += int64_t(gridDim.x) * 256)
+    p[d] = z[d] + beta * p[d];
+}
+
+__global__ void k_cg_start(double* scal, CgFlags* flags) {
+  flags->done = scal[kBB] > 0.0 ? 0 : 1;  // b = 0 on the free DOFs: x = 0
+  flags->iters = 0;
+}
+
+template <typename T>
+static void launch_spmv(const mpm_mesh* m, const void* K, const double* x, double* y, const uint8_t* fr,
+                        const CgFlags* flags, hipStream_t st) {
+  const dim3 grid(unsigned((m->n_node + kSpmvNodes - 1) / kSpmvNodes));
+  hipLaunchKernelGGL(k_spmv<T>, grid, dim3(64 * kSpmvNodes), 0, st, m->d_row_ptr, m->d_col,
+                     static_cast<const T*>(K), x, y, fr, m->n_node, flags);
+}
+
+static void launch_dot(const double* a, const double* b, int64_t n, double* part, double* scal, int dst,
+                       const CgFlags* flags, hipStream_t st) {
+  const int nb = int(std::max<int64_t>(1, std::min<int64_t>(kDotBlocks, (n + 255) / 256)));
+  hipLaunchKernelGGL(k_dot_partial, dim3(nb), dim3(256), 0, st, a, b, n, part, flags);
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(256), 0, st, part, nb, scal, dst, flags);
+}
+
+// work buffer of the solver kept with the mesh: r, z, p, q, dinv [n_dof] doubles, partials,
+// scalars, flags, free mask
+struct CgBuf {
+  double *r, *z, *p, *q, *dinv, *part, *scal;
+  CgFlags* flags;
+  uint8_t* fr;
+};
+
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+static int32_t cg_buffers(mpm_mesh* m, hipStream_t st, CgBuf* B) {
+  const size_t nd = size_t(3 * m->n_node);
+  const size_t vec = align256(nd * 8);
+  const size_t need = 5 * vec + align256(kDotBlocks * 8) + align256(kNumScalars * 8) + align256(sizeof(CgFlags)) +
+                      align256(std::max<size_t>(1, nd));
+  if (m->cg_bytes < need || !m->d_cg) {
+    MPM_HIP(hipStreamSynchronize(st));
+    if (m->d_cg) MPM_HIP(hipFree(m->d_cg));
+    m->d_cg = nullptr;
+    m->cg_bytes = 0;
+    const hipError_t e = hipMalloc(&m->d_cg, need);
+    if (e != hipSuccess) {
+      m->d_cg = nullptr;
+      return hip_fail(e, "mpm_solve_cg: work buffer");
+    }
+    m->cg_bytes = need;
+  }
+  char* w = static_cast<char*>(m->d_cg);
+  B->r = reinterpret_cast<double*>(w);
+  B->z = reinterpret_cast<double*>(w + vec);
+  B->p = reinterpret_cast<double*>(w + 2 * vec);
+  B->q = reinterpret_cast<double*>(w + 3 * vec);
+  B->dinv = reinterpret_cast<double*>(w + 4 * vec);
+  w += 5 * vec;
+  B->part = reinterpret_cast<double*>(w);
+  w += align256(kDotBlocks * 8);
+  B->scal = reinterpret_cast<double*>(w);
+  w += align256(kNumScalars * 8);
+  B->flags = reinterpret_cast<CgFlags*>(w);
+  w += align256(sizeof(CgFlags));
+  B->fr = reinterpret_cast<uint8_t*>(w);
+  return MPM_OK;
+}
+
+template <typename T>
+static int32_t solve_cg(mpm_mesh* m, const void* K, const uint8_t* dir, const double* b, double* x, double rtol,
+                        int max_iter, int* iters, double* relres, hipStream_t st) {
+  CgBuf B;
+  int32_t rc = cg_buffers(m, st, &B);
+  if (rc) return rc;
+  const int64_t nd = 3 * m->n_node;
+  const unsigned gv = unsigned(std::max<int64_t>(1, std::min<int64_t>(2048, (nd + 255) / 256)));
+  hipLaunchKernelGGL(k_cg_init<T>, dim3(unsigned((nd + 255) / 256)), dim3(256), 0, st, m->d_row_ptr, m->d_col,
+                     static_cast<const T*>(K), dir, b, nd, B.fr, B.dinv, x, B.r, B.z, B.p);
+  launch_dot(B.r, B.z, nd, B.part, B.scal, kRZ, nullptr, st);
+  launch_dot(B.r, B.r, nd, B.part, B.scal, kBB, nullptr, st);
+  launch_dot(B.r, B.r, nd, B.part, B.scal, kRR, nullptr, st);
+  hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(1), 0, st, B.scal, B.flags);
+  const double rtol2 = rtol * rtol;
+  if (!m->h_cg) MPM_HIP(hipHostMalloc((void**)&m->h_cg, sizeof(CgFlags) + 8 * kNumScalars, hipHostMallocDefault));
+  if (!m->cg_ev) MPM_HIP(hipEventCreateWithFlags(&m->cg_ev, hipEventDisableTiming));
+  constexpr int kCheck = 16;  // iterations between host reads of the flags
+  for (int it = 0; it < max_iter; it += kCheck) {
+    const int nk = std::min(kCheck, max_iter - it);
+    for (int k = 0; k < nk; ++k) {
+      launch_spmv<T>(m, K, B.p, B.q, B.fr, B.flags, st);
+      launch_dot(B.p, B.q, nd, B.part, B.scal, kPQ, B.flags, st);
+      hipLaunchKernelGGL(k_cg_update, dim3(gv), dim3(256), 0, st, x, B.r, B.z, B.p, B.q, B.dinv, nd, B.scal,
+                         B.flags);
+      launch_dot(B.r, B.z, nd, B.part, B.scal, kRZN, B.flags, st);
+      launch_dot(B.r, B.r, nd, B.part, B.scal, kRR, B.flags, st);
+      hipLaunchKernelGGL(k_cg_step, dim3(1), dim3(1), 0, st, B.scal, B.flags, rtol2, max_iter);
+      hipLaunchKernelGGL(k_cg_dir, dim3(gv), dim3(256), 0, st, B.p, B.z, nd, B.scal, B.flags);
+    }
+    MPM_HIP(hipGetLastError());
+    MPM_HIP(hipMemcpyAsync(m->h_cg, B.flags, sizeof(CgFlags), hipMemcpyDeviceToHost, st));
+    MPM_HIP(hipMemcpyAsync(static_cast<char*>(m->h_cg) + sizeof(CgFlags), B.scal, 8 * kNumScalars,
+                           hipMemcpyDeviceToHost, st));
+    MPM_HIP(hipEventRecord(m->cg_ev, st));
+    hipError_t q;
+    while ((q = hipEventQuery(m->cg_ev)) == hipErrorNotReady) {
+    }
+    if (q != hipSuccess) return hip_fail(q, "mpm_solve_cg");
+    const CgFlags* f = static_cast<const CgFlags*>(m->h_cg);
+    if (f->done) break;
+  }
+  const CgFlags* f = static_cast<const CgFlags*>(m->h_cg);
+  const double* sc = reinterpret_cast<const double*>(static_cast<const char*>(m->h_cg) + sizeof(CgFlags));
+  if (iters) *iters = f->iters;
+  if (relres) *relres = sc[kBB] > 0.0 ? std::sqrt(std::max(0.0, sc[kRR]) / sc[kBB]) : 0.0;
+  if (f->iters == 0 && sc[kBB] > 0.0 && relres) *relres = 1.0;
+  return MPM_OK;
+}
+
+}  // namespace mpm
+
+using namespace mpm;
+
+extern "C" int32_t mpm_spmv(const mpm_mesh_t* m, int32_t precision, const void* K_vals, const double* x, double* y,
+                            void* stream) {
+  if (!m || !K_vals || !x || !y || (precision != MPM_F64 && precision != MPM_F32K)) {
+    set_error(MPM_EARG, "mpm_spmv: null argument or bad precision");
+    return MPM_EARG;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (m->n_node) {
+    if (precision == MPM_F64) launch_spmv<double>(m, K_vals, x, y, nullptr, nullptr, st);
+    else launch_spmv<float>(m, K_vals, x, y, nullptr, nullptr, st);
+  }
+  MPM_HIP(hipGetLastError());
+  return MPM_OK;
+}
+
+extern "C" int32_t mpm_solve_cg(const mpm_mesh_t* m, int32_t precision, const void* K_vals,
+                                const uint8_t* dirichlet, const double* b, double* x, double rtol, int32_t max_iter,
+                                int32_t* iters, double* relres, void* stream) {
+  if (!m || !K_vals || !b || !x || (precision != MPM_F64 && precision != MPM_F32K) || !(rtol >= 0.0) ||
+      max_iter < 0) {
+    set_error(MPM_EARG, "mpm_solve_cg: null argument, bad precision, negative tolerance or iteration limit");
+    return MPM_EARG;
+  }
+  mpm_mesh* mm = const_cast<mpm_mesh*>(m);
+  hipStream_t st = (hipStream_t)stream;
+  int it = 0;
+  double rr = 0.0;
+  int32_t rc = MPM_OK;
+  if (m->n_node == 0) {
+    if (iters) *iters = 0;
+    if (relres) *relres = 0.0;
+    return MPM_OK;
+  }
+  if (precision == MPM_F64) rc = solve_cg<double>(mm, K_vals, dirichlet, b, x, rtol, max_iter, &it, &rr, st);
+  else rc = solve_cg<float>(mm, K_vals, dirichlet, b, x, rtol, max_iter, &it, &rr, st);
+  if (iters) *iters = it;
+  if (relres) *relres = rr;
+  return rc;
+}

@@ -220,6 +220,24 @@ class Mesh:
                                          _ptr(o.get("v_new") if want_kinematics else None), _stream()))
         return o
 
+    def spmv(self, K: torch.Tensor, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """y = K x on the mesh's CSR (K FP64 or FP32, x FP64)."""
+        p = MPM_F64 if K.dtype == torch.float64 else MPM_F32K
+        y = torch.empty_like(x) if out is None else out
+        check(lib().mpm_spmv(self.h, p, _ptr(K), _ptr(x), _ptr(y), _stream()))
+        return y
+
+    def solve_cg(self, K: torch.Tensor, b: torch.Tensor, dirichlet=None, rtol: float = 1e-8, max_iter: int = 1000,
+                 out: Optional[torch.Tensor] = None):
+        """Jacobi-preconditioned CG for K_ff x_f = b_f (free DOFs); returns (x, iterations, relres)."""
+        p = MPM_F64 if K.dtype == torch.float64 else MPM_F32K
+        x = torch.empty_like(b) if out is None else out
+        it = C.c_int32(0)
+        rr = C.c_double(0.0)
+        check(lib().mpm_solve_cg(self.h, p, _ptr(K), _ptr(dirichlet), _ptr(b), _ptr(x), float(rtol), int(max_iter),
+                                 C.byref(it), C.byref(rr), _stream()))
+        return x, int(it.value), float(rr.value)
+
     def adjoint(self, s: dict, u: torch.Tensor, lam: torch.Tensor, precision="f64", out: Optional[dict] = None):
         p = PRECISION.get(precision, precision)
         n = self.info["n_point"]

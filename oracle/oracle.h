@@ -58,6 +58,13 @@ void orc_mesh_hanging(const orc_mesh* m, int32_t* ijk /* n_hang x 3 */, int32_t*
 void orc_mesh_cells(const orc_mesh* m, int32_t* n, int32_t* inodes /* n_leaf x ORC_MAXI */,
                     double* cmat /* n_leaf x 8 x ORC_MAXI */);
 
+/* Ghost stabilisation (Section 4): enable before orc_mesh_set_points to add the couplings of
+ * the ghost faces to the CSR pattern; faces: n x 8 (lo leaf, hi leaf, axis, plane, b0, b1,
+ * c0, c1 in lattice units) */
+void orc_mesh_set_ghost(orc_mesh* m, int32_t enable);
+int64_t orc_ghost_nfaces(const orc_mesh* m);
+void orc_ghost_faces(const orc_mesh* m, int32_t* out);
+
 /* points: SoA x[3][n], l[3][n] */
 int32_t orc_mesh_set_points(orc_mesh* m, const double* x, const double* l, int64_t n, int64_t* bad_index);
 void orc_mesh_perm(const orc_mesh* m, int64_t* perm /* sorted position -> original index */,
@@ -91,6 +98,10 @@ int32_t orc_external_force(const orc_mesh* m, const orc_state* s, double* f_ext)
  * velocity [3][n] (may be NULL); vel = point velocities at the start of the step [3][n]. */
 int32_t orc_inertia(const orc_mesh* m, const orc_state* s, const double* u, const double* vel, double dt,
                     double* f_iner, double* K, double* a_new, double* v_new, int64_t* bad_index);
+/* ghost term: K += K_G (may be NULL), f += K_G u (may be NULL), beta_leaf [n_leaf] = max E of
+ * the points overlapping each leaf (may be NULL) */
+int32_t orc_ghost_assemble(const orc_mesh* m, const orc_state* s, const double* u, double* K, double* f,
+                           double* beta_leaf);
 /* r = f_int - f_ext with dirichlet DOFs zeroed; returns ||r||_2 in *rnorm */
 void orc_residual(int64_t ndof, const double* f_int, const double* f_ext, const uint8_t* dirichlet,
                   double* r, double* rnorm);

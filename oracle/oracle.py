@@ -14,7 +14,7 @@ import numpy as np
 
 HERE = Path(__file__).resolve().parent
 LIB = HERE / "liboracle.so"
-SOURCES = ["orc_mesh.c", "orc_point.c"]
+SOURCES = ["orc_mesh.c", "orc_point.c", "orc_ghost.c"]
 
 _i64 = np.int64
 _f64 = np.float64
@@ -72,6 +72,12 @@ def lib():
         L.orc_assemble.argtypes = [vp, C.POINTER(_State), vp, vp, vp, vp, vp, vp, vp, i64p]
         L.orc_external_force.restype = C.c_int32
         L.orc_external_force.argtypes = [vp, C.POINTER(_State), vp]
+        L.orc_mesh_set_ghost.argtypes = [vp, C.c_int32]
+        L.orc_ghost_nfaces.restype = C.c_int64
+        L.orc_ghost_nfaces.argtypes = [vp]
+        L.orc_ghost_faces.argtypes = [vp, vp]
+        L.orc_ghost_assemble.restype = C.c_int32
+        L.orc_ghost_assemble.argtypes = [vp, C.POINTER(_State), vp, vp, vp, vp]
         L.orc_inertia.restype = C.c_int32
         L.orc_inertia.argtypes = [vp, C.POINTER(_State), vp, vp, C.c_double, vp, vp, vp, vp, i64p]
         L.orc_residual.argtypes = [C.c_int64, vp, vp, vp, vp, vp]
@@ -109,13 +115,35 @@ MAXI = 27
 
 
 class OracleMesh:
-    def __init__(self, crit: dict):
+    def __init__(self, crit: dict, ghost: bool = False):
         self._crit = make_crit(crit)
         st = C.c_int32(0)
         self.h = lib().orc_mesh_build(C.byref(self._crit), C.byref(st))
         if not self.h:
             raise OracleError(st.value)
         self._keep = []
+        lib().orc_mesh_set_ghost(self.h, 1 if ghost else 0)
+
+    def ghost_faces(self) -> np.ndarray:
+        """Ghost faces (lo leaf, hi leaf, axis, plane, b0, b1, c0, c1), lattice units."""
+        n = int(lib().orc_ghost_nfaces(self.h))
+        out = np.zeros((n, 8), np.int32)
+        if n:
+            lib().orc_ghost_faces(self.h, _p(out))
+        return out
+
+    def ghost(self, s: dict, u: np.ndarray) -> dict:
+        """Ghost term: K_G on the CSR pattern, f_G = K_G u, per-leaf maximum Young's modulus."""
+        c = self.counts()
+        st = self._state(s)
+        u = np.ascontiguousarray(u, dtype=_f64)
+        K = np.zeros(c["nnz"], _f64)
+        f = np.zeros(3 * c["n_node"], _f64)
+        beta = np.zeros(c["n_leaf"], _f64)
+        code = lib().orc_ghost_assemble(self.h, C.byref(st), _p(u), _p(K), _p(f), _p(beta))
+        if code != 0:
+            raise OracleError(code)
+        return dict(K=K, f=f, beta=beta)
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -40,7 +40,14 @@ struct orc_mesh {
   int64_t nnz;
   int64_t* row_ptr;          /* 3*nindep + 1 */
   int32_t* col;
+  /* ghost stabilisation */
+  int32_t ghost;             /* add ghost-face couplings to the CSR pattern at set_points */
+  int64_t ngface;
+  int32_t* gface;            /* ngface x 8: lo leaf, hi leaf, axis, plane, b0, b1, c0, c1 */
 };
+
+int64_t orc_ghost_build_faces(orc_mesh* m, const uint8_t* pop);
+int64_t orc_ghost_pairs(const orc_mesh* m, uint64_t** pairs, int64_t npair, int64_t* cap);
 
 uint64_t orc_morton3(uint64_t x, uint64_t y, uint64_t z);
 /* overlapped leaves of a domain (centre x, half-lengths l): returns count or negative status.

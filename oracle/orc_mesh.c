@@ -431,7 +431,7 @@ void orc_mesh_free(orc_mesh* m) {
   free(m->leaf); free(m->leafmap); free(m->node_ijk); free(m->nodemap); free(m->hang); free(m->indep);
   free(m->indep_node); free(m->hang_owner); free(m->hang_nsup); free(m->hang_sup); free(m->hang_w);
   free(m->ik_n); free(m->ik_node); free(m->ik_c); free(m->px); free(m->pl); free(m->perm); free(m->pleaf);
-  free(m->pnleaf); free(m->sup_off); free(m->sup_node); free(m->row_ptr); free(m->col);
+  free(m->pnleaf); free(m->sup_off); free(m->sup_node); free(m->row_ptr); free(m->col); free(m->gface);
   free(m);
 }
 
@@ -564,6 +564,7 @@ int32_t orc_mesh_set_points(orc_mesh* m, const double* x, const double* l, int64
   m->nstraddle = 0;
   m->maxsup = 0;
   uint8_t* leaf_pop = (uint8_t*)calloc((size_t)m->nleaf, 1);
+  uint8_t* any_pop = (uint8_t*)calloc((size_t)m->nleaf + 1, 1);  /* overlapped by any point */
   int32_t lv[ORC_MAXL];
   double box[6 * ORC_MAXL];
   int64_t npair_cap = 1 << 20, npair = 0;
@@ -571,7 +572,7 @@ int32_t orc_mesh_set_points(orc_mesh* m, const double* x, const double* l, int64
   for (int64_t p = 0; p < n; p++) {
     double xp[3] = {x[p], x[n + p], x[2 * n + p]}, lp[3] = {l[p], l[n + p], l[2 * n + p]};
     int nl = orc_point_leaves(m, xp, lp, lv, box);
-    if (nl < 0) { *bad = p; free(leaf_pop); free(pairs); return nl; }
+    if (nl < 0) { *bad = p; free(leaf_pop); free(any_pop); free(pairs); return nl; }
     m->pnleaf[p] = (uint8_t)nl;
     int32_t sup[ORC_MAXS];
     int ns = 0;
@@ -581,7 +582,7 @@ int32_t orc_mesh_set_points(orc_mesh* m, const double* x, const double* l, int64
         int f = 0;
         for (int t = 0; t < ns; t++) f |= sup[t] == id;
         if (!f) {
-          if (ns >= ORC_MAXS) { *bad = p; free(leaf_pop); free(pairs); return ORC_ESTENCIL; }
+          if (ns >= ORC_MAXS) { *bad = p; free(leaf_pop); free(any_pop); free(pairs); return ORC_ESTENCIL; }
           sup[ns++] = id;
         }
       }
@@ -592,6 +593,7 @@ int32_t orc_mesh_set_points(orc_mesh* m, const double* x, const double* l, int64
     memcpy(m->sup_node + used, sup, (size_t)ns * sizeof(int32_t));
     used += ns;
     if (ns > m->maxsup) m->maxsup = ns;
+    for (int k = 0; k < nl; k++) any_pop[lv[k]] = 1;
     if (nl == 1) leaf_pop[lv[0]] = 1;
     else {
       m->nstraddle++;
@@ -614,6 +616,14 @@ int32_t orc_mesh_set_points(orc_mesh* m, const double* x, const double* l, int64
       }
   }
   free(leaf_pop);
+  free(m->gface);
+  m->gface = NULL;
+  m->ngface = 0;
+  if (m->ghost) {
+    orc_ghost_build_faces(m, any_pop);
+    npair = orc_ghost_pairs(m, &pairs, npair, &npair_cap);
+  }
+  free(any_pop);
   qsort(pairs, (size_t)npair, sizeof(uint64_t), cmp_u64);
   int64_t nu = 0;
   for (int64_t i = 0; i < npair; i++)

@@ -61,7 +61,9 @@ extern "C" {
  * rounds repeat until nothing is marked, each followed by 2:1 balance across faces and
  * edges (at most one hanging node per edge or face). The mesh box is lo + [0, base*h0];
  * base cells have level lvl_base; a level-l leaf has side h0 * 2^(lvl_base - l).
- * Ties of the distance predicates are inclusive up to a relative 1e-12 slack. */
+ * Ties of the distance predicates are inclusive up to a relative 1e-12 slack.
+ * ghost != 0 adds the ghost stabilisation of Section 4 (eq. ghost) to every assembly on the
+ * mesh; see octree_build and mpm_assemble. */
 typedef struct {
   double lo[3];
   int32_t base[3];
@@ -70,6 +72,7 @@ typedef struct {
   int32_t body_kind;
   double body[8];
   double dx_region;
+  int32_t ghost;
 } mpm_refine_t;
 
 typedef struct mpm_mesh mpm_mesh_t;
@@ -86,6 +89,7 @@ typedef struct {
   int32_t max_support;   /* largest point support (nodes) */
   int32_t lattice[3];    /* finest-lattice cells per axis */
   double h_min;          /* finest cell size */
+  int64_t n_ghost_face;  /* ghost faces (0 unless mpm_refine_t.ghost) */
 } mpm_mesh_info_t;
 
 /* Library-owned device arrays, valid until mpm_mesh_free (read only). */
@@ -134,12 +138,24 @@ typedef struct {
  * pair is a dense 3x3 block; rows of unsupported nodes are empty.
  *   x, l: [3][n] host OR device arrays (detected), caller-owned; n may be 0 (mesh only).
  *   *out_mesh: new library-owned handle (free with mpm_mesh_free).
- * Host work: refinement, balance, numbering, CSR pattern. Device work: point-to-leaf search,
- * radix sort and overlap classification. */
+ * With crit->ghost != 0 (Section 4): a leaf is populated when some point domain overlaps it;
+ * a boundary leaf is a populated leaf with an unpopulated face neighbour; the ghost faces are
+ * the faces shared by a boundary leaf and a populated leaf (each once; between leaves of two
+ * sizes the face is the smaller leaf's face). The nodes of the two leaves of a ghost face are
+ * coupled in the pattern too, and per face the library keeps the 16 x 16 matrix
+ * G_F[a][b] = int_F [d_n phi~_a] [d_n phi~_b] dA of the jumps across F of the normal
+ * derivatives of the two leaves' constrained trilinear basis functions (2 x 2 Gauss rule,
+ * exact for the biquadratic integrand).
+ * Host work: refinement, balance, numbering, CSR pattern, ghost faces. Device work:
+ * point-to-leaf search, radix sort and overlap classification. */
 int32_t octree_build(const mpm_refine_t* crit, const double* x, const double* l, int64_t n, void* stream,
                      mpm_mesh_t** out_mesh);
 int32_t mpm_mesh_info(const mpm_mesh_t* mesh, mpm_mesh_info_t* out);
 int32_t mpm_mesh_arrays(const mpm_mesh_t* mesh, mpm_mesh_arrays_t* out);
+/* Ghost faces of the mesh (host out [n_ghost_face][8], caller-owned): lower leaf rank, higher
+ * leaf rank, normal axis, plane, then the face's extent [b0, b1) x [c0, c1) along the axes
+ * (axis + 1) % 3 and (axis + 2) % 3, all in finest-lattice units; sorted by leaf pair. */
+int32_t mpm_ghost_faces(const mpm_mesh_t* mesh, int32_t* out);
 void mpm_mesh_free(mpm_mesh_t* mesh);
 
 /* Re-order points of an existing mesh (device only): leaf search and a stable radix sort by
@@ -175,6 +191,11 @@ int32_t mpm_external_force(const mpm_mesh_t* mesh, const mpm_state_t* s, double*
  *   r [n_dof] = f_int - f_ext with DOFs where dirichlet[dof] != 0 zeroed (f_ext, dirichlet
  *   may be NULL = zero / none), and rnorm (device, 1 double) = ||r||_2 in FP64; both may be
  *   NULL; F_new [9][n] = dF F_n and be_new [6][n] updated b_e, may be NULL (commit state).
+ * On a mesh built with ghost stabilisation (Section 4, eq. ghost) the penalty
+ *   j(u, v) = sum_F (h_F beta_F / kappa) int_F [d_n u] . [d_n v] dA,  kappa = 10,
+ * h_F the larger side of the face's two leaves and beta_F the larger of their maxima of the
+ * Young's moduli of the points overlapping them, adds K_G (the same scalar form on each
+ * displacement component) to K and K_G u to f_int.
  * Synchronises `stream` once at the end to read the device error flag. */
 int32_t mpm_assemble(const mpm_mesh_t* mesh, const mpm_state_t* s, const double* u, int32_t precision,
                      const double* f_ext, const uint8_t* dirichlet, double* f_int, void* K_vals, double* sigma6,
@@ -198,7 +219,9 @@ int32_t mpm_assemble_dynamic(const mpm_mesh_t* mesh, const mpm_state_t* s, const
 
 /* Adjoint of the assembly for L = lambda . f_int(u) (lambda: device [n_dof]): per point
  * dL/dE, dL/dnu, dL/dsy, dL/dV_n (device [n] FP64 each, caller-owned). Gather only (no
- * atomics); the return map is recomputed, nothing is stored by the forward pass. */
+ * atomics); the return map is recomputed, nothing is stored by the forward pass.
+ * The ghost penalty depends on E only through per-leaf maxima (not differentiable where two
+ * points tie); a mesh built with ghost stabilisation returns MPM_EARG. */
 int32_t mpm_assemble_adjoint(const mpm_mesh_t* mesh, const mpm_state_t* s, const double* u, const double* lambda,
                              int32_t precision, double* dL_dE, double* dL_dnu, double* dL_dsy, double* dL_dV,
                              void* stream);

@@ -14,14 +14,15 @@ MPM_F64, MPM_F32K = 0, 1
 
 class RefineT(C.Structure):
     _fields_ = [("lo", C.c_double * 3), ("base", C.c_int32 * 3), ("h0", C.c_double), ("lvl_base", C.c_int32),
-                ("lvl_max", C.c_int32), ("body_kind", C.c_int32), ("body", C.c_double * 8), ("dx_region", C.c_double)]
+                ("lvl_max", C.c_int32), ("body_kind", C.c_int32), ("body", C.c_double * 8), ("dx_region", C.c_double),
+                ("ghost", C.c_int32)]
 
 
 class MeshInfoT(C.Structure):
     _fields_ = [("n_leaf", C.c_int64), ("n_node", C.c_int64), ("n_hang", C.c_int64), ("n_dof", C.c_int64),
                 ("nnz", C.c_int64), ("n_point", C.c_int64), ("n_straddle", C.c_int64),
                 ("n_active_rows", C.c_int64), ("max_support", C.c_int32), ("lattice", C.c_int32 * 3),
-                ("h_min", C.c_double)]
+                ("h_min", C.c_double), ("n_ghost_face", C.c_int64)]
 
 
 class MeshArraysT(C.Structure):
@@ -61,6 +62,8 @@ def lib():
     L.mpm_mesh_info.argtypes = [vp, C.POINTER(MeshInfoT)]
     L.mpm_mesh_arrays.restype = i32
     L.mpm_mesh_arrays.argtypes = [vp, C.POINTER(MeshArraysT)]
+    L.mpm_ghost_faces.restype = i32
+    L.mpm_ghost_faces.argtypes = [vp, vp]
     L.mpm_mesh_free.restype = None
     L.mpm_mesh_free.argtypes = [vp]
     L.mpm_point_sort.restype = i32
@@ -90,7 +93,7 @@ def lib():
     return L
 
 
-EXPORTED = ["octree_build", "mpm_mesh_info", "mpm_mesh_arrays", "mpm_mesh_free", "mpm_point_sort", "mpm_permute",
+EXPORTED = ["octree_build", "mpm_mesh_info", "mpm_mesh_arrays", "mpm_ghost_faces", "mpm_mesh_free", "mpm_point_sort", "mpm_permute",
             "mpm_external_force", "mpm_assemble", "mpm_assemble_dynamic", "mpm_assemble_adjoint", "mpm_spmv",
             "mpm_solve_cg", "mpm_kernel_timing", "mpm_last_error",
             "mpm_last_error_index"]

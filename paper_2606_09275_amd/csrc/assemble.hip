@@ -1054,6 +1054,8 @@ static int32_t assemble_impl(const mpm_mesh_t* m, const AsmArgs& A, int32_t prec
     if (precision == MPM_F64) hipLaunchKernelGGL(k_assemble_general<double>, grid, dim3(64), 0, st, A);
     else hipLaunchKernelGGL(k_assemble_general<float>, grid, dim3(64), 0, st, A);
   }
+  // ghost penalty (Section 4): after every point term, before the residual
+  if (const int32_t rg = ghost_apply(m, &A.s, A.u, precision, K_vals, f_int, st)) return rg;
   if (r || rnorm) {
     const int64_t nd = 3 * m->n_node;
     int nb = int(std::min<int64_t>(kResBlocks, (nd + 255) / 256));
@@ -1082,6 +1084,10 @@ extern "C" int32_t mpm_assemble_adjoint(const mpm_mesh_t* m, const mpm_state_t* 
   if (!m || !state_ok(s) || !u || !lambda || !dE || !dnu || !dsy || !dV ||
       (precision != MPM_F64 && precision != MPM_F32K)) {
     set_error(MPM_EARG, "mpm_assemble_adjoint: null argument or bad precision");
+    return MPM_EARG;
+  }
+  if (m->n_gface) {
+    set_error(MPM_EARG, "mpm_assemble_adjoint: not defined on a mesh with ghost stabilisation");
     return MPM_EARG;
   }
   hipStream_t st = (hipStream_t)stream;

@@ -60,6 +60,16 @@ struct HostTree {
   std::vector<double> cell_cmat;   // n_leaf x 8 x 8: C_K[vertex][slot]
 };
 
+// ghost faces built on the host: per face the two leaves (lower rank first), the union of
+// their slot nodes (16, -1 padded), the 16 x 16 matrix of normal-derivative jump integrals,
+// h_F / kappa, and the face record (lo leaf, hi leaf, axis, plane, b0, b1, c0, c1) in
+// finest-lattice units
+struct GhostHost {
+  int64_t nf = 0;
+  std::vector<int32_t> leaf2, nodes, face;
+  std::vector<double> G, h;
+};
+
 }  // namespace mpm
 
 struct mpm_mesh {
@@ -123,9 +133,33 @@ struct mpm_mesh {
   size_t cg_bytes = 0;
   void* h_cg = nullptr;             // pinned host copy of the solver flags and scalars
   hipEvent_t cg_ev = nullptr;
+  // ghost stabilisation (enabled by mpm_refine_t.ghost): faces, their node unions and jump
+  // matrices; the nodes with ghost couplings and, per node, its (face * 16 + local index)
+  // contributions in ascending face order; the block column of every face node pair in the
+  // row of the first node; the per-leaf maximum Young's modulus (recomputed per call)
+  int64_t n_gface = 0, n_gnode = 0;
+  std::vector<int32_t> h_gface;     // n_gface x 8 face records (host copy)
+  int32_t* d_gf_leaf = nullptr;     // n_gface x 2
+  int32_t* d_gf_nodes = nullptr;    // n_gface x 16
+  double* d_gf_G = nullptr;         // n_gface x 256
+  double* d_gf_h = nullptr;         // n_gface: h_F / kappa
+  int16_t* d_gf_bpos = nullptr;     // n_gface x 256
+  int32_t* d_gnode = nullptr;       // n_gnode
+  int32_t* d_gcon_off = nullptr;    // n_gnode + 1
+  int32_t* d_gcon = nullptr;
+  double* d_gbeta = nullptr;        // n_leaf
   // kernel timing (measurement)
   bool timing = false;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   double t_asm = 0, t_adj = 0, t_gat = 0;
   int64_t n_asm = 0, n_adj = 0, n_gat = 0;
 };
+
+namespace mpm {
+struct LeafGeo;
+// ghost faces of the populated flags pop (host leaf geometry G: leaf and key arrays of T)
+int64_t ghost_faces_host(const HostTree& T, const LeafGeo& G, const std::vector<uint8_t>& pop, GhostHost* out);
+// adds the ghost form's stiffness to K (precision's type) and K_G u to f on stream st
+int32_t ghost_apply(const mpm_mesh* m, const mpm_state_t* s, const double* u, int32_t precision, void* K, double* f,
+                    hipStream_t st);
+}  // namespace mpm

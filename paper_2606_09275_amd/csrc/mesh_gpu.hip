@@ -488,7 +488,8 @@ extern "C" void mpm_mesh_free(mpm_mesh_t* m) {
                   m->d_hang_ijk, m->d_hang_sup, m->d_hang_w, m->d_hang_owner, m->d_perm, m->d_pleaf, m->d_pnleaf,
                   m->d_row_ptr, m->d_col, m->d_wave_seg, m->d_leaf_seg0, m->d_leaf_nseg, m->d_con_off, m->d_con_seg, m->d_con_bp, m->d_bpos,
                   m->d_segK, m->d_segF, m->d_red1, m->d_red2, m->d_strad, m->d_strad_leaf, m->d_err,
-                  m->d_partial, m->d_scratch, m->d_stage, m->d_cellmap, m->d_cg};
+                  m->d_partial, m->d_scratch, m->d_stage, m->d_cellmap, m->d_cg, m->d_gf_leaf, m->d_gf_nodes,
+                  m->d_gf_G, m->d_gf_h, m->d_gf_bpos, m->d_gnode, m->d_gcon_off, m->d_gcon, m->d_gbeta};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (hipEvent_t e : m->ev)
@@ -650,6 +651,28 @@ extern "C" int32_t octree_build(const mpm_refine_t* crit, const double* x, const
     for (int a = 0; a < 8; ++a)
       for (int b = 0; b < 8; ++b) pairs.push_back((uint64_t(uint32_t(s[a])) << 32) | uint32_t(s[b]));
   }
+  // ghost faces (Section 4): populated here means overlapped by any point domain
+  GhostHost gh;
+  if (crit->ghost) {
+    std::vector<uint8_t> any_pop(populated);
+    for (int32_t e : sleaf)
+      if (e >= 0) any_pop[e] = 1;
+    LeafGeo HG = make_geo(m);
+    HG.leaf = T.leaf.data();
+    HG.leaf_key = T.leaf_key.data();
+    HG.cellmap = nullptr;
+    ghost_faces_host(T, HG, any_pop, &gh);
+    if (gh.nf >= (int64_t(1) << 27)) {
+      set_error(MPM_EARG, "octree_build: too many ghost faces");
+      mpm_mesh_free(m);
+      return MPM_EARG;
+    }
+    for (int64_t f = 0; f < gh.nf; ++f) {
+      const int32_t* id = &gh.nodes[16 * f];
+      for (int a = 0; a < 16 && id[a] >= 0; ++a)
+        for (int b = 0; b < 16 && id[b] >= 0; ++b) pairs.push_back((uint64_t(uint32_t(id[a])) << 32) | uint32_t(id[b]));
+    }
+  }
   m->max_support = npop ? 8 : 0;
   for (int64_t t = 0; t < m->n_straddle; ++t) {
     int32_t sup[kMaxPointLeaves * 8];
@@ -777,6 +800,38 @@ extern "C" int32_t octree_build(const mpm_refine_t* crit, const double* x, const
     }
   }
   for (int64_t a = 0; a < nn; ++a) m->max_deg = std::max<int32_t>(m->max_deg, int32_t(nb_off[a + 1] - nb_off[a]));
+  // ghost couplings: block column of every face node pair in the first node's row, and per
+  // node its (face, local index) contributions in ascending face order
+  std::vector<int16_t> gbpos(size_t(std::max<int64_t>(1, gh.nf)) * 256, 0);
+  std::vector<int32_t> gnode, gcon_off(1, 0), gcon;
+  if (gh.nf) {
+    std::vector<int32_t> gcnt(nn + 1, 0);
+    for (int64_t f = 0; f < gh.nf; ++f) {
+      const int32_t* id = &gh.nodes[16 * f];
+      for (int a = 0; a < 16 && id[a] >= 0; ++a) {
+        gcnt[id[a] + 1]++;
+        const uint64_t* lo = pairs.data() + nb_off[id[a]];
+        const uint64_t* hi = pairs.data() + nb_off[id[a] + 1];
+        for (int b = 0; b < 16 && id[b] >= 0; ++b) {
+          const uint64_t key = (uint64_t(uint32_t(id[a])) << 32) | uint32_t(id[b]);
+          gbpos[256 * f + 16 * a + b] = int16_t(std::lower_bound(lo, hi, key) - lo);
+        }
+      }
+    }
+    std::vector<int32_t> slot(nn, -1);
+    for (int64_t a = 0; a < nn; ++a)
+      if (gcnt[a + 1]) {
+        slot[a] = int32_t(gnode.size());
+        gnode.push_back(int32_t(a));
+        gcon_off.push_back(gcon_off.back() + gcnt[a + 1]);
+      }
+    gcon.resize(gcon_off.back());
+    std::vector<int32_t> gfill(gcon_off.begin(), gcon_off.end() - 1);
+    for (int64_t f = 0; f < gh.nf; ++f) {
+      const int32_t* id = &gh.nodes[16 * f];
+      for (int a = 0; a < 16 && id[a] >= 0; ++a) gcon[gfill[slot[id[a]]]++] = int32_t(16 * f + a);
+    }
+  }
   if (m->max_deg > 1024 || nl >= (int64_t(1) << 25)) {
     set_error(MPM_ESTENCIL, "octree_build: node row too wide or too many leaves for the gather");
     mpm_mesh_free(m);
@@ -796,6 +851,23 @@ extern "C" int32_t octree_build(const mpm_refine_t* crit, const double* x, const
   }
   if (!red2.empty()) {
     UP(m->d_red2, red2);
+  }
+  if (gh.nf) {
+    m->n_gface = gh.nf;
+    m->n_gnode = int64_t(gnode.size());
+    m->h_gface = gh.face;
+    UP(m->d_gf_leaf, gh.leaf2);
+    UP(m->d_gf_nodes, gh.nodes);
+    UP(m->d_gf_G, gh.G);
+    UP(m->d_gf_h, gh.h);
+    UP(m->d_gf_bpos, gbpos);
+    UP(m->d_gnode, gnode);
+    UP(m->d_gcon_off, gcon_off);
+    UP(m->d_gcon, gcon);
+    if (hipMalloc(&m->d_gbeta, size_t(nl) * 8) != hipSuccess) {
+      mpm_mesh_free(m);
+      return hip_fail(hipErrorOutOfMemory, "octree_build: ghost moduli");
+    }
   }
   if (hipMalloc(&m->d_segK, size_t(std::max<int64_t>(1, nrec)) * 576 * 8) != hipSuccess ||
       hipMalloc(&m->d_segF, size_t(std::max<int64_t>(1, nrec)) * 24 * 8) != hipSuccess) {
@@ -834,6 +906,16 @@ extern "C" int32_t mpm_mesh_info(const mpm_mesh_t* m, mpm_mesh_info_t* o) {
   o->lattice[1] = m->ny;
   o->lattice[2] = m->nz;
   o->h_min = m->hmin;
+  o->n_ghost_face = m->n_gface;
+  return MPM_OK;
+}
+
+extern "C" int32_t mpm_ghost_faces(const mpm_mesh_t* m, int32_t* out) {
+  if (!m || (!out && m->n_gface)) {
+    set_error(MPM_EARG, "mpm_ghost_faces: null argument");
+    return MPM_EARG;
+  }
+  if (m->n_gface) std::memcpy(out, m->h_gface.data(), m->h_gface.size() * sizeof(int32_t));
   return MPM_OK;
 }
 

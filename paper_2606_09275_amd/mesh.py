@@ -5,6 +5,8 @@ from __future__ import annotations
 import ctypes as C
 from typing import Optional
 
+import numpy as np
+
 import torch
 
 from . import _lib
@@ -30,7 +32,7 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def refine_struct(crit: dict) -> _lib.RefineT:
+def refine_struct(crit: dict, ghost: bool = False) -> _lib.RefineT:
     r = _lib.RefineT()
     r.lo = (C.c_double * 3)(*crit["lo"])
     r.base = (C.c_int32 * 3)(*crit["base"])
@@ -41,14 +43,17 @@ def refine_struct(crit: dict) -> _lib.RefineT:
     b = list(crit.get("body", ())) + [0.0] * (8 - len(crit.get("body", ())))
     r.body = (C.c_double * 8)(*b)
     r.dx_region = crit["dx_region"]
+    r.ghost = 1 if ghost else 0
     return r
 
 
 class Mesh:
-    """Octree mesh + point order + CSR pattern, owned by the HIP library."""
+    """Octree mesh + point order + CSR pattern, owned by the HIP library. ghost=True adds the
+    ghost stabilisation of Section 4 to every assembly on the mesh."""
 
-    def __init__(self, crit: dict, x: Optional[torch.Tensor] = None, l: Optional[torch.Tensor] = None):
-        self._crit = refine_struct(crit)
+    def __init__(self, crit: dict, x: Optional[torch.Tensor] = None, l: Optional[torch.Tensor] = None,
+                 ghost: bool = False):
+        self._crit = refine_struct(crit, ghost)
         self.crit = dict(crit)
         h = C.c_void_p()
         n = 0 if x is None else int(x.shape[1])
@@ -103,6 +108,12 @@ class Mesh:
                 "col": self._copy(a.col, (i["nnz"],), torch.int32),
             }
         return self._arrays
+
+    def ghost_faces(self) -> np.ndarray:
+        """[n_ghost_face, 8] int32: lo leaf, hi leaf, axis, plane, b0, b1, c0, c1 (lattice units)."""
+        out = np.zeros((self.info["n_ghost_face"], 8), dtype=np.int32)
+        check(lib().mpm_ghost_faces(self.h, out.ctypes.data_as(C.c_void_p)))
+        return out
 
     # -------------------------------------------------------------- point order
     def permute(self, src: torch.Tensor, perm: Optional[torch.Tensor] = None,

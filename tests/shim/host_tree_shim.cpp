@@ -2,7 +2,7 @@
 #include <cstring>
 #include <string>
 
-#include "../../paper_2606_09275_amd/csrc/internal.h"
+#include "../../paper_2606_09275_amd/csrc/geom.h"
 
 namespace mpm {
 int32_t build_tree(const mpm_refine_t& c, HostTree& T, int lat_out[3], double* hmin_out);
@@ -35,4 +35,35 @@ extern "C" void shim_arrays(int32_t* leaf, int32_t* node_ijk, int32_t* hang_ijk,
   std::memcpy(cell_nodes, g_tree.cell_nodes.data(), g_tree.cell_nodes.size() * 4);
   std::memcpy(cell_code, g_tree.cell_code.data(), g_tree.cell_code.size() * 4);
   std::memcpy(cell_cmat, g_tree.cell_cmat.data(), g_tree.cell_cmat.size() * 8);
+}
+
+// ghost faces of the last tree for the populated flags pop [n_leaf]; returns the face count
+static mpm::GhostHost g_ghost;
+extern "C" int64_t shim_ghost(const mpm_refine_t* c, const uint8_t* pop) {
+  int lat[3];
+  double hmin;
+  mpm::HostTree T;
+  if (mpm::build_tree(*c, T, lat, &hmin)) return -1;
+  mpm::LeafGeo G;
+  G.leaf = T.leaf.data();
+  G.leaf_key = T.leaf_key.data();
+  G.cellmap = nullptr;
+  G.n_leaf = int64_t(T.leaf_key.size());
+  for (int a = 0; a < 3; ++a) {
+    G.lo[a] = c->lo[a];
+    G.lat[a] = lat[a];
+  }
+  G.hmin = hmin;
+  G.lmax = c->lvl_max;
+  std::vector<uint8_t> p(pop, pop + G.n_leaf);
+  g_ghost = mpm::GhostHost();
+  return mpm::ghost_faces_host(T, G, p, &g_ghost);
+}
+
+extern "C" void shim_ghost_arrays(int32_t* face, int32_t* leaf2, int32_t* nodes, double* h, double* G) {
+  std::memcpy(face, g_ghost.face.data(), g_ghost.face.size() * 4);
+  std::memcpy(leaf2, g_ghost.leaf2.data(), g_ghost.leaf2.size() * 4);
+  std::memcpy(nodes, g_ghost.nodes.data(), g_ghost.nodes.size() * 4);
+  std::memcpy(h, g_ghost.h.data(), g_ghost.h.size() * 8);
+  std::memcpy(G, g_ghost.G.data(), g_ghost.G.size() * 8);
 }

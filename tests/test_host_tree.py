@@ -21,8 +21,10 @@ _lib = None
 def shim():
     global _lib
     if _lib is None:
-        srcs = [SHIM_SRC, ROOT / "paper_2606_09275_amd" / "csrc" / "octree_host.cpp"]
-        stale = not SHIM.exists() or any(s.stat().st_mtime > SHIM.stat().st_mtime for s in srcs)
+        srcs = [SHIM_SRC, ROOT / "paper_2606_09275_amd" / "csrc" / "octree_host.cpp",
+                ROOT / "paper_2606_09275_amd" / "csrc" / "ghost_host.cpp"]
+        deps = srcs + [ROOT / "paper_2606_09275_amd" / "csrc" / h for h in ("internal.h", "geom.h")]
+        stale = not SHIM.exists() or any(s.stat().st_mtime > SHIM.stat().st_mtime for s in deps)
         if stale:
             cmd = ["/opt/rocm/bin/hipcc", "-O2", "-std=c++17", "-fPIC", "-shared", "-x", "c++",
                    "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"] + [str(s) for s in srcs] + ["-o", str(SHIM)]
@@ -35,16 +37,22 @@ def shim():
 
 class Refine(C.Structure):
     _fields_ = [("lo", C.c_double * 3), ("base", C.c_int32 * 3), ("h0", C.c_double), ("lvl_base", C.c_int32),
-                ("lvl_max", C.c_int32), ("body_kind", C.c_int32), ("body", C.c_double * 8), ("dx_region", C.c_double)]
+                ("lvl_max", C.c_int32), ("body_kind", C.c_int32), ("body", C.c_double * 8), ("dx_region", C.c_double),
+                ("ghost", C.c_int32)]
 
 
-def host_tree(crit):
+def refine(crit):
     r = Refine()
     r.lo = (C.c_double * 3)(*crit["lo"])
     r.base = (C.c_int32 * 3)(*crit["base"])
     r.h0, r.lvl_base, r.lvl_max, r.body_kind = crit["h0"], crit["lvl_base"], crit["lvl_max"], crit["body_kind"]
     r.body = (C.c_double * 8)(*crit["body"])
     r.dx_region = crit["dx_region"]
+    return r
+
+
+def host_tree(crit):
+    r = refine(crit)
     cnt = np.zeros(3, np.int64)
     rc = shim().shim_build(C.byref(r), cnt.ctypes.data_as(C.c_void_p))
     assert rc == 0

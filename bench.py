@@ -248,6 +248,7 @@ def main():
     if not args.only:
         out["dynamic"] = dynamic_assembly(mesh, w, ps, views, u, f_ext, dirichlet, n)
         out["solve"] = newton_solve(mesh, views, u, f_ext, dirichlet, info)
+        out["ghost"] = ghost_stabilisation(w, x_dev, l_dev, views, u, f_ext, dirichlet, R["assemble_ms"])
     if "prev_x_s" in w.extra:
         out["protocol"] = tool_protocol(mesh, w, nodes, views, x_dev, perm_buf, leaf_buf, packed, sorted_buf,
                                         f_ext, dirichlet, lam)
@@ -281,6 +282,36 @@ def dynamic_assembly(mesh, w, ps, views, u, f_ext, dirichlet, n, reps=10, dt=1e-
                      "gather_kernel_ms": kt[4] / max(kt[5], 1), "assembly_points_per_s": n / (ms * 1e-3)}
     log(f"[bench] dynamic assembly: f64 {res['f64']['assembly_ms']:.3f} ms (kernel "
         f"{res['f64']['assemble_kernel_ms']:.3f}), f32k {res['f32k']['assembly_ms']:.3f} ms")
+    return res
+
+
+def ghost_stabilisation(w, x_dev, l_dev, views, u, f_ext, dirichlet, plain_ms, reps=10):
+    """The FP64 assembly on the same points with the ghost penalty of Section 4 (mesh built with
+    ghost faces): build time, face count, pattern growth, and mean ms of the assembly (HIP
+    events over reps calls) against the plain assembly's."""
+    import torch
+    from paper_2606_09275_amd.mesh import Mesh
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gm = Mesh(w.crit(), x_dev, l_dev, ghost=True)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    outs = {}
+    for _ in range(2):
+        gm.assemble(views, u, "f64", f_ext=f_ext, dirichlet=dirichlet, out=outs)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        gm.assemble(views, u, "f64", f_ext=f_ext, dirichlet=dirichlet, out=outs)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    res = {"n_ghost_face": gm.info["n_ghost_face"], "nnz": gm.info["nnz"], "octree_build_ms": build_ms,
+           "assemble_ms": ms, "plain_assemble_ms": plain_ms, "overhead_ms": ms - plain_ms}
+    log(f"[bench] ghost: {res['n_ghost_face']} faces, nnz {res['nnz']}, build {build_ms:.1f} ms, "
+        f"assemble {ms:.3f} ms (plain {plain_ms:.3f} ms)")
+    del gm
     return res
 
 

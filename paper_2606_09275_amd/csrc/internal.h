@@ -143,6 +143,7 @@ struct mpm_mesh {
   int32_t* d_gf_nodes = nullptr;    // n_gface x 16
   double* d_gf_G = nullptr;         // n_gface x 256
   double* d_gf_h = nullptr;         // n_gface: h_F / kappa
+  double* d_gf_sc = nullptr;        // n_gface: (h_F / kappa) beta_F of the current call
   int16_t* d_gf_bpos = nullptr;     // n_gface x 256
   int32_t* d_gnode = nullptr;       // n_gnode
   int32_t* d_gcon_off = nullptr;    // n_gnode + 1

@@ -5,7 +5,8 @@ whole and bit-exact. Floating-point outputs are compared on samples the oracle c
 exactly: the f_int entries and K rows of sampled nodes from an oracle run over every point
 whose support holds those nodes, sigma of sampled points, and the adjoint gradients of 64
 seeded points (against the oracle and central differences); over the whole vectors, the
-internal forces balance and the body forces sum to the total weight."""
+internal forces balance and the body forces sum to the total weight. The ghost stabilisation
+at full size: faces and pattern bit-exact, its stiffness and force against the oracle's."""
 import math
 
 import numpy as np
@@ -184,6 +185,41 @@ def test_c2_body_force_total(c2):
 
 
 # ---------------------------------------------------------------- moving-tool trail workload
+
+def test_c2_ghost_full_size(c2):
+    """Ghost stabilisation at full size: faces and the extended CSR pattern bit-exact against
+    the oracle; the library's assembly on the ghost mesh minus its assembly on the plain mesh
+    (the same point kernels on the same sorted state) against the oracle's K_G and K_G u."""
+    from paper_2606_09275_amd.mesh import Mesh
+    w, ps, m = c2["w"], c2["ps"], c2["m"]
+    og = OracleMesh(w.crit(), ghost=True)
+    og.set_points(ps.x, ps.l)
+    mg = Mesh(w.crit(), torch.from_numpy(ps.x).cuda(), torch.from_numpy(ps.l).cuda(), ghost=True)
+    faces = mg.ghost_faces()
+    log(f"[run] c2 ghost: {faces.shape[0]} faces, nnz {mg.info['nnz']} (plain {m.info['nnz']})")
+    assert faces.shape[0] > 0 and np.array_equal(faces, og.ghost_faces())
+    rp, col = og.csr()
+    ag = mg.arrays()
+    assert np.array_equal(to_np(ag["row_ptr"]), rp) and np.array_equal(to_np(ag["col"]), col)
+    g = og.ghost(c2["st"], c2["u"])
+    ud = torch.from_numpy(c2["u"]).cuda()
+    a = m.assemble(c2["s_dev"], ud, "f64", want_sigma=False)
+    b = mg.assemble(c2["s_dev"], ud, "f64", want_sigma=False)
+    torch.cuda.synchronize()
+    e_f = rel_err(to_np(b["f_int"]) - to_np(a["f_int"]), g["f"])
+    n_dof = m.info["n_dof"]
+    ap = m.arrays()
+    rp0, col0 = to_np(ap["row_ptr"]), to_np(ap["col"])
+    key0 = np.repeat(np.arange(n_dof, dtype=np.int64), np.diff(rp0)) * n_dof + col0
+    key1 = np.repeat(np.arange(n_dof, dtype=np.int64), np.diff(rp)) * n_dof + col
+    pos = np.searchsorted(key1, key0)
+    assert np.array_equal(key1[pos], key0)
+    Kd = to_np(b["K"]).copy()
+    Kd[pos] -= to_np(a["K"])
+    e_k = rel_err(Kd, g["K"])
+    log(f"[parity] c2 ghost full: K_G={e_k:.2e} K_G u={e_f:.2e}")
+    assert e_k <= 1e-10 and e_f <= 1e-10
+
 
 @pytest.fixture(scope="module")
 def c4():

@@ -100,6 +100,10 @@ int32_t orc_inertia(const orc_mesh* m, const orc_state* s, const double* u, cons
                     double* f_iner, double* K, double* a_new, double* v_new, int64_t* bad_index);
 /* ghost term: K += K_G (may be NULL), f += K_G u (may be NULL), beta_leaf [n_leaf] = max E of
  * the points overlapping each leaf (may be NULL) */
+/* GIMP refinement criterion (Section 5): split[p] = 1 when a leaf overlapped by point p's domain
+ * has half side < beta * (largest half side of the domain); bad = first failing point */
+int32_t orc_split_mark(const orc_mesh* m, const double* x, const double* l, int64_t n, double beta, uint8_t* split,
+                       int64_t* bad);
 int32_t orc_ghost_assemble(const orc_mesh* m, const orc_state* s, const double* u, double* K, double* f,
                            double* beta_leaf);
 /* r = f_int - f_ext with dirichlet DOFs zeroed; returns ||r||_2 in *rnorm */

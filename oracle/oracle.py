@@ -14,7 +14,7 @@ import numpy as np
 
 HERE = Path(__file__).resolve().parent
 LIB = HERE / "liboracle.so"
-SOURCES = ["orc_mesh.c", "orc_point.c", "orc_ghost.c"]
+SOURCES = ["orc_mesh.c", "orc_point.c", "orc_ghost.c", "orc_split.c"]
 
 _i64 = np.int64
 _f64 = np.float64
@@ -78,6 +78,8 @@ def lib():
         L.orc_ghost_faces.argtypes = [vp, vp]
         L.orc_ghost_assemble.restype = C.c_int32
         L.orc_ghost_assemble.argtypes = [vp, C.POINTER(_State), vp, vp, vp, vp]
+        L.orc_split_mark.restype = C.c_int32
+        L.orc_split_mark.argtypes = [vp, vp, vp, C.c_int64, C.c_double, vp, i64p]
         L.orc_inertia.restype = C.c_int32
         L.orc_inertia.argtypes = [vp, C.POINTER(_State), vp, vp, C.c_double, vp, vp, vp, vp, i64p]
         L.orc_residual.argtypes = [C.c_int64, vp, vp, vp, vp, vp]
@@ -144,6 +146,17 @@ class OracleMesh:
         if code != 0:
             raise OracleError(code)
         return dict(K=K, f=f, beta=beta)
+
+    def split_mark(self, x: np.ndarray, l: np.ndarray, beta: float = 2.0) -> np.ndarray:
+        """GIMP refinement criterion (Section 5) for points x, l [3][n] (any order): uint8 flags."""
+        x = np.ascontiguousarray(x, dtype=_f64)
+        l = np.ascontiguousarray(l, dtype=_f64)
+        out = np.zeros(x.shape[1], np.uint8)
+        bad = C.c_int64(-1)
+        code = lib().orc_split_mark(self.h, _p(x), _p(l), x.shape[1], float(beta), _p(out), C.byref(bad))
+        if code != 0:
+            raise OracleError(code, bad.value)
+        return out
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -248,6 +248,49 @@ int32_t mpm_solve_cg(const mpm_mesh_t* mesh, int32_t precision, const void* K_va
                      const double* b, double* x, double rtol, int32_t max_iter, int32_t* iters, double* relres,
                      void* stream);
 
+/* GIMP refinement criterion of the adaptive strategy (Section 5): split[p] = 1 when a leaf that
+ * point p's domain overlaps with positive volume has half side l_K < beta l_p, l_p the largest
+ * of the domain's three half sides (the paper uses beta = 2). The mesh gives the leaves only
+ * (it may have been built without points); x, l: [3][n] device, any order; split: [n] device
+ * uint8, written; *n_split (host): number of points flagged. Errors: MPM_EARG (null argument,
+ * beta not positive and finite), MPM_ENONFINITE, MPM_EOUTSIDE, MPM_ESTENCIL (a domain over more
+ * than 4096 lattice cells of the finest level whose leaves do not trigger the split; only
+ * possible for beta well below 2), with the first such point. */
+int32_t mpm_split_mark(const mpm_mesh_t* mesh, const double* x, const double* l, int64_t n, double beta,
+                       uint8_t* split, int64_t* n_split, void* stream);
+
+/* Output state of mpm_split_apply: device [c][n_out] arrays, same fields as mpm_state_t. */
+typedef struct {
+  double* x;
+  double* l;
+  double* vol;
+  double* mass;
+  double* Jn;
+  double* bn;
+  double* Fn;
+  double* E;
+  double* nu;
+  double* sy;
+} mpm_state_out_t;
+
+/* Splits the flagged GIMPs (Section 5, transfer of GIMP data). Point p with split[p] != 0
+ * becomes 8 GIMPs tiling its domain: child c (bit a of c for axis a) is centred at
+ * x_a - l_a / 2 (bit clear) or x_a + l_a / 2 (bit set), with half sides l / 2 and volume and
+ * mass / 8; J_n, b_n, F_n, velocity and material parameters are copied. With the reference
+ * positions X (X_in/X_out), each child gets X + F_n^{-1} (x_c - x), and a material parameter
+ * selected by prop_mask (bit 0 E, bit 1 nu, bit 2 sy) is evaluated there as
+ * props[4r] + props[4r+1] X_1 + props[4r+2] X_2 + props[4r+3] X_3 (props: host [3][4]) rather
+ * than copied. Unflagged points are copied. The output keeps the input order: a point, or its
+ * 8 children in child order.
+ *   in: x, l, vol, mass required; Jn, bn, Fn, E, nu, sy optional, each paired with the same
+ *   field of out (both NULL or both set); X_in/X_out and v_in/v_out optional pairs [3][n]
+ *   (X_in needs Fn);
+ *   n_out must equal n + 7 * (number of flagged points). Inputs and outputs must not overlap.
+ * A work buffer of 8 (n / 256 + 2) bytes is kept with the mesh. */
+int32_t mpm_split_apply(const mpm_mesh_t* mesh, int64_t n, const uint8_t* split, const mpm_state_t* in,
+                        const double* X_in, const double* v_in, const double* props, int32_t prop_mask,
+                        const mpm_state_out_t* out, double* X_out, double* v_out, int64_t n_out, void* stream);
+
 /* Kernel timing for measurement tools. enable = 1: from now on HIP events bracket the fused
  * assembly kernel (single-leaf points), the row-gather kernel that writes f_int and K, and
  * the adjoint kernel on the caller's stream, and their elapsed times accumulate in the handle

@@ -42,7 +42,7 @@ typedef struct orc_mesh orc_mesh;
 
 #define ORC_MAXI 27     /* max |I(K)| accepted */
 #define ORC_MAXS 128    /* max support size of one point */
-#define ORC_MAXL 64     /* max leaves overlapped by one point domain */
+#define ORC_MAXL 1024   /* max leaves overlapped by one point domain */
 
 orc_mesh* orc_mesh_build(const orc_crit* c, int32_t* status);
 void orc_mesh_free(orc_mesh* m);

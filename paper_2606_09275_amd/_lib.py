@@ -18,6 +18,10 @@ class RefineT(C.Structure):
                 ("ghost", C.c_int32)]
 
 
+class StateOutT(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("x", "l", "vol", "mass", "Jn", "bn", "Fn", "E", "nu", "sy")]
+
+
 class MeshInfoT(C.Structure):
     _fields_ = [("n_leaf", C.c_int64), ("n_node", C.c_int64), ("n_hang", C.c_int64), ("n_dof", C.c_int64),
                 ("nnz", C.c_int64), ("n_point", C.c_int64), ("n_straddle", C.c_int64),
@@ -83,6 +87,11 @@ def lib():
     L.mpm_assemble_dynamic.restype = i32
     L.mpm_assemble_dynamic.argtypes = [vp, C.POINTER(StateT), vp, vp, C.c_double, i32, vp, vp, vp, vp, vp, vp, vp,
                                        vp, vp, vp]
+    L.mpm_split_mark.restype = i32
+    L.mpm_split_mark.argtypes = [vp, vp, vp, i64, C.c_double, vp, C.POINTER(i64), vp]
+    L.mpm_split_apply.restype = i32
+    L.mpm_split_apply.argtypes = [vp, i64, vp, C.POINTER(StateT), vp, vp, vp, i32, C.POINTER(StateOutT), vp, vp,
+                                  i64, vp]
     L.mpm_kernel_timing.restype = i32
     L.mpm_kernel_timing.argtypes = [vp, i32, vp]
     L.mpm_last_error.restype = i32
@@ -95,7 +104,7 @@ def lib():
 
 EXPORTED = ["octree_build", "mpm_mesh_info", "mpm_mesh_arrays", "mpm_ghost_faces", "mpm_mesh_free", "mpm_point_sort", "mpm_permute",
             "mpm_external_force", "mpm_assemble", "mpm_assemble_dynamic", "mpm_assemble_adjoint", "mpm_spmv",
-            "mpm_solve_cg", "mpm_kernel_timing", "mpm_last_error",
+            "mpm_solve_cg", "mpm_split_mark", "mpm_split_apply", "mpm_kernel_timing", "mpm_last_error",
             "mpm_last_error_index"]
 
 

@@ -11,9 +11,6 @@
 
 namespace mpm {
 
-int32_t read_error(mpm_mesh* m, hipStream_t st, const char* what);
-LeafGeo make_geo(const mpm_mesh* m);
-
 struct AsmArgs {
   LeafGeo G;
   const int32_t* cell_nodes;

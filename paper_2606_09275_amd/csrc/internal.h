@@ -133,6 +133,9 @@ struct mpm_mesh {
   size_t cg_bytes = 0;
   void* h_cg = nullptr;             // pinned host copy of the solver flags and scalars
   hipEvent_t cg_ev = nullptr;
+  void* d_split = nullptr;          // GIMP split: per-block counts and their scan
+  size_t split_bytes = 0;
+  int64_t* h_word = nullptr;        // pinned host copy of one device word (counts)
   // ghost stabilisation (enabled by mpm_refine_t.ghost): faces, their node unions and jump
   // matrices; the nodes with ghost couplings and, per node, its (face * 16 + local index)
   // contributions in ascending face order; the block column of every face node pair in the
@@ -158,6 +161,13 @@ struct mpm_mesh {
 
 namespace mpm {
 struct LeafGeo;
+LeafGeo make_geo(const mpm_mesh* m);
+// copies the device error word to the host; sets the message and returns its code
+int32_t read_error(mpm_mesh* m, hipStream_t st, const char* what);
+// grows a work buffer of the mesh to at least `bytes` (old contents dropped)
+int32_t ensure_buffer(void** buf, size_t* have, size_t bytes, hipStream_t st, const char* what);
+// copies one device int64 to the host (ordered on st, waits for it)
+int32_t read_word(mpm_mesh* m, const int64_t* d, int64_t* out, hipStream_t st, const char* what);
 // ghost faces of the populated flags pop (host leaf geometry G: leaf and key arrays of T)
 int64_t ghost_faces_host(const HostTree& T, const LeafGeo& G, const std::vector<uint8_t>& pop, GhostHost* out);
 // adds the ghost form's stiffness to K (precision's type) and K_G u to f on stream st

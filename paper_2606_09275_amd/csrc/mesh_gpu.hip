@@ -411,9 +411,22 @@ int32_t read_error(mpm_mesh* m, hipStream_t st, const char* what) {
   return MPM_OK;
 }
 
+int32_t read_word(mpm_mesh* m, const int64_t* d, int64_t* out, hipStream_t st, const char* what) {
+  if (!m->h_word) MPM_HIP(hipHostMalloc((void**)&m->h_word, sizeof(int64_t), hipHostMallocDefault));
+  if (!m->err_ev) MPM_HIP(hipEventCreateWithFlags(&m->err_ev, hipEventDisableTiming));
+  MPM_HIP(hipMemcpyAsync(m->h_word, d, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  MPM_HIP(hipEventRecord(m->err_ev, st));
+  hipError_t q;
+  while ((q = hipEventQuery(m->err_ev)) == hipErrorNotReady) {
+  }
+  if (q != hipSuccess) return hip_fail(q, what);
+  *out = *m->h_word;
+  return MPM_OK;
+}
+
 // Grows a work buffer of the mesh to at least `bytes` (the old contents are dropped). The
 // stream is drained first: work already queued may still read the old buffer.
-static int32_t ensure_buffer(void** buf, size_t* have, size_t bytes, hipStream_t st, const char* what) {
+int32_t ensure_buffer(void** buf, size_t* have, size_t bytes, hipStream_t st, const char* what) {
   if (*have >= bytes && *buf) return MPM_OK;
   MPM_HIP(hipStreamSynchronize(st));
   if (*buf) MPM_HIP(hipFree(*buf));
@@ -488,7 +501,7 @@ extern "C" void mpm_mesh_free(mpm_mesh_t* m) {
                   m->d_hang_ijk, m->d_hang_sup, m->d_hang_w, m->d_hang_owner, m->d_perm, m->d_pleaf, m->d_pnleaf,
                   m->d_row_ptr, m->d_col, m->d_wave_seg, m->d_leaf_seg0, m->d_leaf_nseg, m->d_con_off, m->d_con_seg, m->d_con_bp, m->d_bpos,
                   m->d_segK, m->d_segF, m->d_red1, m->d_red2, m->d_strad, m->d_strad_leaf, m->d_err,
-                  m->d_partial, m->d_scratch, m->d_stage, m->d_cellmap, m->d_cg, m->d_gf_leaf, m->d_gf_nodes,
+                  m->d_partial, m->d_scratch, m->d_stage, m->d_cellmap, m->d_cg, m->d_split, m->d_gf_leaf, m->d_gf_nodes,
                   m->d_gf_G, m->d_gf_h, m->d_gf_sc, m->d_gf_bpos, m->d_gnode, m->d_gcon_off, m->d_gcon, m->d_gbeta};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -497,6 +510,7 @@ extern "C" void mpm_mesh_free(mpm_mesh_t* m) {
   if (m->h_err) (void)hipHostFree(m->h_err);
   if (m->err_ev) (void)hipEventDestroy(m->err_ev);
   if (m->h_cg) (void)hipHostFree(m->h_cg);
+  if (m->h_word) (void)hipHostFree(m->h_word);
   if (m->cg_ev) (void)hipEventDestroy(m->cg_ev);
   delete m;
 }

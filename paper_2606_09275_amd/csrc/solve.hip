@@ -12,8 +12,6 @@
 
 namespace mpm {
 
-int32_t read_error(mpm_mesh* m, hipStream_t st, const char* what);
-
 constexpr int kSpmvNodes = 4;    // nodes per workgroup, one wavefront per node
 constexpr int kDotBlocks = 512;  // partial sums of a dot product
 

@@ -163,6 +163,47 @@ class Mesh:
         st.g = (C.c_double * 3)(*s.get("g", (0.0, 0.0, -9.81)))
         return st
 
+    # -------------------------------------------------------------- GIMP refinement
+    def split_mark(self, x: torch.Tensor, l: torch.Tensor, beta: float = 2.0, out: Optional[torch.Tensor] = None):
+        """mpm_split_mark: uint8 flags [n] of the points to split and their count."""
+        n = int(x.shape[1])
+        flags = torch.empty(n, dtype=torch.uint8, device="cuda") if out is None else out
+        cnt = C.c_int64(0)
+        check(lib().mpm_split_mark(self.h, _ptr(x), _ptr(l), n, float(beta), _ptr(flags), C.byref(cnt), _stream()))
+        return flags, int(cnt.value)
+
+    SPLIT_FIELDS = {"x": 3, "l": 3, "vol": 1, "mass": 1, "Jn": 1, "bn": 6, "Fn": 9, "E": 1, "nu": 1, "sy": 1}
+
+    def split_apply(self, s: dict, flags: torch.Tensor, n_split: int, X: Optional[torch.Tensor] = None,
+                    v: Optional[torch.Tensor] = None, props: Optional[dict] = None) -> dict:
+        """mpm_split_apply: new per-point arrays ([c][n_out] / [n_out]) of the fields present in s,
+        plus "X" and "v" when given; props {"E"|"nu"|"sy": (a0, a1, a2, a3)} evaluates those
+        parameters at the children's reference positions."""
+        n = int(flags.shape[0])
+        n_out = n + 7 * int(n_split)
+        o = {}
+        so = _lib.StateOutT()
+        for k, c in self.SPLIT_FIELDS.items():
+            if s.get(k) is None:
+                continue
+            shape = (c, n_out) if c > 1 else (n_out,)
+            o[k] = torch.empty(shape, dtype=torch.float64, device="cuda")
+            setattr(so, k, _ptr(o[k]).value)
+        if X is not None:
+            o["X"] = torch.empty((3, n_out), dtype=torch.float64, device="cuda")
+        if v is not None:
+            o["v"] = torch.empty((3, n_out), dtype=torch.float64, device="cuda")
+        mask, coef = 0, [0.0] * 12
+        for r, name in enumerate(("E", "nu", "sy")):
+            if props and name in props:
+                mask |= 1 << r
+                coef[4 * r:4 * r + 4] = [float(a) for a in props[name]]
+        cbuf = (C.c_double * 12)(*coef)
+        st = self._state(s)
+        check(lib().mpm_split_apply(self.h, n, _ptr(flags), C.byref(st), _ptr(X), _ptr(v), cbuf, mask, C.byref(so),
+                                    _ptr(o.get("X")), _ptr(o.get("v")), n_out, _stream()))
+        return o
+
     def external_force(self, s: dict, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         out = torch.empty(self.info["n_dof"], dtype=torch.float64, device="cuda") if out is None else out
         st = self._state(s)

@@ -41,6 +41,16 @@ __host__ __device__ inline uint64_t spread3(uint64_t v) {
 __host__ __device__ inline uint64_t morton(uint64_t x, uint64_t y, uint64_t z) {
   return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
 }
+// inverse of spread3: bits 3b of v back to bit b
+__host__ __device__ inline uint64_t compact3(uint64_t v) {
+  v &= 0x1249249249249249ull;
+  v = (v ^ (v >> 2)) & 0x10c30c30c30c30c3ull;
+  v = (v ^ (v >> 4)) & 0x100f00f00f00f00full;
+  v = (v ^ (v >> 8)) & 0x1f0000ff0000ffull;
+  v = (v ^ (v >> 16)) & 0x1f00000000ffffull;
+  v = (v ^ (v >> 32)) & 0x1fffffull;
+  return v;
+}
 
 constexpr int kMaxPointLeaves = 8; // leaves a point domain may overlap (one boundary per axis)
 
@@ -168,6 +178,46 @@ int32_t read_error(mpm_mesh* m, hipStream_t st, const char* what);
 int32_t ensure_buffer(void** buf, size_t* have, size_t bytes, hipStream_t st, const char* what);
 // copies one device int64 to the host (ordered on st, waits for it)
 int32_t read_word(mpm_mesh* m, const int64_t* d, int64_t* out, hipStream_t st, const char* what);
+
+// Stable LSD radix sort of (keys, vals) by the low `bits` bits of the 32-bit keys, 8-bit
+// digits over tiles of kRsTile elements; ktmp/vtmp: n-element work arrays, hist: 256 x
+// (tiles) counts, tot: 256 totals. The result ends in whichever buffer the last pass wrote.
+constexpr int kRsThreads = 256;
+constexpr int kRsRounds = 16;
+constexpr int kRsTile = kRsThreads * kRsRounds;
+int32_t radix_sort(uint32_t* keys, uint32_t* vals, int64_t n, int bits, uint32_t* ktmp, uint32_t* vtmp, uint32_t* hist,
+                   uint32_t* tot, hipStream_t st, uint32_t** kres, uint32_t** vres);
+
+// Device work buffer owned by one construction step (freed on scope exit).
+struct DevBuf {
+  void* p = nullptr;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  int32_t alloc(size_t bytes, const char* what) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    const hipError_t e = hipMalloc(&p, bytes ? bytes : 8);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return hip_fail(e, what);
+    }
+    return MPM_OK;
+  }
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+// exclusive scan of n int32 counts into int64 offsets: out[i] = sum of in[0..i), out[n] =
+// the total (out: n + 1 entries)
+int32_t scan_counts(const int32_t* in, int64_t n, int64_t* out, hipStream_t st);
+// sorts n 64-bit keys in place by their low `bits` bits (stable two-stage LSD radix)
+int32_t sort_u64(uint64_t* keys, int64_t n, int bits, hipStream_t st);
 // ghost faces of the populated flags pop (host leaf geometry G: leaf and key arrays of T)
 int64_t ghost_faces_host(const HostTree& T, const LeafGeo& G, const std::vector<uint8_t>& pop, GhostHost* out);
 // adds the ghost form's stiffness to K (precision's type) and K_G u to f on stream st

@@ -24,7 +24,7 @@ int32_t hip_fail(hipError_t e, const char* what) {
   return MPM_EHIP;
 }
 
-int32_t build_tree(const mpm_refine_t& c, HostTree& T, int lat_out[3], double* hmin_out);
+int32_t gpu_build_tree(mpm_mesh* m, const mpm_refine_t& c, hipStream_t st);
 
 // ------------------------------------------------------------------ point keys
 // key = rank of the leaf containing the point's centre, value = original index; a stable
@@ -70,9 +70,6 @@ __global__ __launch_bounds__(256) void k_fill_cellmap(const int32_t* __restrict_
 // 8-bit digits; 32-bit keys with 32-bit values. Per pass: per-tile digit counts, one scan
 // per digit over the tiles, then a scatter that ranks equal digits inside each wavefront
 // with ballots (stable: tiles, wavefronts and lanes keep their input order).
-constexpr int kRsThreads = 256;
-constexpr int kRsRounds = 16;
-constexpr int kRsTile = kRsThreads * kRsRounds;
 
 __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
                                                         uint32_t* __restrict__ hist) {
@@ -205,8 +202,8 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* __res
 
 // sorts (keys, vals) by the low `bits` bits of keys; the result ends in whichever of the
 // two buffers the last pass wrote, returned through *kres / *vres
-static int32_t radix_sort(uint32_t* keys, uint32_t* vals, int64_t n, int bits, uint32_t* ktmp, uint32_t* vtmp,
-                          uint32_t* hist, uint32_t* tot, hipStream_t st, uint32_t** kres, uint32_t** vres) {
+int32_t radix_sort(uint32_t* keys, uint32_t* vals, int64_t n, int bits, uint32_t* ktmp, uint32_t* vtmp, uint32_t* hist,
+                   uint32_t* tot, hipStream_t st, uint32_t** kres, uint32_t** vres) {
   uint32_t *ka = keys, *kb = ktmp;
   uint32_t *va = vals, *vb = vtmp;
   if (n > 1) {
@@ -523,41 +520,46 @@ extern "C" int32_t octree_build(const mpm_refine_t* crit, const double* x, const
   }
   *out_mesh = nullptr;
   hipStream_t st = (hipStream_t)stream;
-  HostTree T;
-  int lat[3];
-  double hmin;
-  int32_t rc = build_tree(*crit, T, lat, &hmin);
-  if (rc) return rc;
   mpm_mesh* m = new mpm_mesh();
   m->crit = *crit;
-  m->nx = lat[0];
-  m->ny = lat[1];
-  m->nz = lat[2];
-  m->hmin = hmin;
-  m->n_leaf = int64_t(T.leaf_key.size());
-  m->n_node = int64_t(T.node_ijk.size() / 3);
-  m->n_hang = int64_t(T.hang_owner.size());
+  if (hipMalloc(&m->d_err, sizeof(DevErr)) != hipSuccess || hipMemsetAsync(m->d_err, 0, sizeof(DevErr), st) != hipSuccess) {
+    mpm_mesh_free(m);
+    return hip_fail(hipErrorOutOfMemory, "octree_build: error word");
+  }
+  int32_t rc = gpu_build_tree(m, *crit, st);
+  if (rc) {
+    mpm_mesh_free(m);
+    return rc;
+  }
   while ((int64_t(1) << m->leaf_bits) < m->n_leaf + 1) ++m->leaf_bits;
   if (m->leaf_bits > 31) {
     set_error(MPM_ESTENCIL, "octree_build: too many leaves for 32-bit point keys");
     mpm_mesh_free(m);
     return MPM_ESTENCIL;
   }
+  // host copies of the tree arrays that the host part of the construction reads
+  HostTree T;
+  {
+    T.cell_nodes.resize(size_t(m->n_leaf) * 8);
+    hipError_t e = hipMemcpy(T.cell_nodes.data(), m->d_cell_nodes, T.cell_nodes.size() * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && crit->ghost) {
+      T.leaf.resize(size_t(m->n_leaf) * 4);
+      T.leaf_key.resize(size_t(m->n_leaf));
+      T.cell_cmat.resize(size_t(m->n_leaf) * 64);
+      e = hipMemcpy(T.leaf.data(), m->d_leaf, T.leaf.size() * 4, hipMemcpyDeviceToHost);
+      if (e == hipSuccess) e = hipMemcpy(T.leaf_key.data(), m->d_leaf_key, T.leaf_key.size() * 8, hipMemcpyDeviceToHost);
+      if (e == hipSuccess) e = hipMemcpy(T.cell_cmat.data(), m->d_cell_cmat, T.cell_cmat.size() * 8, hipMemcpyDeviceToHost);
+    }
+    if (e != hipSuccess) {
+      mpm_mesh_free(m);
+      return hip_fail(e, "octree_build: tree download");
+    }
+  }
 #define UP(dst, v)                     \
   if ((rc = upload(&(dst), v, st))) { \
     mpm_mesh_free(m);                  \
     return rc;                         \
   }
-  UP(m->d_leaf, T.leaf);
-  UP(m->d_leaf_key, T.leaf_key);
-  UP(m->d_cell_nodes, T.cell_nodes);
-  UP(m->d_cell_code, T.cell_code);
-  UP(m->d_cell_cmat, T.cell_cmat);
-  UP(m->d_node_ijk, T.node_ijk);
-  UP(m->d_hang_ijk, T.hang_ijk);
-  UP(m->d_hang_sup, T.hang_sup);
-  UP(m->d_hang_w, T.hang_w);
-  UP(m->d_hang_owner, T.hang_owner);
   // dense leaf map of the finest cells when it takes at most 1 GiB (else the leaf search
   // bisects the sorted leaf keys)
   const int64_t ncell = int64_t(m->nx) * m->ny * m->nz;
@@ -569,10 +571,6 @@ extern "C" int32_t octree_build(const mpm_refine_t* crit, const double* x, const
     }
     hipLaunchKernelGGL(k_fill_cellmap, dim3(unsigned(m->n_leaf)), dim3(256), 0, st, m->d_leaf, crit->lvl_max, m->nx,
                        m->ny, m->d_cellmap);
-  }
-  if (hipMalloc(&m->d_err, sizeof(DevErr)) != hipSuccess || hipMemsetAsync(m->d_err, 0, sizeof(DevErr), st) != hipSuccess) {
-    mpm_mesh_free(m);
-    return hip_fail(hipErrorOutOfMemory, "octree_build: error word");
   }
   m->n_point = n;
   std::vector<int32_t> pleaf;

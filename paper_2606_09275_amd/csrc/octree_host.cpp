@@ -20,16 +20,6 @@ namespace {
 
 constexpr double kTie = 1e-12;  // relative slack: ties of distance predicates count as inside
 
-uint64_t compact3(uint64_t v) {
-  v &= 0x1249249249249249ull;
-  v = (v ^ (v >> 2)) & 0x10c30c30c30c30c3ull;
-  v = (v ^ (v >> 4)) & 0x100f00f00f00f00full;
-  v = (v ^ (v >> 8)) & 0x1f0000ff0000ffull;
-  v = (v ^ (v >> 16)) & 0x1f00000000ffffull;
-  v = (v ^ (v >> 32)) & 0x1fffffull;
-  return v;
-}
-
 // squared distance from (r, z) in the meridian half-plane to segment p0-p1
 double seg_dist2(double r, double z, double r0, double z0, double r1, double z1) {
   const double er = r1 - r0, ez = z1 - z0;

@@ -59,14 +59,11 @@ __host__ __device__ inline int code_hmask(int32_t code) { return code & 0xff; }
 __host__ __device__ inline int code_child(int32_t code) { return (code >> 8) & 7; }
 
 // ------------------------------------------------------------------ mesh handle
+// host copies of tree arrays that host-side construction steps read
 struct HostTree {
   std::vector<int32_t> leaf;       // n_leaf x 4, Morton order
   std::vector<uint64_t> leaf_key;  // Morton key of anchors
-  std::vector<int32_t> node_ijk;   // independent nodes x 3
-  std::vector<int32_t> hang_ijk, hang_sup, hang_owner;
-  std::vector<double> hang_w;
   std::vector<int32_t> cell_nodes; // n_leaf x 8
-  std::vector<int32_t> cell_code;  // n_leaf
   std::vector<double> cell_cmat;   // n_leaf x 8 x 8: C_K[vertex][slot]
 };
 

@@ -1,61 +1,39 @@
-// Test shim: exposes the library's host octree construction (no GPU calls) to CPU tests.
+// Test shim: exposes the library's host-side ghost-face builder (no GPU calls) to CPU tests.
+// The tree arrays come from the caller (leaf anchors and levels in Morton order, anchor keys,
+// 8 slot nodes and the 8 x 8 constraint matrix C[vertex][slot] of every leaf).
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../paper_2606_09275_amd/csrc/geom.h"
 
 namespace mpm {
-int32_t build_tree(const mpm_refine_t& c, HostTree& T, int lat_out[3], double* hmin_out);
 void set_error(int32_t, const std::string&, int64_t) {}
 int32_t hip_fail(hipError_t, const char*) { return MPM_EHIP; }
 }  // namespace mpm
 
-static mpm::HostTree g_tree;
-
-extern "C" int32_t shim_build(const mpm_refine_t* c, int64_t* counts) {
-  g_tree = mpm::HostTree();
-  int lat[3];
-  double hmin;
-  int32_t rc = mpm::build_tree(*c, g_tree, lat, &hmin);
-  if (rc) return rc;
-  counts[0] = int64_t(g_tree.leaf_key.size());
-  counts[1] = int64_t(g_tree.node_ijk.size() / 3);
-  counts[2] = int64_t(g_tree.hang_owner.size());
-  return 0;
-}
-
-extern "C" void shim_arrays(int32_t* leaf, int32_t* node_ijk, int32_t* hang_ijk, int32_t* hang_sup, double* hang_w,
-                            int32_t* hang_owner, int32_t* cell_nodes, int32_t* cell_code, double* cell_cmat) {
-  std::memcpy(leaf, g_tree.leaf.data(), g_tree.leaf.size() * 4);
-  std::memcpy(node_ijk, g_tree.node_ijk.data(), g_tree.node_ijk.size() * 4);
-  std::memcpy(hang_ijk, g_tree.hang_ijk.data(), g_tree.hang_ijk.size() * 4);
-  std::memcpy(hang_sup, g_tree.hang_sup.data(), g_tree.hang_sup.size() * 4);
-  std::memcpy(hang_w, g_tree.hang_w.data(), g_tree.hang_w.size() * 8);
-  std::memcpy(hang_owner, g_tree.hang_owner.data(), g_tree.hang_owner.size() * 4);
-  std::memcpy(cell_nodes, g_tree.cell_nodes.data(), g_tree.cell_nodes.size() * 4);
-  std::memcpy(cell_code, g_tree.cell_code.data(), g_tree.cell_code.size() * 4);
-  std::memcpy(cell_cmat, g_tree.cell_cmat.data(), g_tree.cell_cmat.size() * 8);
-}
-
-// ghost faces of the last tree for the populated flags pop [n_leaf]; returns the face count
 static mpm::GhostHost g_ghost;
-extern "C" int64_t shim_ghost(const mpm_refine_t* c, const uint8_t* pop) {
-  int lat[3];
-  double hmin;
+
+extern "C" int64_t shim_ghost(int64_t nl, const int32_t* leaf, const uint64_t* leaf_key, const int32_t* cell_nodes,
+                              const double* cell_cmat, const double* lo, double hmin, int32_t lmax, const int32_t* lat,
+                              const uint8_t* pop) {
   mpm::HostTree T;
-  if (mpm::build_tree(*c, T, lat, &hmin)) return -1;
+  T.leaf.assign(leaf, leaf + 4 * nl);
+  T.leaf_key.assign(leaf_key, leaf_key + nl);
+  T.cell_nodes.assign(cell_nodes, cell_nodes + 8 * nl);
+  T.cell_cmat.assign(cell_cmat, cell_cmat + 64 * nl);
   mpm::LeafGeo G;
   G.leaf = T.leaf.data();
   G.leaf_key = T.leaf_key.data();
   G.cellmap = nullptr;
-  G.n_leaf = int64_t(T.leaf_key.size());
+  G.n_leaf = nl;
   for (int a = 0; a < 3; ++a) {
-    G.lo[a] = c->lo[a];
+    G.lo[a] = lo[a];
     G.lat[a] = lat[a];
   }
   G.hmin = hmin;
-  G.lmax = c->lvl_max;
-  std::vector<uint8_t> p(pop, pop + G.n_leaf);
+  G.lmax = lmax;
+  std::vector<uint8_t> p(pop, pop + nl);
   g_ghost = mpm::GhostHost();
   return mpm::ghost_faces_host(T, G, p, &g_ghost);
 }

@@ -1,9 +1,12 @@
-"""Host part of the ghost stabilisation (Section 4) on CPU through the test shim: the library's
-ghost faces equal the oracle's bit for bit, and its per-face jump matrices (2 x 2 Gauss rule)
-reproduce the oracle's penalty (3 x 3 Gauss rule, assembled into the CSR) as a quadratic form
-u . K_G u on random displacements, on meshes with hanging nodes, jittered points and a varying
-Young's modulus. No GPU call is made."""
+"""Host part of the ghost stabilisation (Section 4) on CPU through a test shim: the library's
+ghost-face builder, given the oracle's tree (leaves, I(K) and C_K), finds the oracle's ghost
+faces bit for bit, and its per-face jump matrices (2 x 2 Gauss rule) reproduce the oracle's
+penalty (3 x 3 Gauss rule, assembled into the CSR) as a quadratic form u . K_G u on random
+displacements, on meshes with hanging nodes, jittered points and a varying Young's modulus.
+No GPU call is made."""
 import ctypes as C
+import subprocess
+from pathlib import Path
 
 import numpy as np
 import pytest
@@ -11,8 +14,40 @@ import scipy.sparse as sp
 
 import workloads as W
 from oracle.oracle import OracleMesh
-from tests.helpers import tiny_workload
-from tests.test_host_tree import refine, shim
+from tests.helpers import morton3_np, tiny_workload
+
+ROOT = Path(__file__).resolve().parent.parent
+SHIM_SRC = ROOT / "tests" / "shim" / "host_tree_shim.cpp"
+SHIM = ROOT / "tests" / "shim" / "libhostghost.so"
+_lib = None
+
+
+def shim():
+    global _lib
+    if _lib is None:
+        srcs = [SHIM_SRC, ROOT / "paper_2606_09275_amd" / "csrc" / "ghost_host.cpp"]
+        deps = srcs + [ROOT / "paper_2606_09275_amd" / "csrc" / h for h in ("internal.h", "geom.h")]
+        stale = not SHIM.exists() or any(s.stat().st_mtime > SHIM.stat().st_mtime for s in deps)
+        if stale:
+            cmd = ["/opt/rocm/bin/hipcc", "-O2", "-std=c++17", "-fPIC", "-shared", "-x", "c++",
+                   "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"] + [str(s) for s in srcs] + ["-o", str(SHIM)]
+            r = subprocess.run(cmd, capture_output=True, text=True)
+            assert r.returncode == 0, r.stderr
+        _lib = C.CDLL(str(SHIM))
+        _lib.shim_ghost.restype = C.c_int64
+        _lib.shim_ghost.argtypes = [C.c_int64] + [C.c_void_p] * 5 + [C.c_double, C.c_int32, C.c_void_p, C.c_void_p]
+    return _lib
+
+
+def _tree(w, o):
+    """The oracle's tree in the layout of the library's host arrays: every leaf of a balanced
+    tree has exactly 8 independent nodes in I(K)."""
+    lv = np.ascontiguousarray(o.leaves(), np.int32)
+    n, ids, cm = o.cells()
+    assert np.all(n == 8)
+    keys = np.ascontiguousarray(morton3_np(lv[:, 0], lv[:, 1], lv[:, 2]), np.uint64)
+    return dict(leaf=lv, key=keys, nodes=np.ascontiguousarray(ids[:, :8], np.int32),
+                cmat=np.ascontiguousarray(cm[:, :, :8], np.float64))
 
 
 def _case(kind, jit):
@@ -33,16 +68,19 @@ def _case(kind, jit):
     return w, o, st
 
 
-def _host_ghost(crit, pop):
-    L = shim()
-    L.shim_ghost.restype = C.c_int64
+def _host_ghost(w, o, pop):
+    t = _tree(w, o)
     pop = np.ascontiguousarray(pop, np.uint8)
-    nf = int(L.shim_ghost(C.byref(refine(crit)), pop.ctypes.data_as(C.c_void_p)))
+    lo = np.ascontiguousarray(w.lo, np.float64)
+    lat = np.ascontiguousarray(w.lattice_dims(), np.int32)
+    p = lambda a: a.ctypes.data_as(C.c_void_p)
+    nf = int(shim().shim_ghost(t["leaf"].shape[0], p(t["leaf"]), p(t["key"]), p(t["nodes"]), p(t["cmat"]), p(lo),
+                               w.h_min, w.lvl_max, p(lat), p(pop)))
     assert nf >= 0
     a = dict(face=np.zeros((nf, 8), np.int32), leaf2=np.zeros((nf, 2), np.int32),
              nodes=np.zeros((nf, 16), np.int32), h=np.zeros(nf), G=np.zeros((nf, 16, 16)))
-    p = lambda k: a[k].ctypes.data_as(C.c_void_p)
-    L.shim_ghost_arrays(p("face"), p("leaf2"), p("nodes"), p("h"), p("G"))
+    shim().shim_ghost_arrays(p(a["face"]), p(a["leaf2"]), p(a["nodes"]), p(a["h"]), p(a["G"]))
+    a["cells"] = t["nodes"]
     return a
 
 
@@ -53,13 +91,13 @@ def test_host_ghost_faces_and_matrices(kind, jit):
     u = np.random.default_rng(3).normal(size=3 * nn)
     g = o.ghost(st, u)
     pop = g["beta"] > 0.0  # every point has E > 0: a leaf is populated iff its maximum is positive
-    a = _host_ghost(w.crit(), pop)
+    a = _host_ghost(w, o, pop)
     assert np.array_equal(a["face"], o.ghost_faces())
     assert np.array_equal(a["leaf2"], a["face"][:, :2])
     if kind == "c0":
         assert a["face"].shape[0] == 176
     # same node sets: the union of the two leaves' slot nodes
-    lib_cells = _cells(w)
+    lib_cells = a["cells"]
     for i in range(a["face"].shape[0]):
         ids = a["nodes"][i]
         union = set(lib_cells[a["leaf2"][i, 0]]) | set(lib_cells[a["leaf2"][i, 1]])
@@ -86,13 +124,9 @@ def test_host_ghost_faces_and_matrices(kind, jit):
     assert np.allclose(a["h"], hF / 10.0, rtol=1e-15, atol=0)
 
 
-def _cells(w):
-    from tests.test_host_tree import host_tree
-    return host_tree(w.crit())["cell"]
-
-
 def test_host_ghost_no_faces_without_empty_neighbours():
     w = tiny_workload("sphere", E=1e4)
-    n_leaf = OracleMesh(w.crit()).leaves().shape[0]
-    assert _host_ghost(w.crit(), np.ones(n_leaf, bool))["face"].shape[0] == 0
-    assert _host_ghost(w.crit(), np.zeros(n_leaf, bool))["face"].shape[0] == 0
+    o = OracleMesh(w.crit())
+    n_leaf = o.leaves().shape[0]
+    assert _host_ghost(w, o, np.ones(n_leaf, bool))["face"].shape[0] == 0
+    assert _host_ghost(w, o, np.zeros(n_leaf, bool))["face"].shape[0] == 0

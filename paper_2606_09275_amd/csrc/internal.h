@@ -173,6 +173,8 @@ LeafGeo make_geo(const mpm_mesh* m);
 int32_t read_error(mpm_mesh* m, hipStream_t st, const char* what);
 // grows a work buffer of the mesh to at least `bytes` (old contents dropped)
 int32_t ensure_buffer(void** buf, size_t* have, size_t bytes, hipStream_t st, const char* what);
+// leaves overlapped by each straddling point's domain (m->d_strad_leaf from m->d_strad)
+int32_t strad_leaves(mpm_mesh* m, const double* dx, const double* dl, hipStream_t st);
 // copies one device int64 to the host (ordered on st, waits for it)
 int32_t read_word(mpm_mesh* m, const int64_t* d, int64_t* out, hipStream_t st, const char* what);
 

@@ -25,6 +25,7 @@ int32_t hip_fail(hipError_t e, const char* what) {
 }
 
 int32_t gpu_build_tree(mpm_mesh* m, const mpm_refine_t& c, hipStream_t st);
+int32_t gpu_build_pattern(mpm_mesh* m, const double* dx, const double* dl, const HostTree& T, hipStream_t st);
 
 // ------------------------------------------------------------------ point keys
 // key = rank of the leaf containing the point's centre, value = original index; a stable
@@ -375,12 +376,6 @@ LeafGeo make_geo(const mpm_mesh* m) {
   return G;
 }
 
-template <typename T>
-static int32_t upload(T** dst, const std::vector<T>& v, hipStream_t st) {
-  MPM_HIP(hipMalloc(dst, std::max<size_t>(1, v.size()) * sizeof(T)));
-  if (!v.empty()) MPM_HIP(hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
-  return MPM_OK;
-}
 
 // Copies the device error word to pinned host memory and waits for it by polling an event
 // (a blocking stream synchronisation can leave the device idle for hundreds of microseconds
@@ -555,11 +550,6 @@ extern "C" int32_t octree_build(const mpm_refine_t* crit, const double* x, const
       return hip_fail(e, "octree_build: tree download");
     }
   }
-#define UP(dst, v)                     \
-  if ((rc = upload(&(dst), v, st))) { \
-    mpm_mesh_free(m);                  \
-    return rc;                         \
-  }
   // dense leaf map of the finest cells when it takes at most 1 GiB (else the leaf search
   // bisects the sorted leaf keys)
   const int64_t ncell = int64_t(m->nx) * m->ny * m->nz;
@@ -573,34 +563,24 @@ extern "C" int32_t octree_build(const mpm_refine_t* crit, const double* x, const
                        m->ny, m->d_cellmap);
   }
   m->n_point = n;
-  std::vector<int32_t> pleaf;
-  std::vector<uint8_t> pnleaf;
-  std::vector<int64_t> strad;
-  std::vector<int32_t> sleaf;
+  const double *dx = x, *dl = l;
+  DevBuf tx, tl;
   if (n > 0) {
-    const double *dx = x, *dl = l;
-    double *tx = nullptr, *tl = nullptr;
-    auto cleanup = [&]() {
-      if (tx) (void)hipFree(tx);
-      if (tl) (void)hipFree(tl);
-    };
     if (!is_device_ptr(x) || !is_device_ptr(l)) {
-      hipError_t e1 = hipMalloc(&tx, size_t(3 * n) * 8), e2 = hipMalloc(&tl, size_t(3 * n) * 8);
-      if (e1 != hipSuccess || e2 != hipSuccess) {
-        cleanup();
+      if ((rc = tx.alloc(size_t(3 * n) * 8, "octree_build: point upload")) ||
+          (rc = tl.alloc(size_t(3 * n) * 8, "octree_build: point upload"))) {
         mpm_mesh_free(m);
-        return hip_fail(e1 != hipSuccess ? e1 : e2, "octree_build: point upload");
+        return rc;
       }
-      (void)hipMemcpyAsync(tx, x, size_t(3 * n) * 8, hipMemcpyHostToDevice, st);
-      (void)hipMemcpyAsync(tl, l, size_t(3 * n) * 8, hipMemcpyHostToDevice, st);
-      dx = tx;
-      dl = tl;
+      (void)hipMemcpyAsync(tx.p, x, size_t(3 * n) * 8, hipMemcpyHostToDevice, st);
+      (void)hipMemcpyAsync(tl.p, l, size_t(3 * n) * 8, hipMemcpyHostToDevice, st);
+      dx = tx.as<double>();
+      dl = tl.as<double>();
     }
     hipError_t e = hipMalloc(&m->d_perm, size_t(n) * 8);
     if (e == hipSuccess) e = hipMalloc(&m->d_pleaf, size_t(n) * 4);
     if (e == hipSuccess) e = hipMalloc(&m->d_pnleaf, size_t(n));
     if (e != hipSuccess) {
-      cleanup();
       mpm_mesh_free(m);
       return hip_fail(e, "octree_build: point arrays");
     }
@@ -612,294 +592,33 @@ extern "C" int32_t octree_build(const mpm_refine_t* crit, const double* x, const
                          m->d_pnleaf, m->d_err);
       rc = read_error(m, st, "octree_build (domain overlaps)");
     }
-    if (!rc) {
-      pleaf.resize(n);
-      pnleaf.resize(n);
-      if (hipMemcpy(pleaf.data(), m->d_pleaf, size_t(n) * 4, hipMemcpyDeviceToHost) != hipSuccess ||
-          hipMemcpy(pnleaf.data(), m->d_pnleaf, size_t(n), hipMemcpyDeviceToHost) != hipSuccess)
-        rc = hip_fail(hipGetLastError(), "octree_build: copy classification");
-    }
-    if (!rc) {
-      for (int64_t i = 0; i < n; ++i)
-        if (pnleaf[i] > 1) strad.push_back(i);
-      m->n_straddle = int64_t(strad.size());
-      if (!strad.empty()) {
-        rc = upload(&m->d_strad, strad, st);
-        if (!rc) rc = (hipMalloc(&m->d_strad_leaf, strad.size() * kMaxPointLeaves * 4) == hipSuccess)
-                          ? MPM_OK
-                          : hip_fail(hipErrorOutOfMemory, "octree_build: straddle list");
-        if (!rc) {
-          const LeafGeo G = make_geo(m);
-          hipLaunchKernelGGL(k_strad_leaves, dim3((strad.size() + 255) / 256), dim3(256), 0, st, dx, dl, n,
-                             m->d_perm, m->d_pleaf, m->d_strad, int64_t(strad.size()), G, m->d_strad_leaf);
-          sleaf.resize(strad.size() * kMaxPointLeaves);
-          if (hipMemcpyAsync(sleaf.data(), m->d_strad_leaf, sleaf.size() * 4, hipMemcpyDeviceToHost, st) !=
-                  hipSuccess ||
-              hipStreamSynchronize(st) != hipSuccess)
-            rc = hip_fail(hipGetLastError(), "octree_build: copy straddle leaves");
-        }
-      }
-    }
-    (void)hipStreamSynchronize(st);
-    cleanup();
     if (rc) {
       mpm_mesh_free(m);
       return rc;
     }
   }
-
-  // CSR pattern: pairs of nodes sharing a point support, 3x3 blocks
-  const int64_t nl = m->n_leaf, nn = m->n_node;
-  std::vector<uint8_t> populated(nl, 0);
-  for (int64_t i = 0; i < n; ++i)
-    if (pnleaf[i] == 1) populated[pleaf[i]] = 1;
-  std::vector<uint64_t> pairs;
-  int64_t npop = 0;
-  for (int64_t e = 0; e < nl; ++e) npop += populated[e];
-  pairs.reserve(size_t(npop) * 64 + size_t(m->n_straddle) * 200);
-  for (int64_t e = 0; e < nl; ++e) {
-    if (!populated[e]) continue;
-    const int32_t* s = &T.cell_nodes[8 * e];
-    for (int a = 0; a < 8; ++a)
-      for (int b = 0; b < 8; ++b) pairs.push_back((uint64_t(uint32_t(s[a])) << 32) | uint32_t(s[b]));
-  }
-  // ghost faces (Section 4): populated here means overlapped by any point domain
-  GhostHost gh;
-  if (crit->ghost) {
-    std::vector<uint8_t> any_pop(populated);
-    for (int32_t e : sleaf)
-      if (e >= 0) any_pop[e] = 1;
-    LeafGeo HG = make_geo(m);
-    HG.leaf = T.leaf.data();
-    HG.leaf_key = T.leaf_key.data();
-    HG.cellmap = nullptr;
-    ghost_faces_host(T, HG, any_pop, &gh);
-    if (gh.nf >= (int64_t(1) << 27)) {
-      set_error(MPM_EARG, "octree_build: too many ghost faces");
-      mpm_mesh_free(m);
-      return MPM_EARG;
-    }
-    for (int64_t f = 0; f < gh.nf; ++f) {
-      const int32_t* id = &gh.nodes[16 * f];
-      for (int a = 0; a < 16 && id[a] >= 0; ++a)
-        for (int b = 0; b < 16 && id[b] >= 0; ++b) pairs.push_back((uint64_t(uint32_t(id[a])) << 32) | uint32_t(id[b]));
-    }
-  }
-  m->max_support = npop ? 8 : 0;
-  for (int64_t t = 0; t < m->n_straddle; ++t) {
-    int32_t sup[kMaxPointLeaves * 8];
-    int ns = 0;
-    for (int k = 0; k < kMaxPointLeaves; ++k) {
-      const int32_t e = sleaf[t * kMaxPointLeaves + k];
-      if (e < 0) break;
-      for (int v = 0; v < 8; ++v) {
-        const int32_t id = T.cell_nodes[8 * int64_t(e) + v];
-        bool f = false;
-        for (int z = 0; z < ns; ++z) f |= sup[z] == id;
-        if (!f) sup[ns++] = id;
-      }
-    }
-    m->max_support = std::max(m->max_support, ns);
-    for (int a = 0; a < ns; ++a)
-      for (int b = 0; b < ns; ++b) pairs.push_back((uint64_t(uint32_t(sup[a])) << 32) | uint32_t(sup[b]));
-  }
-  std::sort(pairs.begin(), pairs.end());
-  pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
-  std::vector<int64_t> nb_off(nn + 1, 0);
-  for (uint64_t pr : pairs) nb_off[(pr >> 32) + 1]++;
-  for (int64_t a = 0; a < nn; ++a) nb_off[a + 1] += nb_off[a];
-  std::vector<int64_t> row_ptr(3 * nn + 1, 0);
-  for (int64_t a = 0; a < nn; ++a) {
-    const int64_t deg = nb_off[a + 1] - nb_off[a];
-    for (int c = 0; c < 3; ++c) row_ptr[3 * a + c + 1] = row_ptr[3 * a + c] + 3 * deg;
-    if (deg) m->n_active_rows += 3;
-  }
-  m->nnz = row_ptr[3 * nn];
-  if (m->nnz >= (int64_t(1) << 62)) {
-    set_error(MPM_EARG, "octree_build: nnz overflow");
+  // pattern, segments, records and contribution lists of the points
+  rc = gpu_build_pattern(m, dx, dl, T, st);
+  if (!rc) rc = read_error(m, st, "octree_build (pattern)");
+  if (rc) {
+    (void)hipStreamSynchronize(st);
     mpm_mesh_free(m);
-    return MPM_EARG;
-  }
-  std::vector<int32_t> col(size_t(m->nnz));
-  for (int64_t a = 0; a < nn; ++a)
-    for (int c = 0; c < 3; ++c) {
-      int64_t w = row_ptr[3 * a + c];
-      for (int64_t t = nb_off[a]; t < nb_off[a + 1]; ++t) {
-        const int32_t b = int32_t(pairs[t] & 0xffffffffu);
-        for (int k = 0; k < 3; ++k) col[w++] = 3 * b + k;
-      }
-    }
-  // segments (runs of one leaf inside each 64-point wavefront), per-leaf segment ranges,
-  // node -> (leaf, slot) incidences of populated leaves and the block column of every
-  // (slot a, slot b) pair of a populated leaf in the row of slot a's node
-  m->n_wave = (n + 63) / 64;
-  std::vector<int32_t> wave_seg(m->n_wave + 1, 0), leaf_seg0(nl, 0), leaf_nseg(nl, 0);
-  int64_t nseg = 0;
-  for (int64_t w = 0; w < m->n_wave; ++w) {
-    wave_seg[w] = int32_t(nseg);
-    for (int64_t i = 64 * w; i < std::min<int64_t>(n, 64 * w + 64); ++i) {
-      if (i != 64 * w && pleaf[i] == pleaf[i - 1]) continue;
-      if (leaf_nseg[pleaf[i]] == 0) leaf_seg0[pleaf[i]] = int32_t(nseg);
-      leaf_nseg[pleaf[i]]++;
-      ++nseg;
-    }
-  }
-  wave_seg[m->n_wave] = int32_t(nseg);
-  m->n_seg = nseg;
-  if (nseg >= (int64_t(1) << 31)) {
-    set_error(MPM_EARG, "octree_build: too many point segments");
-    mpm_mesh_free(m);
-    return MPM_EARG;
-  }
-  // Leaves holding more than kHeavySeg segments (a leaf with many points, which spans
-  // several wavefronts) are summed into one record first, so that every node row gathers a
-  // bounded number of records: chunks of up to kRedChunk segments are summed in parallel,
-  // then the chunk sums of each leaf, always in ascending record order.
-  constexpr int kHeavySeg = 4, kRedChunk = 64;
-  std::vector<int32_t> leaf_rec(nl, -1), red1, red2;
-  int64_t nrec = nseg;
-  for (int64_t e = 0; e < nl; ++e)
-    if (populated[e] && leaf_nseg[e] > kHeavySeg) leaf_rec[e] = int32_t(nrec++);
-  for (int64_t e = 0; e < nl; ++e) {
-    if (leaf_rec[e] < 0) continue;
-    const int32_t ns = leaf_nseg[e];
-    if (ns <= kRedChunk) {
-      red1.insert(red1.end(), {leaf_seg0[e], ns, leaf_rec[e]});
-      continue;
-    }
-    const int32_t first_chunk = int32_t(nrec);
-    const int32_t nch = (ns + kRedChunk - 1) / kRedChunk;
-    for (int32_t c = 0; c < nch; ++c)
-      red1.insert(red1.end(), {leaf_seg0[e] + c * kRedChunk, std::min(kRedChunk, ns - c * kRedChunk),
-                               int32_t(nrec++)});
-    red2.insert(red2.end(), {first_chunk, nch, leaf_rec[e]});
-  }
-  m->n_rec = nrec;
-  m->n_red1 = int64_t(red1.size() / 3);
-  m->n_red2 = int64_t(red2.size() / 3);
-  auto leaf_ncon = [&](int64_t e) -> int32_t { return leaf_rec[e] >= 0 ? 1 : leaf_nseg[e]; };
-  std::vector<int32_t> con_off(nn + 1, 0);
-  for (int64_t e = 0; e < nl; ++e)
-    if (populated[e])
-      for (int a = 0; a < 8; ++a) con_off[T.cell_nodes[8 * e + a] + 1] += leaf_ncon(e);
-  for (int64_t a = 0; a < nn; ++a) con_off[a + 1] += con_off[a];
-  m->n_con = con_off[nn];
-  if (m->n_con >= (int64_t(1) << 31) || nrec >= (int64_t(1) << 28)) {
-    set_error(MPM_EARG, "octree_build: too many segment contributions");
-    mpm_mesh_free(m);
-    return MPM_EARG;
-  }
-  std::vector<int32_t> con_seg(std::max<int64_t>(1, m->n_con)), con_bp(std::max<int64_t>(1, m->n_con));
-  std::vector<int32_t> fill(con_off.begin(), con_off.end() - 1);
-  std::vector<int16_t> bpos(size_t(nl) * 64, -1);
-  for (int64_t e = 0; e < nl; ++e) {  // ascending leaf order per node: a fixed summation order
-    if (!populated[e]) continue;
-    const int32_t* sl = &T.cell_nodes[8 * e];
-    for (int a = 0; a < 8; ++a) {
-      const int64_t na = sl[a];
-      for (int g = 0; g < leaf_ncon(e); ++g) {
-        const int64_t rec = leaf_rec[e] >= 0 ? leaf_rec[e] : leaf_seg0[e] + g;
-        con_seg[fill[na]] = int32_t((rec << 3) | a);
-        con_bp[fill[na]] = int32_t(64 * e + 8 * a);
-        fill[na]++;
-      }
-      const uint64_t* lo = pairs.data() + nb_off[na];
-      const uint64_t* hi = pairs.data() + nb_off[na + 1];
-      for (int b = 0; b < 8; ++b) {
-        const uint64_t key = (uint64_t(uint32_t(na)) << 32) | uint32_t(sl[b]);
-        bpos[64 * e + 8 * a + b] = int16_t(std::lower_bound(lo, hi, key) - lo);
-      }
-    }
-  }
-  for (int64_t a = 0; a < nn; ++a) m->max_deg = std::max<int32_t>(m->max_deg, int32_t(nb_off[a + 1] - nb_off[a]));
-  // ghost couplings: block column of every face node pair in the first node's row, and per
-  // node its (face, local index) contributions in ascending face order
-  std::vector<int16_t> gbpos(size_t(std::max<int64_t>(1, gh.nf)) * 256, 0);
-  std::vector<int32_t> gnode, gcon_off(1, 0), gcon;
-  if (gh.nf) {
-    std::vector<int32_t> gcnt(nn + 1, 0);
-    for (int64_t f = 0; f < gh.nf; ++f) {
-      const int32_t* id = &gh.nodes[16 * f];
-      for (int a = 0; a < 16 && id[a] >= 0; ++a) {
-        gcnt[id[a] + 1]++;
-        const uint64_t* lo = pairs.data() + nb_off[id[a]];
-        const uint64_t* hi = pairs.data() + nb_off[id[a] + 1];
-        for (int b = 0; b < 16 && id[b] >= 0; ++b) {
-          const uint64_t key = (uint64_t(uint32_t(id[a])) << 32) | uint32_t(id[b]);
-          gbpos[256 * f + 16 * a + b] = int16_t(std::lower_bound(lo, hi, key) - lo);
-        }
-      }
-    }
-    std::vector<int32_t> slot(nn, -1);
-    for (int64_t a = 0; a < nn; ++a)
-      if (gcnt[a + 1]) {
-        slot[a] = int32_t(gnode.size());
-        gnode.push_back(int32_t(a));
-        gcon_off.push_back(gcon_off.back() + gcnt[a + 1]);
-      }
-    gcon.resize(gcon_off.back());
-    std::vector<int32_t> gfill(gcon_off.begin(), gcon_off.end() - 1);
-    for (int64_t f = 0; f < gh.nf; ++f) {
-      const int32_t* id = &gh.nodes[16 * f];
-      for (int a = 0; a < 16 && id[a] >= 0; ++a) gcon[gfill[slot[id[a]]]++] = int32_t(16 * f + a);
-    }
-  }
-  if (m->max_deg > 1024 || nl >= (int64_t(1) << 25)) {
-    set_error(MPM_ESTENCIL, "octree_build: node row too wide or too many leaves for the gather");
-    mpm_mesh_free(m);
-    return MPM_ESTENCIL;
-  }
-  UP(m->d_row_ptr, row_ptr);
-  UP(m->d_col, col);
-  UP(m->d_wave_seg, wave_seg);
-  UP(m->d_leaf_seg0, leaf_seg0);
-  UP(m->d_leaf_nseg, leaf_nseg);
-  UP(m->d_con_off, con_off);
-  UP(m->d_con_seg, con_seg);
-  UP(m->d_con_bp, con_bp);
-  UP(m->d_bpos, bpos);
-  if (!red1.empty()) {
-    UP(m->d_red1, red1);
-  }
-  if (!red2.empty()) {
-    UP(m->d_red2, red2);
-  }
-  if (gh.nf) {
-    m->n_gface = gh.nf;
-    m->n_gnode = int64_t(gnode.size());
-    m->h_gface = gh.face;
-    UP(m->d_gf_leaf, gh.leaf2);
-    UP(m->d_gf_nodes, gh.nodes);
-    UP(m->d_gf_G, gh.G);
-    UP(m->d_gf_h, gh.h);
-    UP(m->d_gf_bpos, gbpos);
-    UP(m->d_gnode, gnode);
-    UP(m->d_gcon_off, gcon_off);
-    UP(m->d_gcon, gcon);
-    if (hipMalloc(&m->d_gbeta, size_t(nl) * 8) != hipSuccess ||
-        hipMalloc(&m->d_gf_sc, size_t(gh.nf) * 8) != hipSuccess) {
-      mpm_mesh_free(m);
-      return hip_fail(hipErrorOutOfMemory, "octree_build: ghost moduli");
-    }
-  }
-  if (hipMalloc(&m->d_segK, size_t(std::max<int64_t>(1, nrec)) * 576 * 8) != hipSuccess ||
-      hipMalloc(&m->d_segF, size_t(std::max<int64_t>(1, nrec)) * 24 * 8) != hipSuccess) {
-    mpm_mesh_free(m);
-    return hip_fail(hipErrorOutOfMemory, "octree_build: segment buffers");
-  }
-#undef UP
-  if (hipMalloc(&m->d_partial, 4096 * sizeof(double)) != hipSuccess) {
-    mpm_mesh_free(m);
-    return hip_fail(hipErrorOutOfMemory, "octree_build: partials");
-  }
-  hipError_t e = hipStreamSynchronize(st);
-  if (e != hipSuccess) {
-    mpm_mesh_free(m);
-    return hip_fail(e, "octree_build: final sync");
+    return rc;
   }
   *out_mesh = m;
   return MPM_OK;
 }
+
+namespace mpm {
+int32_t strad_leaves(mpm_mesh* m, const double* dx, const double* dl, hipStream_t st) {
+  const LeafGeo G = make_geo(m);
+  hipLaunchKernelGGL(k_strad_leaves, dim3(unsigned((m->n_straddle + 255) / 256)), dim3(256), 0, st, dx, dl,
+                     m->n_point, m->d_perm, m->d_pleaf, m->d_strad, m->n_straddle, G, m->d_strad_leaf);
+  MPM_HIP(hipGetLastError());
+  return MPM_OK;
+}
+
+}  // namespace mpm
 
 extern "C" int32_t mpm_mesh_info(const mpm_mesh_t* m, mpm_mesh_info_t* o) {
   if (!m || !o) {

@@ -249,6 +249,7 @@ def main():
         out["dynamic"] = dynamic_assembly(mesh, w, ps, views, u, f_ext, dirichlet, n)
         out["solve"] = newton_solve(mesh, views, u, f_ext, dirichlet, info)
         out["ghost"] = ghost_stabilisation(w, x_dev, l_dev, views, u, f_ext, dirichlet, R["assemble_ms"])
+        out["gimp_split"] = gimp_split(mesh, w)
     if "prev_x_s" in w.extra:
         out["protocol"] = tool_protocol(mesh, w, nodes, views, x_dev, perm_buf, leaf_buf, packed, sorted_buf,
                                         f_ext, dirichlet, lam)
@@ -312,6 +313,55 @@ def ghost_stabilisation(w, x_dev, l_dev, views, u, f_ext, dirichlet, plain_ms, r
     log(f"[bench] ghost: {res['n_ghost_face']} faces, nnz {res['nnz']}, build {build_ms:.1f} ms, "
         f"assemble {ms:.3f} ms (plain {plain_ms:.3f} ms)")
     del gm
+    return res
+
+
+def gimp_split(mesh, w, reps=5):
+    """GIMP refinement (Section 5) on the mesh: points laid out one level coarser than the
+    leaves (2 per axis in each parent cell) with the full state, reference positions and
+    velocities; mean ms of the criterion and of the split (HIP events over reps calls), and the
+    split's HBM rate from the bytes it must move (8 bytes x 33 fields read per input point and
+    written per output point, plus the flags)."""
+    import dataclasses
+    import torch
+    import workloads as W
+    lv = mesh.arrays()["leaf"].cpu().numpy()
+    par = lv.copy()
+    s = np.left_shift(1, w.lvl_max - (lv[:, 3] - 1))
+    par[:, :3] = (lv[:, :3] // s[:, None]) * s[:, None]
+    par[:, 3] = lv[:, 3] - 1
+    par = np.unique(par[par[:, 3] >= w.lvl_base], axis=0)
+    w2 = dataclasses.replace(w, ppa=lambda lev: 2)
+    pc = W.make_points(w2, par[:, :3], par[:, 3])
+    st = W.make_state(w2, pc)
+    dev = {k: torch.from_numpy(np.ascontiguousarray(st[k], np.float64)).cuda()
+           for k in ("x", "l", "vol", "mass", "Jn", "bn", "Fn", "E", "nu", "sy")}
+    X = dev["x"].clone()
+    v = torch.zeros_like(X)
+    props = {"E": (float(w.E), 0.0, 0.0, 0.0)}
+    flags, cnt = mesh.split_mark(dev["x"], dev["l"])
+    mesh.split_apply(dev, flags, cnt, X=X, v=v, props=props)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    torch.cuda.synchronize()
+    e[0].record()
+    for _ in range(reps):
+        flags, cnt = mesh.split_mark(dev["x"], dev["l"], out=flags)
+    e[1].record()
+    for _ in range(reps):
+        o = mesh.split_apply(dev, flags, cnt, X=X, v=v, props=props)
+    e[2].record()
+    torch.cuda.synchronize()
+    n = pc.n
+    n_out = n + 7 * cnt
+    mark_ms = e[0].elapsed_time(e[1]) / reps
+    apply_ms = e[1].elapsed_time(e[2]) / reps
+    nbytes = 33 * 8 * (n + n_out) + n
+    res = {"points": n, "split": cnt, "points_out": n_out, "mark_ms": mark_ms, "apply_ms": apply_ms,
+           "mark_points_per_s": n / (mark_ms * 1e-3), "apply_bytes": nbytes,
+           "apply_GBps": nbytes / (apply_ms * 1e-3) / 1e9, "apply_hbm_frac": nbytes / (apply_ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
+    log(f"[bench] GIMP split: {cnt} of {n} points -> {n_out}; criterion {mark_ms:.3f} ms, split {apply_ms:.3f} ms "
+        f"({res['apply_GBps']:.0f} GB/s)")
+    del o
     return res
 
 

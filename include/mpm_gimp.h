@@ -167,9 +167,11 @@ int32_t mpm_point_sort(const mpm_mesh_t* mesh, const double* x, int64_t n, int64
                        void* stream);
 
 /* dst[c][p] = src[c][perm[p]] for c < ncomp (device, double): brings original-order state
- * into sorted order. perm = the mesh's perm when NULL. For 2 <= ncomp <= 32 the arrays pass
- * through a record-major staging copy (8 ncomp n bytes, kept with the mesh and grown when a
- * call needs more); src and dst must not overlap. */
+ * into sorted order. perm = the mesh's perm when NULL. For 2 <= ncomp <= 32 the device counts
+ * the breaks of consecutive runs in perm: with at most one per 64 points (points that moved
+ * little since the last sort) the arrays are gathered directly, else they pass through a
+ * record-major staging copy (8 ncomp n + 256 bytes, kept with the mesh and grown when a call
+ * needs more). src and dst must not overlap. */
 int32_t mpm_permute(const mpm_mesh_t* mesh, const int64_t* perm, const double* src, double* dst, int32_t ncomp,
                     void* stream);
 

@@ -293,9 +293,52 @@ __global__ void k_permute(const int64_t* __restrict__ perm, const double* __rest
 // before the first wait.
 // Step 1: tiled [ncomp][n] -> [n][ncomp] transpose through LDS (coalesced on both sides).
 constexpr int kPermTile = 128, kPermMaxComp = 32;
+//
+// Permutations of points that moved little since the last sort are made of long runs of
+// consecutive indices; then a direct gather is coalesced and moves half the bytes. A first
+// kernel counts the run breaks on the device; the staged and the direct kernels are all
+// launched and each returns at once unless the count selects it (no host round trip).
+__global__ void k_perm_zero(unsigned long long* brk) { *brk = 0; }
+// grid-stride count, one atomic per workgroup (atomics on one address serialise)
+constexpr int kBreakBlocks = 1024;
+__global__ __launch_bounds__(256) void k_perm_breaks(const int64_t* __restrict__ perm, int64_t n,
+                                                     unsigned long long* brk) {
+  __shared__ unsigned long long wsum[4];
+  unsigned long long c = 0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x + 1; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    c += perm[i] != perm[i - 1] + 1;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long t = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    if (t) atomicAdd(brk, t);
+  }
+}
+// direct mode: at most one run break per 64 points on average
+__device__ __forceinline__ bool perm_direct(const unsigned long long* brk, int64_t n) {
+  return (unsigned long long)(n / 64) >= *brk;
+}
+template <int NC>
+__global__ __launch_bounds__(256) void k_permute_runs(const int64_t* __restrict__ perm, const double* __restrict__ src,
+                                                      double* __restrict__ dst, int64_t n,
+                                                      const unsigned long long* brk) {
+  if (!perm_direct(brk, n)) return;
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t p = perm[i];
+  double v[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) v[c] = src[c * n + p];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) dst[c * n + i] = v[c];
+}
+
 template <int NC>
 __global__ __launch_bounds__(kPermTile) void k_soa_to_aos(const double* __restrict__ src, double* __restrict__ aos,
-                                                          int64_t n) {
+                                                          int64_t n, const unsigned long long* brk) {
+  if (perm_direct(brk, n)) return;
   __shared__ double tile[NC * kPermTile];
   const int64_t p0 = int64_t(blockIdx.x) * kPermTile;
   const int t = threadIdx.x;
@@ -322,7 +365,8 @@ __global__ __launch_bounds__(kPermTile) void k_soa_to_aos(const double* __restri
 // Step 2: gather one record per sorted position, write component rows (coalesced).
 template <int NC>
 __global__ __launch_bounds__(256) void k_aos_gather(const int64_t* __restrict__ perm, const double* __restrict__ aos,
-                                                    double* __restrict__ dst, int64_t n) {
+                                                    double* __restrict__ dst, int64_t n, const unsigned long long* brk) {
+  if (perm_direct(brk, n)) return;
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double* r = aos + perm[i] * NC;
@@ -347,17 +391,18 @@ __global__ __launch_bounds__(256) void k_aos_gather(const int64_t* __restrict__ 
 
 template <int NC>
 static void launch_permute(const int64_t* pm, const double* src, double* aos, double* dst, int64_t n,
-                           hipStream_t st) {
+                           const unsigned long long* brk, hipStream_t st) {
+  hipLaunchKernelGGL(k_permute_runs<NC>, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, pm, src, dst, n, brk);
   hipLaunchKernelGGL(k_soa_to_aos<NC>, dim3(unsigned((n + kPermTile - 1) / kPermTile)), dim3(kPermTile), 0, st, src,
-                     aos, n);
-  hipLaunchKernelGGL(k_aos_gather<NC>, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, pm, aos, dst, n);
+                     aos, n, brk);
+  hipLaunchKernelGGL(k_aos_gather<NC>, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, pm, aos, dst, n, brk);
 }
 
 template <int... NC>
 static bool dispatch_permute(int ncomp, const int64_t* pm, const double* src, double* aos, double* dst, int64_t n,
-                             hipStream_t st, std::integer_sequence<int, NC...>) {
+                             const unsigned long long* brk, hipStream_t st, std::integer_sequence<int, NC...>) {
   bool done = false;
-  ((ncomp == NC + 2 ? (launch_permute<NC + 2>(pm, src, aos, dst, n, st), done = true) : false), ...);
+  ((ncomp == NC + 2 ? (launch_permute<NC + 2>(pm, src, aos, dst, n, brk, st), done = true) : false), ...);
   return done;
 }
 
@@ -695,9 +740,15 @@ extern "C" int32_t mpm_permute(const mpm_mesh_t* m, const int64_t* perm, const d
   const int64_t* pm = perm ? perm : m->d_perm;
   mpm_mesh* mm = const_cast<mpm_mesh*>(m);
   if (ncomp >= 2 && ncomp <= kPermMaxComp &&
-      ensure_buffer(&mm->d_stage, &mm->stage_bytes, size_t(n) * ncomp * 8, st, "mpm_permute: staging") == MPM_OK) {
-    dispatch_permute(ncomp, pm, src, static_cast<double*>(mm->d_stage), dst, n, st,
-                     std::make_integer_sequence<int, kPermMaxComp - 1>{});
+      ensure_buffer(&mm->d_stage, &mm->stage_bytes, size_t(n) * ncomp * 8 + 256, st, "mpm_permute: staging") ==
+          MPM_OK) {
+    // the run-break counter sits after the staging copy
+    double* aos = static_cast<double*>(mm->d_stage);
+    unsigned long long* brk = reinterpret_cast<unsigned long long*>(aos + size_t(n) * ncomp);
+    hipLaunchKernelGGL(k_perm_zero, dim3(1), dim3(1), 0, st, brk);
+    hipLaunchKernelGGL(k_perm_breaks, dim3(unsigned(std::min<int64_t>(kBreakBlocks, (n + 255) / 256))), dim3(256), 0,
+                       st, pm, n, brk);
+    dispatch_permute(ncomp, pm, src, aos, dst, n, brk, st, std::make_integer_sequence<int, kPermMaxComp - 1>{});
   } else {
     (void)hipGetLastError();
     hipLaunchKernelGGL(k_permute, dim3((n + 255) / 256), dim3(256), 0, st, pm, src, dst, n, ncomp);

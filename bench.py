@@ -216,7 +216,7 @@ def main():
     kt_s = R["assemble_kernel_ms"] * 1e-3
     peak = PEAK_FP64_VEC_TFLOPS if prim == "f64" else PEAK_FP32_VEC_TFLOPS
     roofline = {
-        "bound": "alu", "kernel": "k_assemble_fast<%s>" % ("double" if prim == "f64" else "float"),
+        "bound": "alu", "kernel": "k_assemble_fast<%s, false>" % ("double" if prim == "f64" else "float"),
         "achieved": alg_flops / kt_s / 1e12, "peak": peak, "unit": "TFLOP/s",
         "frac": alg_flops / kt_s / 1e12 / peak, "traffic": measured_traffic(w.name, prim),
         "flops_per_point": FLOPS_PER_POINT, "points_per_launch": n_fast,
@@ -250,6 +250,7 @@ def main():
         out["solve"] = newton_solve(mesh, views, u, f_ext, dirichlet, info)
         out["ghost"] = ghost_stabilisation(w, x_dev, l_dev, views, u, f_ext, dirichlet, R["assemble_ms"])
         out["gimp_split"] = gimp_split(mesh, w)
+    out["state_gather_runs_ms"] = gather_runs(mesh, packed, sorted_buf)
     if "prev_x_s" in w.extra:
         out["protocol"] = tool_protocol(mesh, w, nodes, views, x_dev, perm_buf, leaf_buf, packed, sorted_buf,
                                         f_ext, dirichlet, lam)
@@ -314,6 +315,26 @@ def ghost_stabilisation(w, x_dev, l_dev, views, u, f_ext, dirichlet, plain_ms, r
         f"assemble {ms:.3f} ms (plain {plain_ms:.3f} ms)")
     del gm
     return res
+
+
+def gather_runs(mesh, packed, sorted_buf, reps=10):
+    """State gather of the same 18 components when the point order is one run (points already
+    in sorted order, as between time steps when few points change leaves): mean ms."""
+    import torch
+    ident = torch.arange(packed.shape[1], dtype=torch.int64, device="cuda")
+    mesh.permute(packed, ident, out=sorted_buf)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        mesh.permute(packed, ident, out=sorted_buf)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    mesh.permute(packed, None, out=sorted_buf)  # restore the sorted state
+    torch.cuda.synchronize()
+    log(f"[bench] state gather of an order made of runs: {ms:.3f} ms")
+    return ms
 
 
 def gimp_split(mesh, w, reps=5):

@@ -7,8 +7,9 @@
 // (F constant over the domain makes the current-to-reference map affine there).
 //
 // The output keeps the input order (a point, or its 8 children in child order): blocks of
-// 256 points count their splits, one workgroup scans the block counts, and each block then
-// scans its own points to place their outputs.
+// 256 points count their splits, one workgroup scans the block counts, each block then scans
+// its own points to place their first outputs, and one thread per output point finds its
+// parent by bisection of those offsets and writes every field (coalesced stores).
 #include "geom.h"
 
 namespace mpm {
@@ -165,22 +166,14 @@ struct SplitIO {
   int64_t n, n_out;
 };
 
-__device__ __forceinline__ void copy_comp(const double* src, double* dst, int nc, int64_t n, int64_t i, int64_t n_out,
-                                          int64_t o, int cnt) {
-  if (!dst) return;
-  for (int c = 0; c < nc; ++c) {
-    const double v = src[c * n + i];
-    for (int k = 0; k < cnt; ++k) dst[c * n_out + o + k] = v;
-  }
-}
-
-__global__ __launch_bounds__(kSplitBlock) void k_split_write(SplitIO io, const uint8_t* __restrict__ split,
-                                                             const int64_t* __restrict__ blk, DevErr* err) {
+// first output of every input point (offs[n] = n_out): the block offset of the counts scan
+// plus the point's rank inside its block
+__global__ __launch_bounds__(kSplitBlock) void k_split_offsets(const uint8_t* __restrict__ split, int64_t n,
+                                                               const int64_t* __restrict__ blk,
+                                                               int64_t* __restrict__ offs, int64_t nb) {
   __shared__ int wtot[kSplitBlock / 64];
-  const int64_t n = io.n, n_out = io.n_out;
   const int64_t i = int64_t(blockIdx.x) * kSplitBlock + threadIdx.x;
-  const int s = i < n ? int(split[i] != 0) : 0;
-  const int cnt = i < n ? (s ? 8 : 1) : 0;
+  const int cnt = i < n ? (split[i] != 0 ? 8 : 1) : 0;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int inc = cnt;
 #pragma unroll
@@ -192,48 +185,68 @@ __global__ __launch_bounds__(kSplitBlock) void k_split_write(SplitIO io, const u
   __syncthreads();
   int pre = 0;
   for (int w = 0; w < wv; ++w) pre += wtot[w];
-  if (i >= n) return;
   // outputs before this block: its points, plus 7 per split among them
-  const int64_t o = int64_t(blockIdx.x) * kSplitBlock + 7 * blk[blockIdx.x] + pre + inc - cnt;
-  if (o + cnt > n_out) {
-    if (atomicCAS(&err->code, 0, MPM_EARG) == 0) err->index = i;
-    return;
+  if (i < n) offs[i] = int64_t(blockIdx.x) * kSplitBlock + 7 * blk[blockIdx.x] + pre + inc - cnt;
+  if (i == 0) offs[n] = n + 7 * blk[nb];
+}
+
+// One thread per output point (coalesced stores): its parent is the last input point whose
+// first output does not exceed it, and its child index the distance to that first output.
+__global__ __launch_bounds__(256) void k_split_emit(SplitIO io, const uint8_t* __restrict__ split,
+                                                    const int64_t* __restrict__ offs) {
+  const int64_t n = io.n, n_out = io.n_out;
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n_out) return;
+  int64_t lo = 0, hi = n;  // first index with offs > j, minus one
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (offs[mid] <= j) lo = mid + 1;
+    else hi = mid;
   }
+  const int64_t i = lo - 1;
+  const int c = int(j - offs[i]);
+  const bool s = split[i] != 0;
   const mpm_state_t& S = io.in;
   const mpm_state_out_t& D = io.out;
   // data constant over the domain
-  copy_comp(S.Jn, D.Jn, 1, n, i, n_out, o, cnt);
-  copy_comp(S.bn, D.bn, 6, n, i, n_out, o, cnt);
-  copy_comp(S.Fn, D.Fn, 9, n, i, n_out, o, cnt);
-  if (io.v) copy_comp(io.v, io.vo, 3, n, i, n_out, o, cnt);
+  if (D.Jn) D.Jn[j] = S.Jn[i];
+  if (D.bn)
+    for (int k = 0; k < 6; ++k) D.bn[k * n_out + j] = S.bn[k * n + i];
+  if (D.Fn)
+    for (int k = 0; k < 9; ++k) D.Fn[k * n_out + j] = S.Fn[k * n + i];
+  if (io.vo)
+    for (int k = 0; k < 3; ++k) io.vo[k * n_out + j] = io.v[k * n + i];
   const double* prm[3] = {S.E, S.nu, S.sy};
   double* prmo[3] = {D.E, D.nu, D.sy};
-  for (int r = 0; r < 3; ++r)
-    if (!((io.mask >> r) & 1) || !s) copy_comp(prm[r], prmo[r], 1, n, i, n_out, o, cnt);
-  double xp[3], lp[3];
-  for (int a = 0; a < 3; ++a) {
-    xp[a] = S.x[a * n + i];
-    lp[a] = S.l[a * n + i];
-  }
   if (!s) {
     for (int a = 0; a < 3; ++a) {
-      D.x[a * n_out + o] = xp[a];
-      D.l[a * n_out + o] = lp[a];
-      if (io.X) io.Xo[a * n_out + o] = io.X[a * n + i];
+      D.x[a * n_out + j] = S.x[a * n + i];
+      D.l[a * n_out + j] = S.l[a * n + i];
+      if (io.Xo) io.Xo[a * n_out + j] = io.X[a * n + i];
     }
-    D.vol[o] = S.vol[i];
-    D.mass[o] = S.mass[i];
+    D.vol[j] = S.vol[i];
+    D.mass[j] = S.mass[i];
+    for (int r = 0; r < 3; ++r)
+      if (prmo[r]) prmo[r][j] = prm[r][i];
     return;
   }
-  const double vol = S.vol[i] * 0.125, mass = S.mass[i] * 0.125;
-  double Xp[3] = {0.0, 0.0, 0.0}, Fi[9];
-  if (io.X) {
-    for (int a = 0; a < 3; ++a) Xp[a] = io.X[a * n + i];
+  double d[3];
+  for (int a = 0; a < 3; ++a) {
+    const double xp = S.x[a * n + i], h = 0.5 * S.l[a * n + i];
+    d[a] = ((c >> a) & 1) ? h : -h;
+    D.x[a * n_out + j] = xp + d[a];
+    D.l[a * n_out + j] = h;
+  }
+  D.vol[j] = S.vol[i] * 0.125;
+  D.mass[j] = S.mass[i] * 0.125;
+  double Xc[3] = {0.0, 0.0, 0.0};
+  if (io.Xo) {
     double F[9];
     for (int k = 0; k < 9; ++k) F[k] = S.Fn[k * n + i];
     // inverse by cofactors (F row-major)
     const double c00 = F[4] * F[8] - F[5] * F[7], c01 = F[5] * F[6] - F[3] * F[8], c02 = F[3] * F[7] - F[4] * F[6];
     const double det = F[0] * c00 + F[1] * c01 + F[2] * c02, r = 1.0 / det;
+    double Fi[9];
     Fi[0] = c00 * r;
     Fi[3] = c01 * r;
     Fi[6] = c02 * r;
@@ -243,35 +256,25 @@ __global__ __launch_bounds__(kSplitBlock) void k_split_write(SplitIO io, const u
     Fi[2] = (F[1] * F[5] - F[2] * F[4]) * r;
     Fi[5] = (F[2] * F[3] - F[0] * F[5]) * r;
     Fi[8] = (F[0] * F[4] - F[1] * F[3]) * r;
-  }
-  for (int c = 0; c < 8; ++c) {
-    const int64_t oc = o + c;
-    double d[3];
     for (int a = 0; a < 3; ++a) {
-      const double h = 0.5 * lp[a];
-      d[a] = ((c >> a) & 1) ? h : -h;
-      D.x[a * n_out + oc] = xp[a] + d[a];
-      D.l[a * n_out + oc] = h;
+      Xc[a] = io.X[a * n + i] + (Fi[3 * a] * d[0] + Fi[3 * a + 1] * d[1] + Fi[3 * a + 2] * d[2]);
+      io.Xo[a * n_out + j] = Xc[a];
     }
-    D.vol[oc] = vol;
-    D.mass[oc] = mass;
-    if (io.X) {
-      double Xc[3];
-      for (int a = 0; a < 3; ++a) {
-        Xc[a] = Xp[a] + (Fi[3 * a] * d[0] + Fi[3 * a + 1] * d[1] + Fi[3 * a + 2] * d[2]);
-        io.Xo[a * n_out + oc] = Xc[a];
-      }
-      for (int r = 0; r < 3; ++r)
-        if (((io.mask >> r) & 1) && prmo[r]) {
-          const double* q = io.props + 4 * r;
-          prmo[r][oc] = q[0] + q[1] * Xc[0] + q[2] * Xc[1] + q[3] * Xc[2];
-        }
+  }
+  for (int r = 0; r < 3; ++r) {
+    if (!prmo[r]) continue;
+    if ((io.mask >> r) & 1) {
+      const double* q = io.props + 4 * r;
+      prmo[r][j] = q[0] + q[1] * Xc[0] + q[2] * Xc[1] + q[3] * Xc[2];
+    } else {
+      prmo[r][j] = prm[r][i];
     }
   }
 }
 
-static int32_t split_buffers(mpm_mesh* m, int64_t nb, hipStream_t st) {
-  return ensure_buffer(&m->d_split, &m->split_bytes, size_t(nb + 1) * 8, st, "GIMP split: block counts");
+// work buffer: nb + 1 block counts, then (apply) n + 1 output offsets
+static int32_t split_buffers(mpm_mesh* m, int64_t nb, int64_t n_offs, hipStream_t st) {
+  return ensure_buffer(&m->d_split, &m->split_bytes, size_t(nb + 1 + n_offs) * 8, st, "GIMP split: work buffer");
 }
 
 }  // namespace mpm
@@ -293,7 +296,7 @@ extern "C" int32_t mpm_split_mark(const mpm_mesh_t* mc, const double* x, const d
     set_error(MPM_EARG, "mpm_split_mark: too many points");
     return MPM_EARG;
   }
-  if (const int32_t rc = split_buffers(m, nb, st)) return rc;
+  if (const int32_t rc = split_buffers(m, nb, 0, st)) return rc;
   int64_t* blk = static_cast<int64_t*>(m->d_split);
   hipLaunchKernelGGL(k_split_mark, dim3(unsigned(nb)), dim3(kSplitBlock), 0, st, x, l, n, beta, make_geo(m),
                      int(m->crit.lvl_base), split, blk, m->d_err);
@@ -326,8 +329,9 @@ extern "C" int32_t mpm_split_apply(const mpm_mesh_t* mc, int64_t n, const uint8_
   mpm_mesh* m = const_cast<mpm_mesh*>(mc);
   hipStream_t st = (hipStream_t)stream;
   const int64_t nb = (n + kSplitBlock - 1) / kSplitBlock;
-  if (const int32_t rc = split_buffers(m, nb, st)) return rc;
+  if (const int32_t rc = split_buffers(m, nb, n + 1, st)) return rc;
   int64_t* blk = static_cast<int64_t*>(m->d_split);
+  int64_t* offs = blk + nb + 1;
   // block counts of the flags (the scan of the marking call may belong to other flags)
   hipLaunchKernelGGL(k_split_count, dim3(unsigned(nb)), dim3(kSplitBlock), 0, st, split, n, blk);
   hipLaunchKernelGGL(k_split_scan, dim3(1), dim3(1024), 0, st, blk, nb);
@@ -348,7 +352,8 @@ extern "C" int32_t mpm_split_apply(const mpm_mesh_t* mc, int64_t n, const uint8_
   io.mask = prop_mask;
   io.n = n;
   io.n_out = n_out;
-  hipLaunchKernelGGL(k_split_write, dim3(unsigned(nb)), dim3(kSplitBlock), 0, st, io, split, blk, m->d_err);
+  hipLaunchKernelGGL(k_split_offsets, dim3(unsigned(nb)), dim3(kSplitBlock), 0, st, split, n, blk, offs, nb);
+  hipLaunchKernelGGL(k_split_emit, dim3(unsigned((n_out + 255) / 256)), dim3(256), 0, st, io, split, offs);
   MPM_HIP(hipGetLastError());
   return read_error(m, st, "mpm_split_apply");
 }

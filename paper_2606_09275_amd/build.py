@@ -9,7 +9,7 @@ from pathlib import Path
 PKG = Path(__file__).resolve().parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libmpmgimp.so"
-SOURCES = ["mesh_gpu.hip", "assemble.hip", "solve.hip", "ghost_host.cpp", "ghost.hip", "split.hip", "prim.hip", "tree.hip", "pattern.hip"]
+SOURCES = ["mesh_gpu.hip", "assemble.hip", "solve.hip", "ghost.hip", "ghost_faces.hip", "split.hip", "prim.hip", "tree.hip", "pattern.hip"]
 ARCH = os.environ.get("MPM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -59,24 +59,6 @@ __host__ __device__ inline int code_hmask(int32_t code) { return code & 0xff; }
 __host__ __device__ inline int code_child(int32_t code) { return (code >> 8) & 7; }
 
 // ------------------------------------------------------------------ mesh handle
-// host copies of tree arrays that host-side construction steps read
-struct HostTree {
-  std::vector<int32_t> leaf;       // n_leaf x 4, Morton order
-  std::vector<uint64_t> leaf_key;  // Morton key of anchors
-  std::vector<int32_t> cell_nodes; // n_leaf x 8
-  std::vector<double> cell_cmat;   // n_leaf x 8 x 8: C_K[vertex][slot]
-};
-
-// ghost faces built on the host: per face the two leaves (lower rank first), the union of
-// their slot nodes (16, -1 padded), the 16 x 16 matrix of normal-derivative jump integrals,
-// h_F / kappa, and the face record (lo leaf, hi leaf, axis, plane, b0, b1, c0, c1) in
-// finest-lattice units
-struct GhostHost {
-  int64_t nf = 0;
-  std::vector<int32_t> leaf2, nodes, face;
-  std::vector<double> G, h;
-};
-
 }  // namespace mpm
 
 struct mpm_mesh {
@@ -169,6 +151,8 @@ struct mpm_mesh {
 namespace mpm {
 struct LeafGeo;
 LeafGeo make_geo(const mpm_mesh* m);
+// ghost faces of the leaves flagged in pop (device, n_leaf): the mesh's face arrays
+int32_t gpu_ghost_faces(mpm_mesh* m, const int32_t* pop, hipStream_t st);
 // copies the device error word to the host; sets the message and returns its code
 int32_t read_error(mpm_mesh* m, hipStream_t st, const char* what);
 // grows a work buffer of the mesh to at least `bytes` (old contents dropped)
@@ -217,8 +201,6 @@ struct DevBuf {
 int32_t scan_counts(const int32_t* in, int64_t n, int64_t* out, hipStream_t st);
 // sorts n 64-bit keys in place by their low `bits` bits (stable two-stage LSD radix)
 int32_t sort_u64(uint64_t* keys, int64_t n, int bits, hipStream_t st);
-// ghost faces of the populated flags pop (host leaf geometry G: leaf and key arrays of T)
-int64_t ghost_faces_host(const HostTree& T, const LeafGeo& G, const std::vector<uint8_t>& pop, GhostHost* out);
 // adds the ghost form's stiffness to K (precision's type) and K_G u to f on stream st
 int32_t ghost_apply(const mpm_mesh* m, const mpm_state_t* s, const double* u, int32_t precision, void* K, double* f,
                     hipStream_t st);

@@ -25,7 +25,7 @@ int32_t hip_fail(hipError_t e, const char* what) {
 }
 
 int32_t gpu_build_tree(mpm_mesh* m, const mpm_refine_t& c, hipStream_t st);
-int32_t gpu_build_pattern(mpm_mesh* m, const double* dx, const double* dl, const HostTree& T, hipStream_t st);
+int32_t gpu_build_pattern(mpm_mesh* m, const double* dx, const double* dl, hipStream_t st);
 
 // ------------------------------------------------------------------ point keys
 // key = rank of the leaf containing the point's centre, value = original index; a stable
@@ -577,24 +577,6 @@ extern "C" int32_t octree_build(const mpm_refine_t* crit, const double* x, const
     mpm_mesh_free(m);
     return MPM_ESTENCIL;
   }
-  // host copies of the tree arrays that the host part of the construction reads
-  HostTree T;
-  {
-    T.cell_nodes.resize(size_t(m->n_leaf) * 8);
-    hipError_t e = hipMemcpy(T.cell_nodes.data(), m->d_cell_nodes, T.cell_nodes.size() * 4, hipMemcpyDeviceToHost);
-    if (e == hipSuccess && crit->ghost) {
-      T.leaf.resize(size_t(m->n_leaf) * 4);
-      T.leaf_key.resize(size_t(m->n_leaf));
-      T.cell_cmat.resize(size_t(m->n_leaf) * 64);
-      e = hipMemcpy(T.leaf.data(), m->d_leaf, T.leaf.size() * 4, hipMemcpyDeviceToHost);
-      if (e == hipSuccess) e = hipMemcpy(T.leaf_key.data(), m->d_leaf_key, T.leaf_key.size() * 8, hipMemcpyDeviceToHost);
-      if (e == hipSuccess) e = hipMemcpy(T.cell_cmat.data(), m->d_cell_cmat, T.cell_cmat.size() * 8, hipMemcpyDeviceToHost);
-    }
-    if (e != hipSuccess) {
-      mpm_mesh_free(m);
-      return hip_fail(e, "octree_build: tree download");
-    }
-  }
   // dense leaf map of the finest cells when it takes at most 1 GiB (else the leaf search
   // bisects the sorted leaf keys)
   const int64_t ncell = int64_t(m->nx) * m->ny * m->nz;
@@ -643,7 +625,7 @@ extern "C" int32_t octree_build(const mpm_refine_t* crit, const double* x, const
     }
   }
   // pattern, segments, records and contribution lists of the points
-  rc = gpu_build_pattern(m, dx, dl, T, st);
+  rc = gpu_build_pattern(m, dx, dl, st);
   if (!rc) rc = read_error(m, st, "octree_build (pattern)");
   if (rc) {
     (void)hipStreamSynchronize(st);

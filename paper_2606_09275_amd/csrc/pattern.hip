@@ -289,9 +289,8 @@ int bits_for(int64_t v) {
 
 // Builds, for the sorted and classified points of the mesh (perm, point leaf, overlap counts
 // on the device), the straddler lists, the CSR pattern, segments, records, contribution lists
-// and slot block columns, and the ghost faces when the criterion asks for them. T holds the
-// host copies of the tree arrays the ghost faces need (leaf, leaf_key, cell_nodes, cell_cmat).
-int32_t gpu_build_pattern(mpm_mesh* m, const double* dx, const double* dl, const HostTree& T, hipStream_t st) {
+// and slot block columns, and the ghost faces when the criterion asks for them.
+int32_t gpu_build_pattern(mpm_mesh* m, const double* dx, const double* dl, hipStream_t st) {
   const int64_t n = m->n_point, nl = m->n_leaf, nn = m->n_node;
   int32_t rc = MPM_OK;
   // straddling points (domain over several leaves) and their leaves
@@ -324,29 +323,17 @@ int32_t gpu_build_pattern(mpm_mesh* m, const double* dx, const double* dl, const
   int64_t npop = 0;
   if ((rc = read64(poff.as<int64_t>() + nl, &npop))) return rc;
 
-  // ghost faces (host): populated here means overlapped by any point domain
-  GhostHost gh;
+  // ghost faces: populated here means overlapped by any point domain
   if (m->crit.ghost && n) {
     if ((rc = anypop.alloc(size_t(nl) * 4, "octree_build: overlapped flags"))) return rc;
-    MPM_HIP(hipMemcpy(anypop.p, pop.p, size_t(nl) * 4, hipMemcpyDeviceToDevice));
+    MPM_HIP(hipMemcpyAsync(anypop.p, pop.p, size_t(nl) * 4, hipMemcpyDeviceToDevice, st));
     if (ns) hipLaunchKernelGGL(k_strad_pop, grid_of(ns), dim3(256), 0, st, m->d_strad_leaf, ns, anypop.as<int32_t>());
-    std::vector<int32_t> ap;
-    MPM_HIP(hipStreamSynchronize(st));
-    if ((rc = download(ap, anypop.as<int32_t>(), nl, "octree_build: overlapped flags"))) return rc;
-    std::vector<uint8_t> any(ap.begin(), ap.end());
-    LeafGeo HG = make_geo(m);
-    HG.leaf = T.leaf.data();
-    HG.leaf_key = T.leaf_key.data();
-    HG.cellmap = nullptr;
-    ghost_faces_host(T, HG, any, &gh);
-    if (gh.nf >= (int64_t(1) << 27)) {
-      set_error(MPM_EARG, "octree_build: too many ghost faces");
-      return MPM_EARG;
-    }
+    if ((rc = gpu_ghost_faces(m, anypop.as<int32_t>(), st))) return rc;
   }
+  const int64_t nf = m->n_gface;
 
   // node pairs: populated leaves (64 each), straddlers (support squared), ghost faces (256)
-  DevBuf scnt, soff, gnodes;
+  DevBuf scnt, soff;
   int64_t n_spair = 0;
   int32_t* d_stats = nullptr;  // [0] widest row, [1] active rows, [2] largest straddler support
   DevBuf stats;
@@ -362,7 +349,7 @@ int32_t gpu_build_pattern(mpm_mesh* m, const double* dx, const double* dl, const
     if ((rc = scan_counts(scnt.as<int32_t>(), ns, soff.as<int64_t>(), st))) return rc;
     if ((rc = read64(soff.as<int64_t>() + ns, &n_spair))) return rc;
   }
-  const int64_t n_lpair = 64 * npop, n_gpair = 256 * gh.nf;
+  const int64_t n_lpair = 64 * npop, n_gpair = 256 * nf;
   const int64_t npair = n_lpair + n_spair + n_gpair;
   DevBuf pairs, ucnt, uoff, upairs, nb_off;
   if ((rc = pairs.alloc(size_t(npair) * 8, "octree_build: node pairs"))) return rc;
@@ -371,12 +358,9 @@ int32_t gpu_build_pattern(mpm_mesh* m, const double* dx, const double* dl, const
   if (ns)
     hipLaunchKernelGGL(k_strad_pairs, grid_of(ns), dim3(256), 0, st, m->d_strad_leaf, ns, m->d_cell_nodes,
                        soff.as<int64_t>(), pairs.as<uint64_t>() + n_lpair);
-  if (gh.nf) {
-    if ((rc = gnodes.alloc(size_t(gh.nf) * 64, "octree_build: ghost face nodes"))) return rc;
-    MPM_HIP(hipMemcpy(gnodes.p, gh.nodes.data(), size_t(gh.nf) * 64, hipMemcpyHostToDevice));
-    hipLaunchKernelGGL(k_ghost_pairs, grid_of(n_gpair), dim3(256), 0, st, gnodes.as<int32_t>(), gh.nf,
+  if (nf)
+    hipLaunchKernelGGL(k_ghost_pairs, grid_of(n_gpair), dim3(256), 0, st, m->d_gf_nodes, nf,
                        pairs.as<uint64_t>() + n_lpair + n_spair);
-  }
   MPM_HIP(hipGetLastError());
   if ((rc = sort_u64(pairs.as<uint64_t>(), npair, 32 + bits_for(nn), st))) return rc;
   if ((rc = ucnt.alloc(size_t(npair) * 4, "octree_build: pair flags")) ||
@@ -529,45 +513,13 @@ int32_t gpu_build_pattern(mpm_mesh* m, const double* dx, const double* dl, const
     return MPM_ESTENCIL;
   }
 
-  // ghost couplings: block column of every face node pair in the first node's row (device),
-  // and per node its (face, local index) contributions in ascending face order (host)
-  if (gh.nf) {
-    std::vector<int32_t> gnode, gcon_off(1, 0), gcon;
-    std::vector<int32_t> gcnt(size_t(nn) + 1, 0);
-    for (int64_t f = 0; f < gh.nf; ++f) {
-      const int32_t* id = &gh.nodes[16 * f];
-      for (int a = 0; a < 16 && id[a] >= 0; ++a) gcnt[id[a] + 1]++;
-    }
-    std::vector<int32_t> slot(size_t(nn), -1);
-    for (int64_t a = 0; a < nn; ++a)
-      if (gcnt[a + 1]) {
-        slot[a] = int32_t(gnode.size());
-        gnode.push_back(int32_t(a));
-        gcon_off.push_back(gcon_off.back() + gcnt[a + 1]);
-      }
-    gcon.resize(gcon_off.back());
-    std::vector<int32_t> gfill(gcon_off.begin(), gcon_off.end() - 1);
-    for (int64_t f = 0; f < gh.nf; ++f) {
-      const int32_t* id = &gh.nodes[16 * f];
-      for (int a = 0; a < 16 && id[a] >= 0; ++a) gcon[gfill[slot[id[a]]]++] = int32_t(16 * f + a);
-    }
-    m->n_gface = gh.nf;
-    m->n_gnode = int64_t(gnode.size());
-    m->h_gface = gh.face;
-    if ((rc = upload_vec(&m->d_gf_leaf, gh.leaf2, "octree_build: ghost faces")) ||
-        (rc = upload_vec(&m->d_gf_G, gh.G, "octree_build: ghost faces")) ||
-        (rc = upload_vec(&m->d_gf_h, gh.h, "octree_build: ghost faces")) ||
-        (rc = upload_vec(&m->d_gnode, gnode, "octree_build: ghost nodes")) ||
-        (rc = upload_vec(&m->d_gcon_off, gcon_off, "octree_build: ghost nodes")) ||
-        (rc = upload_vec(&m->d_gcon, gcon, "octree_build: ghost nodes")))
-      return rc;
-    m->d_gf_nodes = gnodes.as<int32_t>();
-    gnodes.p = nullptr;
-    MPM_HIP(hipMalloc(&m->d_gf_bpos, size_t(gh.nf) * 256 * 2));
-    hipLaunchKernelGGL(k_ghost_bpos, grid_of(256 * gh.nf), dim3(256), 0, st, m->d_gf_nodes, gh.nf,
-                       upairs.as<uint64_t>(), nb_off.as<int64_t>(), m->d_gf_bpos);
+  // ghost couplings: block column of every face node pair in the first node's row
+  if (nf) {
+    MPM_HIP(hipMalloc(&m->d_gf_bpos, size_t(nf) * 256 * 2));
+    hipLaunchKernelGGL(k_ghost_bpos, grid_of(256 * nf), dim3(256), 0, st, m->d_gf_nodes, nf, upairs.as<uint64_t>(),
+                       nb_off.as<int64_t>(), m->d_gf_bpos);
     MPM_HIP(hipMalloc(&m->d_gbeta, size_t(nl) * 8));
-    MPM_HIP(hipMalloc(&m->d_gf_sc, size_t(gh.nf) * 8));
+    MPM_HIP(hipMalloc(&m->d_gf_sc, size_t(nf) * 8));
   }
 
   MPM_HIP(hipMalloc(&m->d_segK, size_t(std::max<int64_t>(1, nrec)) * 576 * 8));

@@ -6,7 +6,9 @@ exactly: the f_int entries and K rows of sampled nodes from an oracle run over e
 whose support holds those nodes, sigma of sampled points, and the adjoint gradients of 64
 seeded points (against the oracle and central differences); over the whole vectors, the
 internal forces balance and the body forces sum to the total weight. The ghost stabilisation
-at full size: faces and pattern bit-exact, its stiffness and force against the oracle's."""
+at full size: faces and pattern bit-exact, its stiffness and force against the oracle's. The
+Newmark inertia on sampled rows, and the CG solve of the full elastic tangent by its true
+residual."""
 import math
 
 import numpy as np
@@ -177,6 +179,78 @@ def _body_force_total(c):
     err = np.abs(tot - ref).max() / np.abs(ref).max()
     log(f"[parity] body force total: rel err {err:.2e}")
     assert err <= BODY_TOL
+
+
+def test_c2_dynamic_sampled_rows(c2):
+    """Newmark inertia at full size: f_int + inertia force and K + (2/dt^2) M rows of sampled
+    nodes, and the point accelerations and velocities of every point of those rows, against
+    an oracle run over the points whose support holds those nodes."""
+    m, o, w, ps = c2["m"], c2["o"], c2["w"], c2["ps"]
+    dt = 1e-3
+    v = W.make_velocity(w, ps)
+    perm = to_np(m.arrays()["perm"])
+    out = m.assemble_dynamic(c2["s_dev"], torch.from_numpy(c2["u"]).cuda(),
+                             torch.from_numpy(np.ascontiguousarray(v[:, perm])).cuda(), dt, "f64",
+                             want_sigma=False, want_kinematics=True)
+    torch.cuda.synchronize()
+    f = to_np(out["f_int"])
+    K = to_np(out["K"])
+    rp, col = o.csr()
+    rng = np.random.default_rng(12)
+    active = np.nonzero(np.diff(rp)[0::3] > 0)[0]
+    nodes = rng.choice(active, 24, replace=False)
+    idx = _subset_for_nodes(c2, nodes)
+    sub, ss = _oracle_subset(c2, idx)
+    ref = sub.assemble(ss, c2["u"])
+    ine = sub.inertia(ss, c2["u"], v[:, idx], dt)
+    srp, scol = sub.csr()
+    ef = ek = 0.0
+    fscale = np.abs(f).max()
+    for nd in nodes:
+        fr = ref["f_int"][3 * nd:3 * nd + 3] + ine["f_iner"][3 * nd:3 * nd + 3]
+        ef = max(ef, np.abs(f[3 * nd:3 * nd + 3] - fr).max() / fscale)
+        for r in range(3):
+            row = 3 * nd + r
+            a0, a1 = rp[row], rp[row + 1]
+            b0, b1 = srp[row], srp[row + 1]
+            assert np.array_equal(col[a0:a1], scol[b0:b1])
+            kr = ref["K"][b0:b1] + ine["K_mass"][b0:b1]
+            ek = max(ek, np.abs(K[a0:a1] - kr).max() / np.abs(kr).max())
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(perm.size)
+    ea = rel_err(to_np(out["a_new"])[:, inv[idx]], ine["a"])
+    ev = rel_err(to_np(out["v_new"])[:, inv[idx]], ine["v"])
+    log(f"[parity] c2 full dynamic: sampled f={ef:.2e} K rows={ek:.2e} a={ea:.2e} v={ev:.2e} ({idx.size} points)")
+    assert ef <= TOL64 and ek <= TOL64 and ea <= TOL64 and ev <= TOL64
+
+
+def test_c2_cg_solves_the_full_system(c2):
+    """Newton-step solve at full size: the CG solution of the elastic tangent (unstrained
+    start, body-force right-hand side) has a true relative residual at the requested tolerance
+    on the free DOFs, computed on the CPU from the same CSR values, and is zero on the
+    Dirichlet DOFs."""
+    from oracle.solve import csr, free_dofs
+    m, o = c2["m"], c2["o"]
+    s = dict(c2["s_dev"])
+    bn0 = torch.zeros_like(s["bn"])
+    bn0[:3] = 1.0
+    s.update(sy=torch.full_like(s["sy"], float("inf")), bn=bn0, Jn=torch.ones_like(s["Jn"]))
+    d = torch.from_numpy(W.dirichlet_dofs(c2["nodes"])).cuda()
+    fe = m.external_force(s)
+    u0 = torch.zeros(m.info["n_dof"], dtype=torch.float64, device="cuda")
+    out = m.assemble(s, u0, "f64", f_ext=fe, dirichlet=d, want_sigma=False)
+    b = -out["r"]
+    x, it, rel = m.solve_cg(out["K"], b, d, rtol=1e-6, max_iter=4000)
+    torch.cuda.synchronize()
+    a = m.arrays()
+    A = csr(to_np(a["row_ptr"]), to_np(a["col"]), to_np(out["K"]), m.info["n_dof"])
+    xn, bn = to_np(x), to_np(b)
+    free = free_dofs(A, to_np(d))
+    r = (bn - A @ xn)[free]
+    true_rel = np.linalg.norm(r) / np.linalg.norm(bn[free])
+    log(f"[parity] c2 full CG: {it} iterations, recursive {rel:.2e}, true residual {true_rel:.2e}")
+    assert rel <= 1e-6 and true_rel <= 2e-6
+    assert np.all(xn[~free] == 0.0)
 
 
 def test_c2_body_force_total(c2):

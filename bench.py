@@ -251,6 +251,8 @@ def main():
         out["ghost"] = ghost_stabilisation(w, x_dev, l_dev, views, u, f_ext, dirichlet, R["assemble_ms"])
         out["gimp_split"] = gimp_split(mesh, w)
     out["state_gather_runs_ms"] = gather_runs(mesh, packed, sorted_buf)
+    if not args.only and w.name.startswith("c2"):
+        out["supplementary"] = supplementary(w)
     if "prev_x_s" in w.extra:
         out["protocol"] = tool_protocol(mesh, w, nodes, views, x_dev, perm_buf, leaf_buf, packed, sorted_buf,
                                         f_ext, dirichlet, lam)
@@ -314,6 +316,50 @@ def ghost_stabilisation(w, x_dev, l_dev, views, u, f_ext, dirichlet, plain_ms, r
     log(f"[bench] ghost: {res['n_ghost_face']} faces, nnz {res['nnz']}, build {build_ms:.1f} ms, "
         f"assemble {ms:.3f} ms (plain {plain_ms:.3f} ms)")
     del gm
+    return res
+
+
+def supplementary(w_main, reps=5):
+    """Assembly throughput (FP64 and FP32K, mean of reps calls with HIP events, inputs sorted
+    and resident) of the other configurations: the sphere workload with full and with partial
+    yielding, and the jittered variant of the main workload (domains over several leaves run
+    the general path with atomics)."""
+    import torch
+    import workloads as W
+    from paper_2606_09275_amd.mesh import Mesh
+    res = {}
+    cases = [("c1", W.get("c1"), None), ("c1b", W.get("c1b"), None), (w_main.name.split("_")[0] + "_jittered", w_main, 0)]
+    for tag, w, jit in cases:
+        m0 = Mesh(w.crit())
+        lv = m0.arrays()["leaf"].cpu().numpy()
+        del m0
+        ps = W.make_points(w, lv[:, :3], lv[:, 3])
+        if jit is not None:
+            ps = W.jitter_points(w, ps, jit)
+        st = W.make_state(w, ps)
+        m = Mesh(w.crit(), torch.from_numpy(ps.x).cuda(), torch.from_numpy(ps.l).cuda())
+        nodes = m.arrays()["node_ijk"].cpu().numpy()
+        u = torch.from_numpy(W.make_u(w, nodes)).cuda()
+        s = m.sorted_state(st)
+        r = {"points": ps.n, "n_straddle": m.info["n_straddle"], "nnz": m.info["nnz"]}
+        for prec in ("f64", "f32k"):
+            outs = {}
+            m.assemble(s, u, prec, out=outs)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                m.assemble(s, u, prec, out=outs)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            r[f"assemble_{prec}_ms"] = ms
+            r[f"assembly_{prec}_points_per_s"] = ps.n / (ms * 1e-3)
+        log(f"[bench] {tag}: {ps.n} points ({r['n_straddle']} straddling), assembly FP64 "
+            f"{r['assemble_f64_ms']:.3f} ms ({r['assembly_f64_points_per_s']:.3e} pts/s), FP32K "
+            f"{r['assemble_f32k_ms']:.3f} ms")
+        res[tag] = r
+        del m, s, outs
     return res
 
 

@@ -617,36 +617,84 @@ __device__ int general_basis(const AsmArgs& A, int64_t t, const double x[3], con
   return ns;
 }
 
+// One wavefront per point whose domain overlaps several leaves. Lane 8q + v takes slot v of
+// the q-th overlapped leaf; the support is the union of the leaves' slot nodes in first-seen
+// order (the order of general_basis), and lane p of the support sums node p's contributions
+// in (leaf, slot) order. The point update is computed alike by every lane; lane a then adds
+// node a's force, and lane b the 3x3 blocks (a, b) of every row node a in turn, with atomics
+// (the three rows of a node share one column pattern: one bisection per block).
 template <typename T>
 __global__ __launch_bounds__(64) void k_assemble_general(AsmArgs A) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= A.n_strad) return;
+  __shared__ int32_t s_id[64];
+  __shared__ T s_c[64][4];   // (leaf, slot) entries: S and grad S
+  __shared__ int32_t s_first[64];
+  __shared__ T s_S[kMaxSup], s_dS[kMaxSup][3], s_g[kMaxSup][3];
+  __shared__ double s_u[kMaxSup][3];
+  __shared__ int32_t s_nd[kMaxSup];
+  const int64_t t = blockIdx.x;
+  const int lane = threadIdx.x;
   const int64_t i = A.strad[t], n = A.n;
   double x[3], l[3];
   for (int a = 0; a < 3; ++a) {
     x[a] = A.s.x[a * n + i];
     l[a] = A.s.l[a * n + i];
   }
-  int32_t nd[kMaxSup];
-  T S[kMaxSup], dS[kMaxSup][3];
-  const int ns = general_basis<T>(A, t, x, l, nd, S, dS);
-  T H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  for (int v = 0; v < ns; ++v) {
-    const double* uv = A.u + 3 * int64_t(nd[v]);
-    for (int r = 0; r < 3; ++r)
-      for (int q = 0; q < 3; ++q) H[r][q] += T(uv[r]) * dS[v][q];
+  // (leaf, slot) entries
+  const int q = lane >> 3, v = lane & 7;
+  const int32_t e = A.strad_leaf[t * kMaxPointLeaves + q];
+  int32_t id = -1;
+  if (e >= 0) {
+    T s8[8], d8[8][3];
+    leaf_overlap_basis<T>(A.G, e, A.cell_code[e], x, l, s8, d8);
+    id = A.cell_nodes[8 * int64_t(e) + v];
+    s_c[lane][0] = s8[v];
+    s_c[lane][1] = d8[v][0];
+    s_c[lane][2] = d8[v][1];
+    s_c[lane][3] = d8[v][2];
   }
+  s_id[lane] = id;
+  __syncthreads();
+  bool first = id >= 0;
+  for (int j = 0; j < lane && first; ++j) first = s_id[j] != id;
+  const uint64_t fm = __ballot(first);
+  const int ns = __popcll(fm);
+  if (first) s_first[__popcll(fm & ((1ull << lane) - 1ull))] = lane;
+  __syncthreads();
+  // support node p = lane: sum of its entries in (leaf, slot) order
+  if (lane < ns) {
+    const int32_t nd = s_id[s_first[lane]];
+    T S = 0, d0 = 0, d1 = 0, d2 = 0;
+    for (int j = 0; j < 64; ++j)
+      if (s_id[j] == nd) {
+        S += s_c[j][0];
+        d0 += s_c[j][1];
+        d1 += s_c[j][2];
+        d2 += s_c[j][3];
+      }
+    s_nd[lane] = nd;
+    s_S[lane] = S;
+    s_dS[lane][0] = d0;
+    s_dS[lane][1] = d1;
+    s_dS[lane][2] = d2;
+    for (int r = 0; r < 3; ++r) s_u[lane][r] = A.u[3 * int64_t(nd) + r];
+  }
+  __syncthreads();
+  // point update (every lane alike)
+  T H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int p = 0; p < ns; ++p)
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) H[r][c] += T(s_u[p][r]) * s_dS[p][c];
   T F[3][3], Fi[3][3];
   for (int r = 0; r < 3; ++r)
-    for (int q = 0; q < 3; ++q) F[r][q] = H[r][q] + (r == q ? T(1) : T(0));
+    for (int c = 0; c < 3; ++c) F[r][c] = H[r][c] + (r == c ? T(1) : T(0));
   const T Jd = inv3(F, Fi);
   const double Jn = A.s.Jn[i];
   if (!isfinite(double(Jd)) || !isfinite(Jn)) {
-    raise(A.err, MPM_ENONFINITE, i);
+    if (lane == 0) raise(A.err, MPM_ENONFINITE, i);
     return;
   }
   if (!(Jd > T(0))) {
-    raise(A.err, MPM_EDET, i);
+    if (lane == 0) raise(A.err, MPM_EDET, i);
     return;
   }
   T B[3][3];
@@ -654,56 +702,69 @@ __global__ __launch_bounds__(64) void k_assemble_general(AsmArgs A) {
   PointMat<T> P;
   const int st = material<T>(H, B, A.s.E[i], A.s.nu[i], A.s.sy[i], P);
   if (st) {
-    raise(A.err, st, i);
+    if (lane == 0) raise(A.err, st, i);
     return;
   }
-  write_point<T>(A, i, P, F, double(Jd) * Jn);
+  if (lane == 0) write_point<T>(A, i, P, F, double(Jd) * Jn);
   const T c = T(A.s.vol[i] / Jn);
-  T g[kMaxSup][3];
-  for (int v = 0; v < ns; ++v)
-    for (int q = 0; q < 3; ++q) g[v][q] = Fi[0][q] * dS[v][0] + Fi[1][q] * dS[v][1] + Fi[2][q] * dS[v][2];
+  if (lane < ns)
+    for (int k = 0; k < 3; ++k)
+      s_g[lane][k] = Fi[0][k] * s_dS[lane][0] + Fi[1][k] * s_dS[lane][1] + Fi[2][k] * s_dS[lane][2];
   double acc[3] = {0.0, 0.0, 0.0}, mp = 0.0;
   if (A.vel) {  // Newmark inertia, gamma = 1, beta = 1/2
     const double c2 = 2.0 / (A.dt * A.dt);
     mp = A.s.mass[i];
     for (int r = 0; r < 3; ++r) {
       double du = 0.0;
-      for (int v = 0; v < ns; ++v) du += double(S[v]) * A.u[3 * int64_t(nd[v]) + r];
+      for (int p = 0; p < ns; ++p) du += double(s_S[p]) * s_u[p][r];
       const double vr = A.vel[r * n + i];
       acc[r] = c2 * (du - A.dt * vr);
-      if (A.a_new) A.a_new[r * n + i] = acc[r];
-      if (A.v_new) A.v_new[r * n + i] = vr + A.dt * acc[r];
+      if (lane == 0 && A.a_new) A.a_new[r * n + i] = acc[r];
+      if (lane == 0 && A.v_new) A.v_new[r * n + i] = vr + A.dt * acc[r];
     }
   }
-  for (int v = 0; v < ns; ++v)
+  __syncthreads();
+  int32_t nda = 0;
+  T ga[3] = {0, 0, 0}, Sa = 0;
+  if (lane < ns) {
+    nda = s_nd[lane];
+    Sa = s_S[lane];
+    for (int k = 0; k < 3; ++k) ga[k] = s_g[lane][k];
     for (int r = 0; r < 3; ++r)
-      atomicAdd(A.f + 3 * int64_t(nd[v]) + r,
-                double(c) * double(P.tau[r][0] * g[v][0] + P.tau[r][1] * g[v][1] + P.tau[r][2] * g[v][2]) +
-                    double(S[v]) * mp * acc[r]);
+      atomicAdd(A.f + 3 * int64_t(nda) + r,
+                double(c) * double(P.tau[r][0] * ga[0] + P.tau[r][1] * ga[1] + P.tau[r][2] * ga[2]) +
+                    double(Sa) * mp * acc[r]);
+  }
   if (!A.K) return;
+  // block (a, b) with lane b: the linearised stress of direction g_b is formed once per lane;
+  // the rows a are taken in turn, so the atomics of one instruction fall into one CSR row
   T* Kout = reinterpret_cast<T*>(A.K);
-  for (int b = 0; b < ns; ++b) {
-    T gt[3], tg[3];
-    for (int al = 0; al < 3; ++al) gt[al] = P.N[0][al] * g[b][0] + P.N[1][al] * g[b][1] + P.N[2][al] * g[b][2];
-    for (int r = 0; r < 3; ++r) tg[r] = P.tau[r][0] * g[b][0] + P.tau[r][1] * g[b][1] + P.tau[r][2] * g[b][2];
-    T dt[3][3][3];
+  T dt[3][3][3], tg[3];
+  if (lane < ns) {
+    T gt[3];
+    for (int al = 0; al < 3; ++al) gt[al] = P.N[0][al] * ga[0] + P.N[1][al] * ga[1] + P.N[2][al] * ga[2];
+    for (int r = 0; r < 3; ++r) tg[r] = P.tau[r][0] * ga[0] + P.tau[r][1] * ga[1] + P.tau[r][2] * ga[2];
     for (int k = 0; k < 3; ++k) dtau_rank1<T>(P, k, gt, T(1), dt[k]);
-    for (int a = 0; a < ns; ++a) {
-      for (int r = 0; r < 3; ++r) {
-        const int64_t row = 3 * int64_t(nd[a]) + r;
-        const int64_t p0 = csr_pos(A.row_ptr, A.col, row, 3 * nd[b]);
-        if (p0 < 0) {
-          raise(A.err, MPM_ESTENCIL, i);
-          return;
-        }
-        for (int k = 0; k < 3; ++k) {
-          const T m = dt[k][r][0] * g[a][0] + dt[k][r][1] * g[a][1] + dt[k][r][2] * g[a][2] - tg[r] * g[a][k];
-          T val = c * m;
-          if (A.vel && r == k) val += T(2.0 * mp / (A.dt * A.dt)) * S[a] * S[b];
-          atomic_add_val<T>(Kout + p0 + k, val);
-        }
-      }
+  }
+  const T c2m = A.vel ? T(2.0 * mp / (A.dt * A.dt)) : T(0);
+  for (int a = 0; a < ns; ++a) {
+    if (lane >= ns) break;
+    const int32_t nra = s_nd[a];
+    const T g0 = s_g[a][0], g1 = s_g[a][1], g2 = s_g[a][2], Sr = s_S[a];
+    const int64_t r0 = A.row_ptr[3 * int64_t(nra)], len3 = A.row_ptr[3 * int64_t(nra) + 1] - r0;
+    const int64_t p0 = csr_pos(A.row_ptr, A.col, 3 * int64_t(nra), 3 * nda);
+    if (p0 < 0) {
+      raise(A.err, MPM_ESTENCIL, i);
+      break;
     }
+    for (int r = 0; r < 3; ++r)
+      for (int k = 0; k < 3; ++k) {
+        const T ak = k == 0 ? g0 : (k == 1 ? g1 : g2);
+        const T m = dt[k][r][0] * g0 + dt[k][r][1] * g1 + dt[k][r][2] * g2 - tg[r] * ak;
+        T val = c * m;
+        if (A.vel && r == k) val += c2m * Sa * Sr;
+        atomic_add_val<T>(Kout + p0 + r * len3 + k, val);
+      }
   }
 }
 
@@ -1046,8 +1107,8 @@ static int32_t assemble_impl(const mpm_mesh_t* m, const AsmArgs& A, int32_t prec
   if (precision == MPM_F64) launch_gather<double>(m, st, A);
   else launch_gather<float>(m, st, A);
   if (timed) MPM_HIP(hipEventRecord(mm->ev[4], st));
-  if (m->n_straddle) {
-    const dim3 grid(unsigned((m->n_straddle + 63) / 64));
+  if (m->n_straddle) {  // one wavefront per straddling point
+    const dim3 grid(unsigned(m->n_straddle));
     if (precision == MPM_F64) hipLaunchKernelGGL(k_assemble_general<double>, grid, dim3(64), 0, st, A);
     else hipLaunchKernelGGL(k_assemble_general<float>, grid, dim3(64), 0, st, A);
   }

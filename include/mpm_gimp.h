@@ -146,8 +146,9 @@ typedef struct {
  * G_F[a][b] = int_F [d_n phi~_a] [d_n phi~_b] dA of the jumps across F of the normal
  * derivatives of the two leaves' constrained trilinear basis functions (2 x 2 Gauss rule,
  * exact for the biquadratic integrand).
- * Host work: refinement, balance, numbering, CSR pattern, ghost faces. Device work:
- * point-to-leaf search, radix sort and overlap classification. */
+ * Every construction step runs on the device (refinement, balance, numbering, constraints,
+ * point order, overlap classification, CSR pattern, ghost faces); the host only reads counts
+ * between the steps and keeps the ghost face records. */
 int32_t octree_build(const mpm_refine_t* crit, const double* x, const double* l, int64_t n, void* stream,
                      mpm_mesh_t** out_mesh);
 int32_t mpm_mesh_info(const mpm_mesh_t* mesh, mpm_mesh_info_t* out);

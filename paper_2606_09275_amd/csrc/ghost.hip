@@ -1,8 +1,8 @@
 // Ghost stabilisation of the stiffness (Section 4, eq. ghost), device part: the largest
 // Young's modulus of the points overlapping each leaf, and one workgroup per node adding
 // (h_F beta_F / kappa) G_F to the diagonals of its 3x3 blocks and K_G u to its forces, with
-// beta_F the larger leaf maximum of the face's two leaves. The faces, G_F and h_F / kappa come
-// from the host part at mesh construction.
+// beta_F the larger leaf maximum of the face's two leaves. The faces, G_F and h_F / kappa are
+// built once per mesh (ghost_faces.hip).
 #include "geom.h"
 
 namespace mpm {

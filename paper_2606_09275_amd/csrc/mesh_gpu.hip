@@ -1,5 +1,6 @@
-// Mesh construction entry points: octree (host), point keys + LSD radix sort + leaf search
-// and overlap classification (device), CSR pattern and per-element slot map (host).
+// Mesh construction entry points and point order: octree_build (tree in tree.hip, then point
+// keys, LSD radix sort by leaf, overlap classification here, then the pattern in pattern.hip),
+// the point sort and state permutation of later steps, mesh queries and error reporting.
 #include <algorithm>
 #include <utility>
 #include <cstring>

@@ -2,6 +2,7 @@
 // keys, LSD radix sort by leaf, overlap classification here, then the pattern in pattern.hip),
 // the point sort and state permutation of later steps, mesh queries and error reporting.
 #include <algorithm>
+#include <cmath>
 #include <utility>
 #include <cstring>
 #include <mutex>
@@ -560,6 +561,19 @@ extern "C" int32_t octree_build(const mpm_refine_t* crit, const double* x, const
     return MPM_EARG;
   }
   *out_mesh = nullptr;
+  // criterion checks come before any device call
+  if (crit->lvl_max < crit->lvl_base || crit->lvl_max - crit->lvl_base > 13 || !(crit->h0 > 0) ||
+      !std::isfinite(crit->h0) || crit->base[0] <= 0 || crit->base[1] <= 0 || crit->base[2] <= 0 ||
+      crit->lvl_base < 0 || crit->lvl_max > 31 || crit->body_kind < MPM_BODY_NONE || crit->body_kind > MPM_BODY_BOX ||
+      !std::isfinite(crit->dx_region) || crit->dx_region < 0.0) {
+    set_error(MPM_EARG, "octree_build: bad refinement levels, base grid, h0, body kind or dx_region");
+    return MPM_EARG;
+  }
+  for (int a = 0; a < 3; ++a)
+    if (int64_t(crit->base[a]) << (crit->lvl_max - crit->lvl_base) >= (int64_t(1) << 13)) {
+      set_error(MPM_ESTENCIL, "octree_build: finest lattice exceeds 8191 cells per axis");
+      return MPM_ESTENCIL;
+    }
   hipStream_t st = (hipStream_t)stream;
   mpm_mesh* m = new mpm_mesh();
   m->crit = *crit;

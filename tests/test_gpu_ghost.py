@@ -151,3 +151,31 @@ def test_no_ghost_faces_on_a_filled_mesh():
     assert m.info["n_ghost_face"] == 0
     rp, col = o.csr()
     assert np.array_equal(to_np(m.arrays()["col"]), col)
+
+
+def test_c1_ghost_full_size():
+    """The sphere workload at full size (151 168 points filling z < 0.6 around a refined
+    sphere): ghost faces and pattern bit-exact, and f_int and K with the penalty against the
+    oracle's point terms plus its ghost term."""
+    from paper_2606_09275_amd.mesh import Mesh
+    w = W.get("c1")
+    o = OracleMesh(w.crit(), ghost=True)
+    lv = o.leaves()
+    ps = W.make_points(w, lv[:, :3], lv[:, 3])
+    o.set_points(ps.x, ps.l)
+    m = Mesh(w.crit(), torch.from_numpy(ps.x).cuda(), torch.from_numpy(ps.l).cuda(), ghost=True)
+    f = m.ghost_faces()
+    assert f.shape[0] > 0 and np.array_equal(f, o.ghost_faces())
+    rp, col = o.csr()
+    a = m.arrays()
+    assert np.array_equal(to_np(a["row_ptr"]), rp) and np.array_equal(to_np(a["col"]), col)
+    st = W.make_state(w, ps)
+    u = W.make_u(w, o.nodes())
+    ref = o.assemble(st, u)
+    g = o.ghost(st, u)
+    out = m.assemble(m.sorted_state(st), torch.from_numpy(u).cuda(), "f64", want_sigma=False)
+    torch.cuda.synchronize()
+    e_k = rel_err(to_np(out["K"]), ref["K"] + g["K"])
+    e_f = rel_err(to_np(out["f_int"]), ref["f_int"] + g["f"])
+    log(f"[parity] c1 ghost full: {f.shape[0]} faces, K={e_k:.2e} f={e_f:.2e}")
+    assert e_k <= TOL64 and e_f <= TOL64

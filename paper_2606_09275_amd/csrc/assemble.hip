@@ -30,6 +30,9 @@ struct AsmArgs {
   const int32_t* col;
   const int64_t* strad;
   const int32_t* strad_leaf;
+  const int32_t* snode;      // rows reached by straddling points
+  const int64_t* sinc_off;   // per such row: its straddling points
+  const int32_t* sinc;
   int64_t n, n_strad;
   mpm_state_t s;
   const double* u;
@@ -617,154 +620,156 @@ __device__ int general_basis(const AsmArgs& A, int64_t t, const double x[3], con
   return ns;
 }
 
-// One wavefront per point whose domain overlaps several leaves. Lane 8q + v takes slot v of
-// the q-th overlapped leaf; the support is the union of the leaves' slot nodes in first-seen
-// order (the order of general_basis), and lane p of the support sums node p's contributions
-// in (leaf, slot) order. The point update is computed alike by every lane; lane a then adds
-// node a's force, and lane b the 3x3 blocks (a, b) of every row node a in turn, with atomics
-// (the three rows of a node share one column pattern: one bisection per block).
+// Points whose domain overlaps several leaves, gathered by the rows they reach: one wavefront
+// per node a, one lane per straddling point whose support holds a (64 at a time, ascending).
+// Each lane recomputes its point's update from the leaves it overlaps, then the force on a and
+// the row-a blocks: K_ab is linear in grad S_b, so every (leaf, slot) term of the point adds
+// its own block to the column of its slot node (LDS additions into the node's three rows),
+// the block being a fixed 9x3 map of the term's spatial gradient per (point, row).
+// The force is summed over the lanes in a fixed order; rows and forces are then added to the
+// values the fast path wrote. No global atomics. One row per point (that of the first slot of
+// its first leaf) also writes the point's stress, committed state and Newmark kinematics.
 template <typename T>
-__global__ __launch_bounds__(64) void k_assemble_general(AsmArgs A) {
-  __shared__ int32_t s_id[64];
-  __shared__ T s_c[64][4];   // (leaf, slot) entries: S and grad S
-  __shared__ int32_t s_first[64];
-  __shared__ T s_S[kMaxSup], s_dS[kMaxSup][3], s_g[kMaxSup][3];
-  __shared__ double s_u[kMaxSup][3];
-  __shared__ int32_t s_nd[kMaxSup];
-  const int64_t t = blockIdx.x;
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : 3)))
+void k_general_rows(AsmArgs A) {
+  extern __shared__ __align__(16) unsigned char gsm[];
+  const int64_t na = A.snode[blockIdx.x];
   const int lane = threadIdx.x;
-  const int64_t i = A.strad[t], n = A.n;
-  double x[3], l[3];
-  for (int a = 0; a < 3; ++a) {
-    x[a] = A.s.x[a * n + i];
-    l[a] = A.s.l[a * n + i];
-  }
-  // (leaf, slot) entries
-  const int q = lane >> 3, v = lane & 7;
-  const int32_t e = A.strad_leaf[t * kMaxPointLeaves + q];
-  int32_t id = -1;
-  if (e >= 0) {
-    T s8[8], d8[8][3];
-    leaf_overlap_basis<T>(A.G, e, A.cell_code[e], x, l, s8, d8);
-    id = A.cell_nodes[8 * int64_t(e) + v];
-    s_c[lane][0] = s8[v];
-    s_c[lane][1] = d8[v][0];
-    s_c[lane][2] = d8[v][1];
-    s_c[lane][3] = d8[v][2];
-  }
-  s_id[lane] = id;
-  __syncthreads();
-  bool first = id >= 0;
-  for (int j = 0; j < lane && first; ++j) first = s_id[j] != id;
-  const uint64_t fm = __ballot(first);
-  const int ns = __popcll(fm);
-  if (first) s_first[__popcll(fm & ((1ull << lane) - 1ull))] = lane;
-  __syncthreads();
-  // support node p = lane: sum of its entries in (leaf, slot) order
-  if (lane < ns) {
-    const int32_t nd = s_id[s_first[lane]];
-    T S = 0, d0 = 0, d1 = 0, d2 = 0;
-    for (int j = 0; j < 64; ++j)
-      if (s_id[j] == nd) {
-        S += s_c[j][0];
-        d0 += s_c[j][1];
-        d1 += s_c[j][2];
-        d2 += s_c[j][3];
-      }
-    s_nd[lane] = nd;
-    s_S[lane] = S;
-    s_dS[lane][0] = d0;
-    s_dS[lane][1] = d1;
-    s_dS[lane][2] = d2;
-    for (int r = 0; r < 3; ++r) s_u[lane][r] = A.u[3 * int64_t(nd) + r];
+  const int64_t r0 = A.row_ptr[3 * na];
+  const int deg = int((A.row_ptr[3 * na + 1] - r0) / 3);
+  T* acc = reinterpret_cast<T*>(gsm);
+  int32_t* rcol = reinterpret_cast<int32_t*>(acc + 9 * deg);  // block-column nodes of the row
+  const bool wantK = A.K != nullptr;
+  if (wantK) {
+    for (int j = lane; j < 9 * deg; j += 64) acc[j] = T(0);
+    for (int j = lane; j < deg; j += 64) rcol[j] = A.col[r0 + 3 * j] / 3;
   }
   __syncthreads();
-  // point update (every lane alike)
-  T H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  for (int p = 0; p < ns; ++p)
-    for (int r = 0; r < 3; ++r)
-      for (int c = 0; c < 3; ++c) H[r][c] += T(s_u[p][r]) * s_dS[p][c];
-  T F[3][3], Fi[3][3];
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c) F[r][c] = H[r][c] + (r == c ? T(1) : T(0));
-  const T Jd = inv3(F, Fi);
-  const double Jn = A.s.Jn[i];
-  if (!isfinite(double(Jd)) || !isfinite(Jn)) {
-    if (lane == 0) raise(A.err, MPM_ENONFINITE, i);
-    return;
+  const int64_t n = A.n;
+  double fa[3] = {0.0, 0.0, 0.0};
+  const int64_t c0 = A.sinc_off[blockIdx.x], c1 = A.sinc_off[blockIdx.x + 1];
+  for (int64_t cb = c0; cb < c1; cb += 64) {
+    const int64_t e = cb + lane;
+    if (e < c1) do {
+        const int64_t t = A.sinc[e];
+        const int64_t i = A.strad[t];
+        double x[3], l[3];
+        for (int q = 0; q < 3; ++q) {
+          x[q] = A.s.x[q * n + i];
+          l[q] = A.s.l[q * n + i];
+        }
+        const int32_t* lv = A.strad_leaf + t * kMaxPointLeaves;
+        // pass 1: displacement gradient, and S and grad S of node a
+        T H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        T Sa = 0, dSa[3] = {0, 0, 0};
+        double du[3] = {0.0, 0.0, 0.0};
+        for (int q = 0; q < kMaxPointLeaves && lv[q] >= 0; ++q) {
+          T s8[8], d8[8][3];
+          leaf_overlap_basis<T>(A.G, lv[q], A.cell_code[lv[q]], x, l, s8, d8);
+          for (int v = 0; v < 8; ++v) {
+            const int32_t id = A.cell_nodes[8 * int64_t(lv[q]) + v];
+            const double* uv = A.u + 3 * int64_t(id);
+            for (int r = 0; r < 3; ++r) {
+              for (int c = 0; c < 3; ++c) H[r][c] += T(uv[r]) * d8[v][c];
+              du[r] += double(s8[v]) * uv[r];
+            }
+            if (id == na) {
+              Sa += s8[v];
+              for (int c = 0; c < 3; ++c) dSa[c] += d8[v][c];
+            }
+          }
+        }
+        T F[3][3], Fi[3][3];
+        for (int r = 0; r < 3; ++r)
+          for (int c = 0; c < 3; ++c) F[r][c] = H[r][c] + (r == c ? T(1) : T(0));
+        const T Jd = inv3(F, Fi);
+        const double Jn = A.s.Jn[i];
+        if (!isfinite(double(Jd)) || !isfinite(Jn)) {
+          raise(A.err, MPM_ENONFINITE, i);
+          break;
+        }
+        if (!(Jd > T(0))) {
+          raise(A.err, MPM_EDET, i);
+          break;
+        }
+        T B[3][3];
+        load_B<T>(A.s, n, i, B);
+        PointMat<T> P;
+        const int stc = material<T>(H, B, A.s.E[i], A.s.nu[i], A.s.sy[i], P);
+        if (stc) {
+          raise(A.err, stc, i);
+          break;
+        }
+        const bool writer = A.cell_nodes[8 * int64_t(lv[0])] == na;
+        if (writer) write_point<T>(A, i, P, F, double(Jd) * Jn);
+        const T c = T(A.s.vol[i] / Jn);
+        T ga[3];
+        for (int k = 0; k < 3; ++k) ga[k] = Fi[0][k] * dSa[0] + Fi[1][k] * dSa[1] + Fi[2][k] * dSa[2];
+        double acc_p[3] = {0.0, 0.0, 0.0}, mp = 0.0;
+        if (A.vel) {  // Newmark inertia, gamma = 1, beta = 1/2
+          const double c2 = 2.0 / (A.dt * A.dt);
+          mp = A.s.mass[i];
+          for (int r = 0; r < 3; ++r) {
+            const double vr = A.vel[r * n + i];
+            acc_p[r] = c2 * (du[r] - A.dt * vr);
+            if (writer && A.a_new) A.a_new[r * n + i] = acc_p[r];
+            if (writer && A.v_new) A.v_new[r * n + i] = vr + A.dt * acc_p[r];
+          }
+        }
+        for (int r = 0; r < 3; ++r)
+          fa[r] += double(c) * double(P.tau[r][0] * ga[0] + P.tau[r][1] * ga[1] + P.tau[r][2] * ga[2]) +
+                   double(Sa) * mp * acc_p[r];
+        if (!wantK) break;
+        // pass 2: the row-a block of every (leaf, slot) term. The block is linear in the
+        // term's spatial gradient g: block_rk = sum_j Mb[r][k][j] g_j, Mb from g = e_0, e_1, e_2.
+        const T c2m = A.vel ? T(2.0 * mp / (A.dt * A.dt)) : T(0);
+        T Mb[3][3][3];
+        for (int j = 0; j < 3; ++j) {
+          const T gt[3] = {P.N[j][0], P.N[j][1], P.N[j][2]};  // N^T e_j
+          for (int k = 0; k < 3; ++k) {
+            T dtk[3][3];
+            dtau_rank1<T>(P, k, gt, T(1), dtk);
+            for (int r = 0; r < 3; ++r)
+              Mb[r][k][j] = c * (dtk[r][0] * ga[0] + dtk[r][1] * ga[1] + dtk[r][2] * ga[2] - P.tau[r][j] * ga[k]);
+          }
+        }
+        for (int q = 0; q < kMaxPointLeaves && lv[q] >= 0; ++q) {
+          T s8[8], d8[8][3];
+          leaf_overlap_basis<T>(A.G, lv[q], A.cell_code[lv[q]], x, l, s8, d8);
+          for (int v = 0; v < 8; ++v) {
+            const int32_t id = A.cell_nodes[8 * int64_t(lv[q]) + v];
+            T gb[3];
+            for (int k = 0; k < 3; ++k) gb[k] = Fi[0][k] * d8[v][0] + Fi[1][k] * d8[v][1] + Fi[2][k] * d8[v][2];
+            int lo = 0, hi = deg;  // block column of node id in row a
+            while (lo < hi) {
+              const int mid = (lo + hi) >> 1;
+              if (rcol[mid] < id) lo = mid + 1;
+              else hi = mid;
+            }
+            if (lo >= deg || rcol[lo] != id) {
+              raise(A.err, MPM_ESTENCIL, i);
+              continue;
+            }
+            for (int r = 0; r < 3; ++r)
+              for (int k = 0; k < 3; ++k) {
+                T val = Mb[r][k][0] * gb[0] + Mb[r][k][1] * gb[1] + Mb[r][k][2] * gb[2];
+                if (A.vel && r == k) val += c2m * Sa * s8[v];
+                atomicAdd(acc + r * 3 * deg + 3 * lo + k, val);
+              }
+          }
+        }
+      } while (false);
   }
-  if (!(Jd > T(0))) {
-    if (lane == 0) raise(A.err, MPM_EDET, i);
-    return;
-  }
-  T B[3][3];
-  load_B<T>(A.s, n, i, B);
-  PointMat<T> P;
-  const int st = material<T>(H, B, A.s.E[i], A.s.nu[i], A.s.sy[i], P);
-  if (st) {
-    if (lane == 0) raise(A.err, st, i);
-    return;
-  }
-  if (lane == 0) write_point<T>(A, i, P, F, double(Jd) * Jn);
-  const T c = T(A.s.vol[i] / Jn);
-  if (lane < ns)
-    for (int k = 0; k < 3; ++k)
-      s_g[lane][k] = Fi[0][k] * s_dS[lane][0] + Fi[1][k] * s_dS[lane][1] + Fi[2][k] * s_dS[lane][2];
-  double acc[3] = {0.0, 0.0, 0.0}, mp = 0.0;
-  if (A.vel) {  // Newmark inertia, gamma = 1, beta = 1/2
-    const double c2 = 2.0 / (A.dt * A.dt);
-    mp = A.s.mass[i];
-    for (int r = 0; r < 3; ++r) {
-      double du = 0.0;
-      for (int p = 0; p < ns; ++p) du += double(s_S[p]) * s_u[p][r];
-      const double vr = A.vel[r * n + i];
-      acc[r] = c2 * (du - A.dt * vr);
-      if (lane == 0 && A.a_new) A.a_new[r * n + i] = acc[r];
-      if (lane == 0 && A.v_new) A.v_new[r * n + i] = vr + A.dt * acc[r];
-    }
-  }
+  // forces of the lanes' points in lane order, then the rows
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1)
+    for (int r = 0; r < 3; ++r) fa[r] += __shfl_xor(fa[r], off);
   __syncthreads();
-  int32_t nda = 0;
-  T ga[3] = {0, 0, 0}, Sa = 0;
-  if (lane < ns) {
-    nda = s_nd[lane];
-    Sa = s_S[lane];
-    for (int k = 0; k < 3; ++k) ga[k] = s_g[lane][k];
-    for (int r = 0; r < 3; ++r)
-      atomicAdd(A.f + 3 * int64_t(nda) + r,
-                double(c) * double(P.tau[r][0] * ga[0] + P.tau[r][1] * ga[1] + P.tau[r][2] * ga[2]) +
-                    double(Sa) * mp * acc[r]);
-  }
-  if (!A.K) return;
-  // block (a, b) with lane b: the linearised stress of direction g_b is formed once per lane;
-  // the rows a are taken in turn, so the atomics of one instruction fall into one CSR row
-  T* Kout = reinterpret_cast<T*>(A.K);
-  T dt[3][3][3], tg[3];
-  if (lane < ns) {
-    T gt[3];
-    for (int al = 0; al < 3; ++al) gt[al] = P.N[0][al] * ga[0] + P.N[1][al] * ga[1] + P.N[2][al] * ga[2];
-    for (int r = 0; r < 3; ++r) tg[r] = P.tau[r][0] * ga[0] + P.tau[r][1] * ga[1] + P.tau[r][2] * ga[2];
-    for (int k = 0; k < 3; ++k) dtau_rank1<T>(P, k, gt, T(1), dt[k]);
-  }
-  const T c2m = A.vel ? T(2.0 * mp / (A.dt * A.dt)) : T(0);
-  for (int a = 0; a < ns; ++a) {
-    if (lane >= ns) break;
-    const int32_t nra = s_nd[a];
-    const T g0 = s_g[a][0], g1 = s_g[a][1], g2 = s_g[a][2], Sr = s_S[a];
-    const int64_t r0 = A.row_ptr[3 * int64_t(nra)], len3 = A.row_ptr[3 * int64_t(nra) + 1] - r0;
-    const int64_t p0 = csr_pos(A.row_ptr, A.col, 3 * int64_t(nra), 3 * nda);
-    if (p0 < 0) {
-      raise(A.err, MPM_ESTENCIL, i);
-      break;
-    }
-    for (int r = 0; r < 3; ++r)
-      for (int k = 0; k < 3; ++k) {
-        const T ak = k == 0 ? g0 : (k == 1 ? g1 : g2);
-        const T m = dt[k][r][0] * g0 + dt[k][r][1] * g1 + dt[k][r][2] * g2 - tg[r] * ak;
-        T val = c * m;
-        if (A.vel && r == k) val += c2m * Sa * Sr;
-        atomic_add_val<T>(Kout + p0 + r * len3 + k, val);
-      }
+  if (lane < 3) A.f[3 * na + lane] += fa[lane];
+  if (wantK) {
+    T* Kout = reinterpret_cast<T*>(A.K);
+    for (int j = lane; j < 9 * deg; j += 64)
+      if (acc[j] != T(0)) Kout[r0 + j] += acc[j];
   }
 }
 
@@ -998,6 +1003,9 @@ static AsmArgs make_args(const mpm_mesh* m, const mpm_state_t* s) {
   A.col = m->d_col;
   A.strad = m->d_strad;
   A.strad_leaf = m->d_strad_leaf;
+  A.snode = m->d_snode;
+  A.sinc_off = m->d_sinc_off;
+  A.sinc = m->d_sinc;
   A.n = m->n_point;
   A.n_strad = m->n_straddle;
   A.s = *s;
@@ -1107,10 +1115,12 @@ static int32_t assemble_impl(const mpm_mesh_t* m, const AsmArgs& A, int32_t prec
   if (precision == MPM_F64) launch_gather<double>(m, st, A);
   else launch_gather<float>(m, st, A);
   if (timed) MPM_HIP(hipEventRecord(mm->ev[4], st));
-  if (m->n_straddle) {  // one wavefront per straddling point
-    const dim3 grid(unsigned(m->n_straddle));
-    if (precision == MPM_F64) hipLaunchKernelGGL(k_assemble_general<double>, grid, dim3(64), 0, st, A);
-    else hipLaunchKernelGGL(k_assemble_general<float>, grid, dim3(64), 0, st, A);
+  if (m->n_snode) {  // rows reached by points whose domain overlaps several leaves
+    const dim3 grid(unsigned(m->n_snode));
+    if (precision == MPM_F64)
+      hipLaunchKernelGGL(k_general_rows<double>, grid, dim3(64), size_t(9 * 8 + 4) * m->max_deg, st, A);
+    else
+      hipLaunchKernelGGL(k_general_rows<float>, grid, dim3(64), size_t(9 * 4 + 4) * m->max_deg, st, A);
   }
   // ghost penalty (Section 4): after every point term, before the residual
   if (const int32_t rg = ghost_apply(m, &A.s, A.u, precision, K_vals, f_int, st)) return rg;

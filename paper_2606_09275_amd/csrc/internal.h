@@ -108,6 +108,12 @@ struct mpm_mesh {
   int32_t* d_red2 = nullptr;        // n_red2 x 3: chunk records of a heavy leaf
   int64_t* d_strad = nullptr;       // n_straddle sorted positions
   int32_t* d_strad_leaf = nullptr;  // n_straddle x 8 overlapped leaves (-1 pad)
+  // rows that straddling points reach: the nodes in their supports and, per node, the
+  // straddling points (indices into d_strad) whose support holds it, in ascending order
+  int64_t n_snode = 0;
+  int32_t* d_snode = nullptr;       // n_snode
+  int64_t* d_sinc_off = nullptr;    // n_snode + 1
+  int32_t* d_sinc = nullptr;
   mpm::DevErr* d_err = nullptr;
   mpm::DevErr* h_err = nullptr;     // pinned host copy of the error word
   hipEvent_t err_ev = nullptr;      // marks the error-word copy (polled, no blocking sync)

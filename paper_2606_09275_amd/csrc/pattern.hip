@@ -82,6 +82,42 @@ __global__ void k_strad_pairs(const int32_t* __restrict__ sleaf, int64_t ns, con
     for (int b = 0; b < k; ++b) o[a * k + b] = (uint64_t(uint32_t(sup[a])) << 32) | uint32_t(sup[b]);
 }
 
+__global__ void k_strad_nsup(const int32_t* __restrict__ sleaf, int64_t ns, const int32_t* __restrict__ cell_nodes,
+                             int32_t* __restrict__ cnt) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= ns) return;
+  int32_t sup[kMaxPointLeaves * 8];
+  cnt[t] = strad_support(sleaf, t, cell_nodes, sup);
+}
+// (support node, straddling point) incidences
+__global__ void k_strad_inc(const int32_t* __restrict__ sleaf, int64_t ns, const int32_t* __restrict__ cell_nodes,
+                            const int64_t* __restrict__ off, uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= ns) return;
+  int32_t sup[kMaxPointLeaves * 8];
+  const int k = strad_support(sleaf, t, cell_nodes, sup);
+  for (int z = 0; z < k; ++z) {
+    key[off[t] + z] = uint32_t(sup[z]);
+    val[off[t] + z] = uint32_t(t);
+  }
+}
+__global__ void k_key_runs(const uint32_t* __restrict__ key, int64_t n, int32_t* __restrict__ cnt) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) cnt[i] = (i == 0 || key[i] != key[i - 1]) ? 1 : 0;
+}
+__global__ void k_run_tables(const uint32_t* __restrict__ key, const uint32_t* __restrict__ val,
+                             const int32_t* __restrict__ cnt, const int64_t* __restrict__ off, int64_t n,
+                             int32_t* __restrict__ node, int64_t* __restrict__ start, int32_t* __restrict__ items) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (cnt[i]) {
+    node[off[i]] = int32_t(key[i]);
+    start[off[i]] = i;
+  }
+  if (i == n - 1) start[off[n]] = n;
+  items[i] = int32_t(val[i]);
+}
+
 __global__ void k_leaf_pairs(const int32_t* __restrict__ pop, const int64_t* __restrict__ poff, int64_t nl,
                              const int32_t* __restrict__ cell_nodes, uint64_t* __restrict__ pairs) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -520,6 +556,46 @@ int32_t gpu_build_pattern(mpm_mesh* m, const double* dx, const double* dl, hipSt
                        nb_off.as<int64_t>(), m->d_gf_bpos);
     MPM_HIP(hipMalloc(&m->d_gbeta, size_t(nl) * 8));
     MPM_HIP(hipMalloc(&m->d_gf_sc, size_t(nf) * 8));
+  }
+
+  // rows reached by straddling points, each with its points in ascending order
+  m->n_snode = 0;
+  if (ns) {
+    DevBuf sc, so, sk, sv, skt, svt, sh, rcn, ro;
+    if ((rc = sc.alloc(size_t(ns) * 4, "octree_build: straddle supports")) ||
+        (rc = so.alloc(size_t(ns + 1) * 8, "octree_build: straddle supports")))
+      return rc;
+    hipLaunchKernelGGL(k_strad_nsup, grid_of(ns), dim3(256), 0, st, m->d_strad_leaf, ns, m->d_cell_nodes,
+                       sc.as<int32_t>());
+    if ((rc = scan_counts(sc.as<int32_t>(), ns, so.as<int64_t>(), st))) return rc;
+    int64_t ninc = 0;
+    if ((rc = read64(so.as<int64_t>() + ns, &ninc))) return rc;
+    const int64_t nblk2 = (ninc + kRsTile - 1) / kRsTile;
+    if ((rc = sk.alloc(size_t(ninc) * 4, "octree_build: straddle incidences")) ||
+        (rc = sv.alloc(size_t(ninc) * 4, "octree_build: straddle incidences")) ||
+        (rc = skt.alloc(size_t(ninc) * 4, "octree_build: straddle incidences")) ||
+        (rc = svt.alloc(size_t(ninc) * 4, "octree_build: straddle incidences")) ||
+        (rc = sh.alloc(size_t(nblk2) * 1024 + 1024, "octree_build: straddle incidence counts")) ||
+        (rc = rcn.alloc(size_t(ninc) * 4, "octree_build: straddle rows")) ||
+        (rc = ro.alloc(size_t(ninc + 1) * 8, "octree_build: straddle rows")))
+      return rc;
+    hipLaunchKernelGGL(k_strad_inc, grid_of(ns), dim3(256), 0, st, m->d_strad_leaf, ns, m->d_cell_nodes,
+                       so.as<int64_t>(), sk.as<uint32_t>(), sv.as<uint32_t>());
+    uint32_t *ks2 = sk.as<uint32_t>(), *vs2 = sv.as<uint32_t>();
+    if ((rc = radix_sort(sk.as<uint32_t>(), sv.as<uint32_t>(), ninc, bits_for(nn), skt.as<uint32_t>(),
+                         svt.as<uint32_t>(), sh.as<uint32_t>(), sh.as<uint32_t>() + size_t(nblk2) * 256, st, &ks2,
+                         &vs2)))
+      return rc;
+    hipLaunchKernelGGL(k_key_runs, grid_of(ninc), dim3(256), 0, st, ks2, ninc, rcn.as<int32_t>());
+    if ((rc = scan_counts(rcn.as<int32_t>(), ninc, ro.as<int64_t>(), st))) return rc;
+    if ((rc = read64(ro.as<int64_t>() + ninc, &m->n_snode))) return rc;
+    MPM_HIP(hipMalloc(&m->d_snode, size_t(std::max<int64_t>(1, m->n_snode)) * 4));
+    MPM_HIP(hipMalloc(&m->d_sinc_off, size_t(m->n_snode + 1) * 8));
+    MPM_HIP(hipMalloc(&m->d_sinc, size_t(std::max<int64_t>(1, ninc)) * 4));
+    hipLaunchKernelGGL(k_run_tables, grid_of(ninc), dim3(256), 0, st, ks2, vs2, rcn.as<int32_t>(), ro.as<int64_t>(),
+                       ninc, m->d_snode, m->d_sinc_off, m->d_sinc);
+    MPM_HIP(hipGetLastError());
+    MPM_HIP(hipStreamSynchronize(st));
   }
 
   MPM_HIP(hipMalloc(&m->d_segK, size_t(std::max<int64_t>(1, nrec)) * 576 * 8));

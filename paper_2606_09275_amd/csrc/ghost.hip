@@ -8,19 +8,17 @@
 namespace mpm {
 
 // ------------------------------------------------------------------ device
-// beta[e] = largest Young's modulus of the points overlapping leaf e (0 if none); E > 0, so
-// the integer order of the IEEE bit patterns is the order of the values.
-__global__ void k_zero_beta(double* beta, int64_t nl) {
-  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (e < nl) beta[e] = 0.0;
-}
-
-// Points are sorted by leaf: a segmented maximum over each wavefront's runs of one leaf,
-// then one atomic per run (points overlapping several leaves count in k_leaf_beta_strad).
-__global__ __launch_bounds__(256) void k_leaf_beta(const double* __restrict__ E, const int32_t* __restrict__ pleaf,
-                                                   const uint8_t* __restrict__ pnleaf, int64_t n, double* beta) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & 63;
+// beta[e] = largest Young's modulus of the points overlapping leaf e (0 if none). Points are
+// sorted by leaf: one wavefront per 64 points takes the maximum of each of its segments (runs
+// of one leaf), then one wavefront per leaf the maximum over the leaf's segments, so a leaf
+// holding many points needs no atomics. Points overlapping several leaves count in
+// k_leaf_beta_strad (E > 0, so the integer order of the IEEE bit patterns is the order of the
+// values there).
+__global__ __launch_bounds__(64) void k_seg_beta(const double* __restrict__ E, const int32_t* __restrict__ pleaf,
+                                                 const uint8_t* __restrict__ pnleaf, int64_t n,
+                                                 const int32_t* __restrict__ wave_seg, double* __restrict__ segmax) {
+  const int64_t i = int64_t(blockIdx.x) * 64 + threadIdx.x;
+  const int lane = threadIdx.x;
   int32_t leaf = -1;
   double v = 0.0;
   if (i < n) {
@@ -34,8 +32,20 @@ __global__ __launch_bounds__(256) void k_leaf_beta(const double* __restrict__ E,
     if (lane + off < 64 && ol == leaf) v = fmax(v, ov);
   }
   const int32_t prev = __shfl_up(leaf, 1);
-  if (i < n && (lane == 0 || prev != leaf) && v > 0.0)
-    atomicMax(reinterpret_cast<unsigned long long*>(beta + leaf), (unsigned long long)__double_as_longlong(v));
+  const bool head = i < n && (lane == 0 || prev != leaf);
+  const uint64_t hm = __ballot(head);
+  if (head) segmax[wave_seg[blockIdx.x] + __popcll(hm & ((1ull << lane) - 1ull))] = v;
+}
+
+__global__ __launch_bounds__(64) void k_leaf_beta(const double* __restrict__ segmax, const int32_t* __restrict__ seg0,
+                                                  const int32_t* __restrict__ nseg, double* __restrict__ beta) {
+  const int64_t e = blockIdx.x;
+  const int lane = threadIdx.x;
+  double v = 0.0;
+  for (int j = lane; j < nseg[e]; j += 64) v = fmax(v, segmax[seg0[e] + j]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  if (lane == 0) beta[e] = v;
 }
 
 __global__ void k_leaf_beta_strad(const double* __restrict__ E, const int64_t* __restrict__ strad,
@@ -140,10 +150,11 @@ __global__ __launch_bounds__(64) void k_ghost_gather(const int64_t* __restrict__
 int32_t ghost_apply(const mpm_mesh* m, const mpm_state_t* s, const double* u, int32_t precision, void* K, double* f,
                     hipStream_t st) {
   if (!m->n_gface) return MPM_OK;
-  hipLaunchKernelGGL(k_zero_beta, dim3(unsigned((m->n_leaf + 255) / 256)), dim3(256), 0, st, m->d_gbeta, m->n_leaf);
   if (m->n_point)
-    hipLaunchKernelGGL(k_leaf_beta, dim3(unsigned((m->n_point + 255) / 256)), dim3(256), 0, st, s->E, m->d_pleaf,
-                       m->d_pnleaf, m->n_point, m->d_gbeta);
+    hipLaunchKernelGGL(k_seg_beta, dim3(unsigned(m->n_wave)), dim3(64), 0, st, s->E, m->d_pleaf, m->d_pnleaf,
+                       m->n_point, m->d_wave_seg, m->d_gsegmax);
+  hipLaunchKernelGGL(k_leaf_beta, dim3(unsigned(m->n_leaf)), dim3(64), 0, st, m->d_gsegmax, m->d_leaf_seg0,
+                     m->d_leaf_nseg, m->d_gbeta);
   if (m->n_straddle)
     hipLaunchKernelGGL(k_leaf_beta_strad, dim3(unsigned((m->n_straddle + 255) / 256)), dim3(256), 0, st, s->E,
                        m->d_strad, m->d_strad_leaf, m->n_straddle, m->d_gbeta);

@@ -147,6 +147,7 @@ struct mpm_mesh {
   int32_t* d_gcon_off = nullptr;    // n_gnode + 1
   int32_t* d_gcon = nullptr;
   double* d_gbeta = nullptr;        // n_leaf
+  double* d_gsegmax = nullptr;      // n_seg: largest modulus of each point segment
   // kernel timing (measurement)
   bool timing = false;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};

@@ -555,6 +555,7 @@ int32_t gpu_build_pattern(mpm_mesh* m, const double* dx, const double* dl, hipSt
     hipLaunchKernelGGL(k_ghost_bpos, grid_of(256 * nf), dim3(256), 0, st, m->d_gf_nodes, nf, upairs.as<uint64_t>(),
                        nb_off.as<int64_t>(), m->d_gf_bpos);
     MPM_HIP(hipMalloc(&m->d_gbeta, size_t(nl) * 8));
+    MPM_HIP(hipMalloc(&m->d_gsegmax, size_t(std::max<int64_t>(1, m->n_seg)) * 8));
     MPM_HIP(hipMalloc(&m->d_gf_sc, size_t(nf) * 8));
   }
 

@@ -56,12 +56,6 @@ __device__ __forceinline__ void raise(DevErr* err, int code, int64_t idx) {
   if (atomicCAS(&err->code, 0, code) == 0) err->index = (unsigned long long)idx;
 }
 
-// upper-triangle slot blocks in (b outer, a <= b inner) order
-__constant__ int8_t c_blk_a[36] = {0, 0, 1, 0, 1, 2, 0, 1, 2, 3, 0, 1, 2, 3, 4, 0, 1, 2,
-                                   3, 4, 5, 0, 1, 2, 3, 4, 5, 6, 0, 1, 2, 3, 4, 5, 6, 7};
-__constant__ int8_t c_blk_b[36] = {0, 1, 1, 2, 2, 2, 3, 3, 3, 3, 4, 4, 4, 4, 4, 5, 5, 5,
-                                   5, 5, 5, 6, 6, 6, 6, 6, 6, 6, 7, 7, 7, 7, 7, 7, 7, 7};
-
 template <typename T>
 __device__ __forceinline__ void atomic_add_val(T* p, T v) {
   atomicAdd(p, v);
@@ -138,8 +132,10 @@ __device__ __forceinline__ void write_point(const AsmArgs& A, int64_t i, const P
 // lies in one leaf share that leaf's 8-node stencil; each lane computes its point's force
 // (24 values) and upper-triangle stiffness blocks (36 x 9); the values are reduced per leaf
 // segment (run of one leaf inside the wavefront) through LDS, 36 values per round, and each
-// segment's sums are stored once, contiguously, in the segment buffer. No atomics: the
-// row-gather kernel below turns segment sums into f_int and the CSR values.
+// segment's sums are stored once, contiguously, in the segment buffer: a record holds the 36
+// upper-triangle blocks (a <= b) in production order (b outer, a inner; then r, k), 324
+// values, so a round's 36 sums land at consecutive offsets. No atomics: the row-gather kernel
+// below turns segment sums into f_int and the CSR values.
 
 // sum of row[0..len) with four independent accumulators (a fixed order for a given len)
 template <typename T>
@@ -194,6 +190,9 @@ __device__ __forceinline__ void round_sums(const T (*red)[NR], const int32_t* se
 // the banks (a stride of 64 would put them all in one bank).
 constexpr int kRow = 65;
 
+// stiffness values of a segment record: the 36 upper-triangle 3x3 slot blocks
+constexpr int kRec = 324;
+
 // Values per reduction round: four 3x3 blocks (36 values); forces in FP64, 24 per round in
 // the FP64 kernel and 12 in the FP32 kernel, whose LDS then holds four wavefronts per SIMD.
 template <typename T>
@@ -234,18 +233,10 @@ void k_assemble_fast(AsmArgs A) {
   __shared__ __align__(16) unsigned char red_raw[Rounds<T>::kBytes];
   __shared__ int32_t seg_start[65];
   __shared__ int32_t seg_cnt;
-  // record offsets of upper-triangle block bi = (a, b): [0] a*72 + b*9, [1] b*72 + a*9 (-1 on
-  // the diagonal)
-  __shared__ int16_t blk_off[2][36];
   T(*red)[kRow] = reinterpret_cast<T(*)[kRow]>(red_raw);
   double(*redd)[kRow] = reinterpret_cast<double(*)[kRow]>(red_raw);
 
   const int lane = threadIdx.x;
-  if (lane < 36) {
-    const int ba = c_blk_a[lane], bb = c_blk_b[lane];
-    blk_off[0][lane] = int16_t(ba * 72 + bb * 9);
-    blk_off[1][lane] = int16_t(ba != bb ? bb * 72 + ba * 9 : -1);
-  }
   const int64_t i = int64_t(blockIdx.x) * 64 + lane;
   const int64_t n = A.n;
   const bool inr = i < n;
@@ -429,13 +420,8 @@ void k_assemble_fast(AsmArgs A) {
       if (blk % kBPR == kBPR - 1) {
         __syncthreads();
         const int rnd = blk / kBPR;
-        round_sums<T, kRound>(red, seg_start, nseg, [&](int sg, int v, T sum) {
-          // slot-major record [a][b][r][k]: block (a,b) and, off the diagonal, its transpose
-          const int bi = rnd * kBPR + v / 9, rk = v % 9, r = rk / 3, k = rk - 3 * r;
-          T* rec = segK + (seg0 + sg) * 576;
-          rec[blk_off[0][bi] + rk] = sum;
-          if (blk_off[1][bi] >= 0) rec[blk_off[1][bi] + 3 * k + r] = sum;
-        });
+        round_sums<T, kRound>(red, seg_start, nseg,
+                              [&](int sg, int v, T sum) { segK[(seg0 + sg) * kRec + rnd * kRound + v] = sum; });
         __syncthreads();
       }
       ++blk;
@@ -445,7 +431,7 @@ void k_assemble_fast(AsmArgs A) {
 
 // ------------------------------------------------------------------ record reduction
 // Task t = (first, count, out): record out = sum of records first .. first+count-1 (K values
-// when wantK, forces always), summed in ascending order. 192 threads x 3 K values.
+// when wantK, forces always), summed in ascending order. 192 threads x 2 K values.
 template <typename T>
 __global__ __launch_bounds__(192) void k_rec_reduce(void* segK_, double* __restrict__ segF,
                                                     const int32_t* __restrict__ task, bool wantK) {
@@ -455,18 +441,19 @@ __global__ __launch_bounds__(192) void k_rec_reduce(void* segK_, double* __restr
   if (wantK) {
     T* segK = reinterpret_cast<T*>(segK_);
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const T* p = segK + first * 576 + t + 192 * q;
+    for (int q = 0; q < 2; ++q) {
+      if (t + 192 * q >= kRec) break;
+      const T* p = segK + first * kRec + t + 192 * q;
       T s0 = 0, s1 = 0, s2 = 0, s3 = 0;
       int j = 0;
       for (; j + 4 <= cnt; j += 4) {
-        s0 += p[int64_t(j) * 576];
-        s1 += p[int64_t(j + 1) * 576];
-        s2 += p[int64_t(j + 2) * 576];
-        s3 += p[int64_t(j + 3) * 576];
+        s0 += p[int64_t(j) * kRec];
+        s1 += p[int64_t(j + 1) * kRec];
+        s2 += p[int64_t(j + 2) * kRec];
+        s3 += p[int64_t(j + 3) * kRec];
       }
-      for (; j < cnt; ++j) s0 += p[int64_t(j) * 576];
-      segK[out * 576 + t + 192 * q] = (s0 + s1) + (s2 + s3);
+      for (; j < cnt; ++j) s0 += p[int64_t(j) * kRec];
+      segK[out * kRec + t + 192 * q] = (s0 + s1) + (s2 + s3);
     }
   }
   if (t < 24) {
@@ -489,8 +476,9 @@ static void launch_rec_reduce(const mpm_mesh* m, hipStream_t st, bool wantK) {
 // ------------------------------------------------------------------ row gather
 // One workgroup per independent node n: the three CSR rows of n are accumulated in LDS from
 // the reduced segment blocks of every (populated leaf, slot a) incidence of n, in ascending
-// leaf order, and written once. A contribution is the contiguous [a][0..7][r][k] slab of a
-// segment record. Rows and f_int are overwritten. The loads of a batch of contributions are
+// leaf order, and written once. A contribution is row a of a segment record: blocks (a, b)
+// for b >= a as stored, blocks (b, a) for b < a read transposed. Rows and f_int are
+// overwritten. The loads of a batch of contributions are
 // issued without branches (indices past the end repeat the last one and are not added), so
 // that they are all in flight together.
 template <typename T, bool WANTK>
@@ -514,6 +502,10 @@ __global__ __launch_bounds__(64) void k_gather(AsmArgs A, int64_t n_node) {
   const int v0 = lane, v1 = has1 ? lane + 64 : lane;
   const int b0 = v0 / 9, r0 = (v0 % 9) / 3, k0 = v0 % 3;
   const int b1 = v1 / 9, r1 = (v1 % 9) / 3, k1 = v1 % 3;
+  // record offset of value (r, k) of block (a, b): block (a, b) = 9 (b (b + 1) / 2 + a) + 3r + k
+  // for a <= b; for a > b the transpose of block (b, a): 9 (a (a + 1) / 2 + b) + 3k + r
+  const int up0 = 9 * (b0 * (b0 + 1) / 2) + 3 * r0 + k0, lo0 = 9 * b0 + 3 * k0 + r0;
+  const int up1 = 9 * (b1 * (b1 + 1) / 2) + 3 * r1 + k1, lo1 = 9 * b1 + 3 * k1 + r1;
   const int fl = lane < 3 ? lane : 0;
   const int c0 = A.con_off[nd], c1 = A.con_off[nd + 1];
   for (int cb = c0; cb < c1; cb += kBatch) {
@@ -535,10 +527,11 @@ __global__ __launch_bounds__(64) void k_gather(AsmArgs A, int64_t n_node) {
       const int64_t rec = cs[j] >> 3;
       const int slot = cs[j] & 7;
       if (WANTK) {
-        const T* src = segK + rec * 576 + slot * 72;  // slot a's 72 values
+        const T* src = segK + rec * kRec;
         const int16_t* bp = A.bpos + cp[j];
-        val0[j] = src[v0];
-        val1[j] = src[v1];
+        const int tri = 9 * (slot * (slot + 1) / 2);
+        val0[j] = src[slot <= b0 ? up0 + 9 * slot : lo0 + tri];
+        val1[j] = src[slot <= b1 ? up1 + 9 * slot : lo1 + tri];
         p0[j] = bp[b0];
         p1[j] = bp[b1];
       }

@@ -100,7 +100,7 @@ struct mpm_mesh {
   // records 0..n_seg-1 are wavefront segments; after them one record per heavily populated
   // leaf (its segments summed) and the partial sums of those leaves' chunks
   int64_t n_rec = 0;
-  void* d_segK = nullptr;           // n_rec x [8][8][3][3] reduced slot blocks (double or float)
+  void* d_segK = nullptr;           // n_rec x 36 upper-triangle 3x3 slot blocks (a <= b; b outer, a inner), double or float
   double* d_segF = nullptr;         // n_rec x 24 reduced nodal forces
   // record reductions (first record, count, output record), run in two stages
   int64_t n_red1 = 0, n_red2 = 0;

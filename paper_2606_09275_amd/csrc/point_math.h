@@ -125,15 +125,52 @@ __device__ __forceinline__ void slot_basis(const T xi[3], T inv_h, int32_t code,
   constrain(g2, &dS[0][2], 3);
 }
 
+// Reciprocal and reciprocal square root from the hardware estimates, refined by Newton steps
+// (two for FP64: the error falls from the estimate's to about one unit in the last place; the
+// FP32 estimates are already within one unit). Used for the Jacobi rotation parameters, which
+// only need c^2 + s^2 = 1 to rounding.
+template <typename T>
+__device__ __forceinline__ T nr_rcp(T x);
+template <>
+__device__ __forceinline__ double nr_rcp<double>(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+template <>
+__device__ __forceinline__ float nr_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <typename T>
+__device__ __forceinline__ T nr_rsq(T x);
+template <>
+__device__ __forceinline__ double nr_rsq<double>(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {  // y <- y (3 - x y^2) / 2
+    const double h = 0.5 * y;
+    y = fma(h, fma(-x * y, y, 1.0), y);
+  }
+  return y;
+}
+template <>
+__device__ __forceinline__ float nr_rsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+
 // one Jacobi rotation annihilating the (p,q) entry of the symmetric A (storage a[p][q]),
-// accumulating the eigenvectors in the columns of V
+// accumulating the eigenvectors in the columns of V; t = tan of the rotation angle, the root
+// of smaller magnitude of t^2 + 2 th t - 1 = 0
+// (off-diagonals below the smallest normal range, whose reciprocal would overflow, are left
+// as they are; for |th| beyond the range of th^2, t = 1 / (2 |th|))
 template <typename T>
 __device__ __forceinline__ void jrot(T A[3][3], T V[3][3], int p, int q, int r) {
+  constexpr T kTiny = sizeof(T) == 8 ? T(1e-290) : T(1e-35), kBig = sizeof(T) == 8 ? T(1e150) : T(1e18);
   const T apq = A[p][q];
-  if (apq == T(0)) return;
-  const T th = (A[q][q] - A[p][p]) / (T(2) * apq);
-  const T t = (th >= T(0) ? T(1) : T(-1)) / (fabs(th) + t_sqrt<T>(T(1) + th * th));
-  const T c = T(1) / t_sqrt<T>(T(1) + t * t), s = t * c;
+  if (!(fabs(apq) > kTiny)) return;
+  const T th = (A[q][q] - A[p][p]) * (T(0.5) * nr_rcp<T>(apq));
+  const T ath = fabs(th), q1 = T(1) + th * th;
+  const T den = ath < kBig ? ath + q1 * nr_rsq<T>(q1) : T(2) * ath;  // |th| + sqrt(1 + th^2)
+  const T t = (th >= T(0) ? T(1) : T(-1)) * nr_rcp<T>(den);
+  const T c = nr_rsq<T>(T(1) + t * t), s = t * c;
   A[p][p] -= t * apq;
   A[q][q] += t * apq;
   A[p][q] = A[q][p] = T(0);

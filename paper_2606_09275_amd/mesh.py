@@ -73,7 +73,10 @@ class Mesh:
     def __del__(self):
         h = getattr(self, "h", None)
         if h:
-            lib().mpm_mesh_free(h)
+            try:
+                lib().mpm_mesh_free(h)
+            except (AttributeError, TypeError, ImportError):
+                pass  # interpreter shutdown: module globals already cleared; the process frees the GPU
             self.h = None
 
     # -------------------------------------------------------------- inspection

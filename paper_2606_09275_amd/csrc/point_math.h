@@ -89,6 +89,16 @@ __device__ __forceinline__ void slot_basis(const T xi[3], T inv_h, int32_t code,
   //   S[k] = [k not hanging] ph[k] + sum over hanging j with j' containing k' of ph[j] / 2^m_j,
   // a sum over supersets taken axis by axis (three passes of eight fused adds).
   const int hm = code_hmask(code);
+  if (hm == 0) {  // no hanging vertex: the map is the identity
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      S[k] = ph[k] * wgt;
+      dS[k][0] = g0[k] * wgt;
+      dS[k][1] = g1[k] * wgt;
+      dS[k][2] = g2[k] * wgt;
+    }
+    return;
+  }
   const int cc = code_child(code);
   T wj[8], nh[8];
 #pragma unroll

@@ -408,13 +408,20 @@ void k_assemble_fast(AsmArgs A) {
 #pragma unroll
     for (int a = 0; a <= b; ++a) {
       const int slotv = (blk % kBPR) * 9;
+      T vd[3][3];  // diagonal block (a == b): symmetric like K, its lower entries are copies
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          T val = X[k][r][0] * g[a][0] + X[k][r][1] * g[a][1] + X[k][r][2] * g[a][2];
-          if constexpr (DYN)
-            if (r == k) val += msb * S[a];
+          T val;
+          if (a == b && k < r) {
+            val = vd[k][r];
+          } else {
+            val = X[k][r][0] * g[a][0] + X[k][r][1] * g[a][1] + X[k][r][2] * g[a][2];
+            if constexpr (DYN)
+              if (r == k) val += msb * S[a];
+          }
+          vd[r][k] = val;
           red[slotv + 3 * r + k][lane] = val;
         }
       if (blk % kBPR == kBPR - 1) {

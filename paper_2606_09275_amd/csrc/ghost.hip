@@ -10,7 +10,7 @@ namespace mpm {
 // ------------------------------------------------------------------ device
 // beta[e] = largest Young's modulus of the points overlapping leaf e (0 if none). Points are
 // sorted by leaf: one wavefront per 64 points takes the maximum of each of its segments (runs
-// of one leaf), then one wavefront per leaf the maximum over the leaf's segments, so a leaf
+// of one leaf), then one thread per leaf the maximum over the leaf's segments, so a leaf
 // holding many points needs no atomics. Points overlapping several leaves count in
 // k_leaf_beta_strad (E > 0, so the integer order of the IEEE bit patterns is the order of the
 // values there).
@@ -37,15 +37,15 @@ __global__ __launch_bounds__(64) void k_seg_beta(const double* __restrict__ E, c
   if (head) segmax[wave_seg[blockIdx.x] + __popcll(hm & ((1ull << lane) - 1ull))] = v;
 }
 
-__global__ __launch_bounds__(64) void k_leaf_beta(const double* __restrict__ segmax, const int32_t* __restrict__ seg0,
-                                                  const int32_t* __restrict__ nseg, double* __restrict__ beta) {
-  const int64_t e = blockIdx.x;
-  const int lane = threadIdx.x;
+__global__ __launch_bounds__(256) void k_leaf_beta(const double* __restrict__ segmax, const int32_t* __restrict__ seg0,
+                                                   const int32_t* __restrict__ nseg, int64_t n_leaf,
+                                                   double* __restrict__ beta) {
+  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;  // one thread per leaf
+  if (e >= n_leaf) return;
+  const int32_t s0 = seg0[e], ns = nseg[e];
   double v = 0.0;
-  for (int j = lane; j < nseg[e]; j += 64) v = fmax(v, segmax[seg0[e] + j]);
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-  if (lane == 0) beta[e] = v;
+  for (int j = 0; j < ns; ++j) v = fmax(v, segmax[s0 + j]);
+  beta[e] = v;
 }
 
 __global__ void k_leaf_beta_strad(const double* __restrict__ E, const int64_t* __restrict__ strad,
@@ -153,8 +153,8 @@ int32_t ghost_apply(const mpm_mesh* m, const mpm_state_t* s, const double* u, in
   if (m->n_point)
     hipLaunchKernelGGL(k_seg_beta, dim3(unsigned(m->n_wave)), dim3(64), 0, st, s->E, m->d_pleaf, m->d_pnleaf,
                        m->n_point, m->d_wave_seg, m->d_gsegmax);
-  hipLaunchKernelGGL(k_leaf_beta, dim3(unsigned(m->n_leaf)), dim3(64), 0, st, m->d_gsegmax, m->d_leaf_seg0,
-                     m->d_leaf_nseg, m->d_gbeta);
+  hipLaunchKernelGGL(k_leaf_beta, dim3(unsigned((m->n_leaf + 255) / 256)), dim3(256), 0, st, m->d_gsegmax,
+                     m->d_leaf_seg0, m->d_leaf_nseg, m->n_leaf, m->d_gbeta);
   if (m->n_straddle)
     hipLaunchKernelGGL(k_leaf_beta_strad, dim3(unsigned((m->n_straddle + 255) / 256)), dim3(256), 0, st, s->E,
                        m->d_strad, m->d_strad_leaf, m->n_straddle, m->d_gbeta);

@@ -206,7 +206,12 @@ class OracleMesh:
             raise OracleError(st, bad.value)
         self.n_point = x.shape[1]
 
+    def _need_points(self, what):
+        if getattr(self, "n_point", None) is None:
+            raise RuntimeError(f"OracleMesh.{what}: call set_points first (the order and the pattern depend on them)")
+
     def perm(self):
+        self._need_points("perm")
         n = self.n_point
         perm = np.zeros(n, _i64)
         pl = np.zeros(n, np.int32)
@@ -215,6 +220,7 @@ class OracleMesh:
         return perm, pl, nl
 
     def csr(self):
+        self._need_points("csr")
         c = self.counts()
         rp = np.zeros(3 * c["n_node"] + 1, _i64)
         col = np.zeros(c["nnz"], np.int32)

@@ -492,7 +492,7 @@ template <typename T, bool WANTK>
 __global__ __launch_bounds__(64) void k_gather(AsmArgs A, int64_t n_node) {
   extern __shared__ __align__(16) unsigned char gsm[];
   T* acc = reinterpret_cast<T*>(gsm);
-  constexpr int kBatch = 8;
+  constexpr int kBatch = 4;  // contributions in flight per step: 52 registers, eight wavefronts per SIMD
   const int64_t nd = blockIdx.x;
   const int lane = threadIdx.x;
   const int64_t base = A.row_ptr[3 * nd];

@@ -515,16 +515,24 @@ __global__ __launch_bounds__(64) void k_gather(AsmArgs A, int64_t n_node) {
   const int up1 = 9 * (b1 * (b1 + 1) / 2) + 3 * r1 + k1, lo1 = 9 * b1 + 3 * k1 + r1;
   const int fl = lane < 3 ? lane : 0;
   const int c0 = A.con_off[nd], c1 = A.con_off[nd + 1];
+  // lane j holds contribution cl + j of the node (64 at a time, indices past the end repeat the
+  // last one); every lane reads a batch's entries back as uniform values
+  int cl = c0;
+  int32_t my_cs = 0, my_cp = 0;  // record * 8 + slot, bpos offset
   for (int cb = c0; cb < c1; cb += kBatch) {
     const int nb = c1 - cb < kBatch ? c1 - cb : kBatch;
-    // lane j < kBatch loads contribution j; every lane then reads them back as uniform values
-    const int jl = cb + (lane < nb ? lane : nb - 1);
-    const int32_t my_cs = A.con_seg[jl], my_cp = A.con_bp[jl];  // record * 8 + slot, bpos offset
+    if (cb == c0 || cb - cl + kBatch > 64) {
+      cl = cb;
+      const int jl = cb + lane < c1 ? cb + lane : c1 - 1;
+      my_cs = A.con_seg[jl];
+      my_cp = A.con_bp[jl];
+    }
     int32_t cs[kBatch], cp[kBatch];
 #pragma unroll
     for (int j = 0; j < kBatch; ++j) {
-      cs[j] = __builtin_amdgcn_readlane(my_cs, j);
-      cp[j] = __builtin_amdgcn_readlane(my_cp, j);
+      const int q = cb - cl + (j < nb ? j : nb - 1);
+      cs[j] = __builtin_amdgcn_readlane(my_cs, q);
+      cp[j] = __builtin_amdgcn_readlane(my_cp, q);
     }
     T val0[kBatch], val1[kBatch];
     int16_t p0[kBatch], p1[kBatch];

@@ -480,6 +480,14 @@ static void launch_rec_reduce(const mpm_mesh* m, hipStream_t st, bool wantK) {
                        m->d_red2, wantK);
 }
 
+// Workgroups are dealt to the chip's 8 XCDs (each with its own L2) in turn: workgroup w runs
+// on XCD w % 8. This maps them so that XCD x takes one contiguous range of items (the first
+// N % 8 XCDs one more): neighbouring items, which read the same records, share an L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t w, int64_t n) {
+  const int64_t x = w & 7, q = w >> 3, m = n >> 3, r = n & 7;
+  return x * m + (x < r ? x : r) + q;
+}
+
 // ------------------------------------------------------------------ row gather
 // One workgroup per independent node n: the three CSR rows of n are accumulated in LDS from
 // the reduced segment blocks of every (populated leaf, slot a) incidence of n, in ascending
@@ -493,7 +501,7 @@ __global__ __launch_bounds__(64) void k_gather(AsmArgs A, int64_t n_node) {
   extern __shared__ __align__(16) unsigned char gsm[];
   T* acc = reinterpret_cast<T*>(gsm);
   constexpr int kBatch = 4;  // contributions in flight per step: 52 registers, eight wavefronts per SIMD
-  const int64_t nd = blockIdx.x;
+  const int64_t nd = xcd_block(blockIdx.x, gridDim.x);
   const int lane = threadIdx.x;
   const int64_t base = A.row_ptr[3 * nd];
   const int deg = int((A.row_ptr[3 * nd + 1] - base) / 3);

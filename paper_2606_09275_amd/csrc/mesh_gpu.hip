@@ -112,6 +112,25 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scan_digit(uint32_t* __restri
   if (threadIdx.x == 0) tot[blockIdx.x] = carry;
 }
 
+// exclusive prefix sum over the 256 threads of a workgroup (thread t holds digit t's value):
+// inclusive sums inside each wavefront by shuffles, then the wavefront totals; all threads call
+static_assert(kRsThreads == 256, "the radix kernels give thread t digit t");
+__device__ __forceinline__ uint32_t block_exclusive_256(uint32_t v, uint32_t* wtot) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  uint32_t inc = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t t = __shfl_up(inc, off);
+    if (lane >= off) inc += t;
+  }
+  if (lane == 63) wtot[wave] = inc;
+  __syncthreads();
+  uint32_t before = 0;
+  for (int w = 0; w < wave; ++w) before += wtot[w];
+  __syncthreads();  // wtot may be reused by the caller's next scan
+  return before + inc - v;
+}
+
 // Ranks each element among equal digits of its tile (ballots per wavefront, counts per
 // wavefront in LDS), stages the tile in LDS in digit order, then writes it out: the elements
 // of one digit leave the tile as one contiguous run.
@@ -122,35 +141,22 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint32_t* __res
                                                            const uint32_t* __restrict__ tot) {
   __shared__ uint32_t run[256];
   __shared__ uint32_t wcnt[kRsThreads / 64][256];
-  __shared__ uint32_t dbase[256];
   __shared__ uint32_t start[256];  // first output position of the tile's elements of digit d
   __shared__ uint32_t lbase[256];  // first staging slot of digit d in the tile
   __shared__ uint32_t lk[kRsTile], lv[kRsTile];
+  __shared__ uint32_t wtot[kRsThreads / 64];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int64_t nblk = gridDim.x, blk = blockIdx.x;
-  if (tid == 0) {
-    uint32_t acc = 0;
-    for (int d = 0; d < 256; ++d) {
-      dbase[d] = acc;
-      acc += tot[d];
-    }
-  }
-  __syncthreads();
   {
+    // digit d's elements start at (all elements of smaller digits) + (digit d in earlier
+    // tiles); inside the tile's staging copy at (the tile's elements of smaller digits)
     const uint32_t h0 = hist[int64_t(tid) * nblk + blk];
     const uint32_t h1 = blk + 1 < nblk ? hist[int64_t(tid) * nblk + blk + 1] : tot[tid];
-    start[tid] = dbase[tid] + h0;
-    run[tid] = start[tid];
-    lbase[tid] = h1 - h0;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    uint32_t acc = 0;
-    for (int d = 0; d < 256; ++d) {
-      const uint32_t c = lbase[d];
-      lbase[d] = acc;
-      acc += c;
-    }
+    const uint32_t db = block_exclusive_256(tot[tid], wtot);
+    const uint32_t lb = block_exclusive_256(h1 - h0, wtot);
+    start[tid] = db + h0;
+    run[tid] = db + h0;
+    lbase[tid] = lb;
   }
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t base = blk * kRsTile;

@@ -88,34 +88,11 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint32_t* __restri
   hist[int64_t(threadIdx.x) * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
-// exclusive scan of one digit's per-block counts (one workgroup per digit); total -> tot[d]
-__global__ __launch_bounds__(kRsThreads) void k_rs_scan_digit(uint32_t* __restrict__ hist, int nblk,
-                                                              uint32_t* __restrict__ tot) {
-  __shared__ uint32_t s[kRsThreads];
-  uint32_t* row = hist + int64_t(blockIdx.x) * nblk;
-  uint32_t carry = 0;
-  for (int base = 0; base < nblk; base += kRsThreads) {
-    const int i = base + threadIdx.x;
-    const uint32_t v = i < nblk ? row[i] : 0u;
-    s[threadIdx.x] = v;
-    __syncthreads();
-    for (int off = 1; off < kRsThreads; off <<= 1) {  // Hillis-Steele inclusive scan
-      const uint32_t t = threadIdx.x >= off ? s[threadIdx.x - off] : 0u;
-      __syncthreads();
-      s[threadIdx.x] += t;
-      __syncthreads();
-    }
-    if (i < nblk) row[i] = carry + s[threadIdx.x] - v;
-    carry += s[kRsThreads - 1];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) tot[blockIdx.x] = carry;
-}
-
 // exclusive prefix sum over the 256 threads of a workgroup (thread t holds digit t's value):
-// inclusive sums inside each wavefront by shuffles, then the wavefront totals; all threads call
+// inclusive sums inside each wavefront by shuffles, then the wavefront totals; all threads
+// call it; *total (if given) receives the sum of all 256 values
 static_assert(kRsThreads == 256, "the radix kernels give thread t digit t");
-__device__ __forceinline__ uint32_t block_exclusive_256(uint32_t v, uint32_t* wtot) {
+__device__ __forceinline__ uint32_t block_exclusive_256(uint32_t v, uint32_t* wtot, uint32_t* total = nullptr) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   uint32_t inc = v;
 #pragma unroll
@@ -127,8 +104,26 @@ __device__ __forceinline__ uint32_t block_exclusive_256(uint32_t v, uint32_t* wt
   __syncthreads();
   uint32_t before = 0;
   for (int w = 0; w < wave; ++w) before += wtot[w];
+  if (total) *total = wtot[0] + wtot[1] + wtot[2] + wtot[3];
   __syncthreads();  // wtot may be reused by the caller's next scan
   return before + inc - v;
+}
+
+// exclusive scan of one digit's per-block counts (one workgroup per digit); total -> tot[d]
+__global__ __launch_bounds__(kRsThreads) void k_rs_scan_digit(uint32_t* __restrict__ hist, int nblk,
+                                                              uint32_t* __restrict__ tot) {
+  __shared__ uint32_t wtot[kRsThreads / 64];
+  uint32_t* row = hist + int64_t(blockIdx.x) * nblk;
+  uint32_t carry = 0;
+  for (int base = 0; base < nblk; base += kRsThreads) {
+    const int i = base + threadIdx.x;
+    const uint32_t v = i < nblk ? row[i] : 0u;
+    uint32_t chunk;
+    const uint32_t ex = block_exclusive_256(v, wtot, &chunk);
+    if (i < nblk) row[i] = carry + ex;
+    carry += chunk;
+  }
+  if (threadIdx.x == 0) tot[blockIdx.x] = carry;
 }
 
 // Ranks each element among equal digits of its tile (ballots per wavefront, counts per

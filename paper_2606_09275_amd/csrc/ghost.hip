@@ -10,8 +10,9 @@ namespace mpm {
 // ------------------------------------------------------------------ device
 // beta[e] = largest Young's modulus of the points overlapping leaf e (0 if none). Points are
 // sorted by leaf: one wavefront per 64 points takes the maximum of each of its segments (runs
-// of one leaf), then one thread per leaf the maximum over the leaf's segments, so a leaf
-// holding many points needs no atomics. Points overlapping several leaves count in
+// of one leaf), then per leaf the maximum over the leaf's segments (one thread per leaf, the
+// whole wavefront for a leaf with many segments), so a leaf holding many points needs no
+// atomics. Points overlapping several leaves count in
 // k_leaf_beta_strad (E > 0, so the integer order of the IEEE bit patterns is the order of the
 // values there).
 __global__ __launch_bounds__(64) void k_seg_beta(const double* __restrict__ E, const int32_t* __restrict__ pleaf,
@@ -37,15 +38,35 @@ __global__ __launch_bounds__(64) void k_seg_beta(const double* __restrict__ E, c
   if (head) segmax[wave_seg[blockIdx.x] + __popcll(hm & ((1ull << lane) - 1ull))] = v;
 }
 
+// One thread per leaf; a leaf with more than kLightSeg segments (coarse leaves holding many
+// points) is taken by the whole wavefront in turn: strided loads, then a shuffle reduction.
+constexpr int kLightSeg = 8;
 __global__ __launch_bounds__(256) void k_leaf_beta(const double* __restrict__ segmax, const int32_t* __restrict__ seg0,
                                                    const int32_t* __restrict__ nseg, int64_t n_leaf,
                                                    double* __restrict__ beta) {
-  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;  // one thread per leaf
-  if (e >= n_leaf) return;
-  const int32_t s0 = seg0[e], ns = nseg[e];
+  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  int32_t s0 = 0, ns = 0;
+  if (e < n_leaf) {
+    s0 = seg0[e];
+    ns = nseg[e];
+  }
   double v = 0.0;
-  for (int j = 0; j < ns; ++j) v = fmax(v, segmax[s0 + j]);
-  beta[e] = v;
+  const bool heavy = ns > kLightSeg;
+  if (!heavy)
+    for (int j = 0; j < ns; ++j) v = fmax(v, segmax[s0 + j]);
+  uint64_t hm = __ballot(heavy);  // every lane takes part (no early exit before this loop)
+  while (hm) {
+    const int src = __ffsll((unsigned long long)hm) - 1;
+    hm &= hm - 1;
+    const int32_t hs0 = __shfl(s0, src), hns = __shfl(ns, src);
+    double w = 0.0;
+    for (int j = lane; j < hns; j += 64) w = fmax(w, segmax[hs0 + j]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) w = fmax(w, __shfl_xor(w, off));
+    if (lane == src) v = w;
+  }
+  if (e < n_leaf) beta[e] = v;
 }
 
 __global__ void k_leaf_beta_strad(const double* __restrict__ E, const int64_t* __restrict__ strad,

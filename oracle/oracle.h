@@ -9,7 +9,12 @@
  * of Section 3.2 "GIMP basis"), a literal 4th-order-tensor consistent tangent and a
  * complex-step parameter derivative for the adjoint. Everything is FP64, single thread.
  *
- * Readings of the paper that this file follows are listed in the design doc of the repository.
+ * Where the paper leaves a choice open this file takes the same readings as the library: a
+ * von Mises surface sqrt(3 J2) = sigma_y on the Kirchhoff stress with a radial return in
+ * principal logarithmic strains; K as the exact Jacobian of f_int with the basis frozen; a
+ * leaf counts in a support only if every axis overlap exceeds 1e-12 of the domain side;
+ * 2:1 balance across faces and edges; edge-hanging ties to the lowest Morton rank; points
+ * ordered by (leaf containing the centre, original index); Newmark gamma = 1, beta = 1/2.
  */
 #ifndef MPM_ORACLE_H
 #define MPM_ORACLE_H

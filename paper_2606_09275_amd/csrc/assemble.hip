@@ -26,6 +26,7 @@ struct AsmArgs {
   const int16_t* bpos;
   void* segK;
   double* segF;
+  void* segM;  // inertia: per record the 36 sums of (2 m / dt^2) S_a S_b (a <= b), or null
   const int64_t* row_ptr;
   const int32_t* col;
   const int64_t* strad;
@@ -224,8 +225,8 @@ __device__ __forceinline__ void wave_segments(int32_t leaf, bool inr, int64_t n,
 }
 
 // Register budget: two wavefronts per SIMD in FP64 (256 registers), four in FP32 (128).
-// DYN adds the Newmark inertia term: f_v += S_v m_p a_p and (2 m_p / dt^2) S_a S_b on the
-// diagonal of every block.
+// DYN adds the Newmark inertia term: f_v += S_v m_p a_p, and the tangent's (2 m_p / dt^2) S_a S_b
+// as 36 per-segment sums in their own record, which the row gather adds to the block diagonals.
 template <typename T, bool DYN>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 4)))
 void k_assemble_fast(AsmArgs A) {
@@ -358,6 +359,21 @@ void k_assemble_fast(AsmArgs A) {
     __syncthreads();
   }
   if (!A.K) return;
+  if constexpr (DYN) {
+    // inertia tangent (2 m / dt^2) S_a S_b on the diagonal of block (a, b): one scalar per
+    // upper-triangle block, summed per segment like the stiffness values and added to the
+    // block diagonals by the row gather (so the basis values are dead in the block loop)
+    const T cm = T(2.0 * mp / (A.dt * A.dt));
+    int q = 0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+#pragma unroll
+      for (int a = 0; a <= b; ++a, ++q) red[q][lane] = cm * S[a] * S[b];
+    __syncthreads();
+    T* segM = reinterpret_cast<T*>(A.segM);
+    round_sums<T, kRound>(red, seg_start, nseg, [&](int sg, int v, T sum) { segM[(seg0 + sg) * 36 + v] = sum; });
+    __syncthreads();
+  }
 
   // ---------------- stiffness: K_(a,i)(b,k) = c [ (dtau(b,k) g_a)_i - (tau g_b)_i g_a,k ]
   // = sum_j X[k][i][j] g_a,j with X[k][i][j] = c dtau(b,k)_ij - (c tau g_b)_i delta_jk.
@@ -404,7 +420,6 @@ void k_assemble_fast(AsmArgs A) {
         X[k][2][k] -= tg2;
       }
     }
-    const T msb = DYN ? T(2.0 * mp / (A.dt * A.dt)) * S[b] : T(0);  // inertia: (2 m / dt^2) S_b
 #pragma unroll
     for (int a = 0; a <= b; ++a) {
       const int slotv = (blk % kBPR) * 9;
@@ -418,8 +433,6 @@ void k_assemble_fast(AsmArgs A) {
             val = vd[k][r];
           } else {
             val = X[k][r][0] * g[a][0] + X[k][r][1] * g[a][1] + X[k][r][2] * g[a][2];
-            if constexpr (DYN)
-              if (r == k) val += msb * S[a];
           }
           vd[r][k] = val;
           red[slotv + 3 * r + k][lane] = val;
@@ -440,7 +453,7 @@ void k_assemble_fast(AsmArgs A) {
 // Task t = (first, count, out): record out = sum of records first .. first+count-1 (K values
 // when wantK, forces always), summed in ascending order. 192 threads x 2 K values.
 template <typename T>
-__global__ __launch_bounds__(192) void k_rec_reduce(void* segK_, double* __restrict__ segF,
+__global__ __launch_bounds__(192) void k_rec_reduce(void* segK_, double* __restrict__ segF, void* segM_,
                                                     const int32_t* __restrict__ task, bool wantK) {
   const int64_t first = task[3 * blockIdx.x], out = task[3 * blockIdx.x + 2];
   const int cnt = task[3 * blockIdx.x + 1];
@@ -468,15 +481,21 @@ __global__ __launch_bounds__(192) void k_rec_reduce(void* segK_, double* __restr
     for (int j = 0; j < cnt; ++j) s += segF[(first + j) * 24 + t];
     segF[out * 24 + t] = s;
   }
+  if (wantK && segM_ && t >= 64 && t < 64 + 36) {  // inertia sums (dynamic assembly)
+    T* segM = reinterpret_cast<T*>(segM_);
+    T s = 0;
+    for (int j = 0; j < cnt; ++j) s += segM[(first + j) * 36 + (t - 64)];
+    segM[out * 36 + (t - 64)] = s;
+  }
 }
 
 template <typename T>
-static void launch_rec_reduce(const mpm_mesh* m, hipStream_t st, bool wantK) {
+static void launch_rec_reduce(const mpm_mesh* m, hipStream_t st, bool wantK, void* segM) {
   if (m->n_red1)
-    hipLaunchKernelGGL(k_rec_reduce<T>, dim3(unsigned(m->n_red1)), dim3(192), 0, st, m->d_segK, m->d_segF,
+    hipLaunchKernelGGL(k_rec_reduce<T>, dim3(unsigned(m->n_red1)), dim3(192), 0, st, m->d_segK, m->d_segF, segM,
                        m->d_red1, wantK);
   if (m->n_red2)
-    hipLaunchKernelGGL(k_rec_reduce<T>, dim3(unsigned(m->n_red2)), dim3(192), 0, st, m->d_segK, m->d_segF,
+    hipLaunchKernelGGL(k_rec_reduce<T>, dim3(unsigned(m->n_red2)), dim3(192), 0, st, m->d_segK, m->d_segF, segM,
                        m->d_red2, wantK);
 }
 
@@ -521,6 +540,10 @@ __global__ __launch_bounds__(64) void k_gather(AsmArgs A, int64_t n_node) {
   // for a <= b; for a > b the transpose of block (b, a): 9 (a (a + 1) / 2 + b) + 3k + r
   const int up0 = 9 * (b0 * (b0 + 1) / 2) + 3 * r0 + k0, lo0 = 9 * b0 + 3 * k0 + r0;
   const int up1 = 9 * (b1 * (b1 + 1) / 2) + 3 * r1 + k1, lo1 = 9 * b1 + 3 * k1 + r1;
+  // dynamic assembly: the inertia sum of block (a, b) (index b (b + 1)/2 + a, a <= b) is added to
+  // the block's diagonal values
+  const T* segM = reinterpret_cast<const T*>(A.segM);
+  const bool dg0 = WANTK && segM && r0 == k0, dg1 = WANTK && segM && has1 && r1 == k1;
   const int fl = lane < 3 ? lane : 0;
   const int c0 = A.con_off[nd], c1 = A.con_off[nd + 1];
   // lane j holds contribution cl + j of the node (64 at a time, indices past the end repeat the
@@ -555,6 +578,8 @@ __global__ __launch_bounds__(64) void k_gather(AsmArgs A, int64_t n_node) {
         const int tri = 9 * (slot * (slot + 1) / 2);
         val0[j] = src[slot <= b0 ? up0 + 9 * slot : lo0 + tri];
         val1[j] = src[slot <= b1 ? up1 + 9 * slot : lo1 + tri];
+        if (dg0) val0[j] += segM[rec * 36 + (slot <= b0 ? b0 * (b0 + 1) / 2 + slot : tri / 9 + b0)];
+        if (dg1) val1[j] += segM[rec * 36 + (slot <= b1 ? b1 * (b1 + 1) / 2 + slot : tri / 9 + b1)];
         p0[j] = bp[b0];
         p1[j] = bp[b1];
       }
@@ -1048,7 +1073,7 @@ extern "C" int32_t mpm_external_force(const mpm_mesh_t* m, const mpm_state_t* s,
   A.K = nullptr;
   if (m->n_point) {
     hipLaunchKernelGGL(k_external_fast, dim3(unsigned((m->n_point + 63) / 64)), dim3(64), 0, st, A);
-    launch_rec_reduce<double>(m, st, false);
+    launch_rec_reduce<double>(m, st, false, nullptr);
   }
   // every f_ext entry is written by the gather (zero where no point contributes)
   launch_gather<double>(m, st, A);
@@ -1098,6 +1123,7 @@ extern "C" int32_t mpm_assemble_dynamic(const mpm_mesh_t* m, const mpm_state_t* 
   A.sigma = sigma6;
   A.vel = v_n;
   A.dt = dt;
+  A.segM = m->d_segM;
   A.a_new = a_new;
   A.v_new = v_new;
   return assemble_impl(m, A, precision, f_ext, dirichlet, r, rnorm, (hipStream_t)stream, "mpm_assemble_dynamic");
@@ -1124,8 +1150,8 @@ static int32_t assemble_impl(const mpm_mesh_t* m, const AsmArgs& A, int32_t prec
   }
   if (timed) MPM_HIP(hipEventRecord(mm->ev[1], st));
   if (n) {
-    if (precision == MPM_F64) launch_rec_reduce<double>(m, st, K_vals != nullptr);
-    else launch_rec_reduce<float>(m, st, K_vals != nullptr);
+    if (precision == MPM_F64) launch_rec_reduce<double>(m, st, K_vals != nullptr, A.segM);
+    else launch_rec_reduce<float>(m, st, K_vals != nullptr, A.segM);
   }
   // f_int and every CSR value are written by the gather (zero where no point contributes)
   if (precision == MPM_F64) launch_gather<double>(m, st, A);

@@ -102,6 +102,7 @@ struct mpm_mesh {
   int64_t n_rec = 0;
   void* d_segK = nullptr;           // n_rec x 36 upper-triangle 3x3 slot blocks (a <= b; b outer, a inner), double or float
   double* d_segF = nullptr;         // n_rec x 24 reduced nodal forces
+  void* d_segM = nullptr;           // n_rec x 36 inertia coefficients sum (2 m / dt^2) S_a S_b (a <= b), double or float
   // record reductions (first record, count, output record), run in two stages
   int64_t n_red1 = 0, n_red2 = 0;
   int32_t* d_red1 = nullptr;        // n_red1 x 3: chunks of a heavy leaf's segments

@@ -601,6 +601,7 @@ int32_t gpu_build_pattern(mpm_mesh* m, const double* dx, const double* dl, hipSt
 
   MPM_HIP(hipMalloc(&m->d_segK, size_t(std::max<int64_t>(1, nrec)) * 324 * 8));
   MPM_HIP(hipMalloc(&m->d_segF, size_t(std::max<int64_t>(1, nrec)) * 24 * 8));
+  MPM_HIP(hipMalloc(&m->d_segM, size_t(std::max<int64_t>(1, nrec)) * 36 * 8));
   MPM_HIP(hipMalloc(&m->d_partial, 4096 * sizeof(double)));
   MPM_HIP(hipGetLastError());
   MPM_HIP(hipStreamSynchronize(st));

@@ -226,7 +226,8 @@ __device__ __forceinline__ void wave_segments(int32_t leaf, bool inr, int64_t n,
 
 // Register budget: two wavefronts per SIMD in FP64 (256 registers), four in FP32 (128).
 // DYN adds the Newmark inertia term: f_v += S_v m_p a_p, and the tangent's (2 m_p / dt^2) S_a S_b
-// as 36 per-segment sums in their own record, which the row gather adds to the block diagonals.
+// (FP64: as 36 per-segment sums in their own record, which the row gather adds to the block
+// diagonals; FP32: in the block values).
 template <typename T, bool DYN>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 4)))
 void k_assemble_fast(AsmArgs A) {
@@ -359,10 +360,12 @@ void k_assemble_fast(AsmArgs A) {
     __syncthreads();
   }
   if (!A.K) return;
-  if constexpr (DYN) {
-    // inertia tangent (2 m / dt^2) S_a S_b on the diagonal of block (a, b): one scalar per
-    // upper-triangle block, summed per segment like the stiffness values and added to the
-    // block diagonals by the row gather (so the basis values are dead in the block loop)
+  // FP64: the inertia tangent (2 m / dt^2) S_a S_b on the diagonal of block (a, b) is one scalar
+  // per upper-triangle block, summed per segment like the stiffness values and added to the
+  // block diagonals by the row gather, so the basis values are dead in the block loop (they
+  // would spill there). FP32 adds it to the block values in the loop.
+  constexpr bool kMassRec = DYN && sizeof(T) == 8;
+  if constexpr (kMassRec) {
     const T cm = T(2.0 * mp / (A.dt * A.dt));
     int q = 0;
 #pragma unroll
@@ -420,6 +423,7 @@ void k_assemble_fast(AsmArgs A) {
         X[k][2][k] -= tg2;
       }
     }
+    const T msb = (DYN && !kMassRec) ? T(2.0 * mp / (A.dt * A.dt)) * S[b] : T(0);  // inertia: (2 m / dt^2) S_b
 #pragma unroll
     for (int a = 0; a <= b; ++a) {
       const int slotv = (blk % kBPR) * 9;
@@ -433,6 +437,8 @@ void k_assemble_fast(AsmArgs A) {
             val = vd[k][r];
           } else {
             val = X[k][r][0] * g[a][0] + X[k][r][1] * g[a][1] + X[k][r][2] * g[a][2];
+            if constexpr (DYN && !kMassRec)
+              if (r == k) val += msb * S[a];
           }
           vd[r][k] = val;
           red[slotv + 3 * r + k][lane] = val;
@@ -515,7 +521,7 @@ __device__ __forceinline__ int64_t xcd_block(int64_t w, int64_t n) {
 // overwritten. The loads of a batch of contributions are
 // issued without branches (indices past the end repeat the last one and are not added), so
 // that they are all in flight together.
-template <typename T, bool WANTK>
+template <typename T, bool WANTK, bool MASS>
 __global__ __launch_bounds__(64) void k_gather(AsmArgs A, int64_t n_node) {
   extern __shared__ __align__(16) unsigned char gsm[];
   T* acc = reinterpret_cast<T*>(gsm);
@@ -543,7 +549,7 @@ __global__ __launch_bounds__(64) void k_gather(AsmArgs A, int64_t n_node) {
   // dynamic assembly: the inertia sum of block (a, b) (index b (b + 1)/2 + a, a <= b) is added to
   // the block's diagonal values
   const T* segM = reinterpret_cast<const T*>(A.segM);
-  const bool dg0 = WANTK && segM && r0 == k0, dg1 = WANTK && segM && has1 && r1 == k1;
+  const bool dg0 = r0 == k0, dg1 = has1 && r1 == k1;
   const int fl = lane < 3 ? lane : 0;
   const int c0 = A.con_off[nd], c1 = A.con_off[nd + 1];
   // lane j holds contribution cl + j of the node (64 at a time, indices past the end repeat the
@@ -565,7 +571,7 @@ __global__ __launch_bounds__(64) void k_gather(AsmArgs A, int64_t n_node) {
       cs[j] = __builtin_amdgcn_readlane(my_cs, q);
       cp[j] = __builtin_amdgcn_readlane(my_cp, q);
     }
-    T val0[kBatch], val1[kBatch];
+    T val0[kBatch], val1[kBatch], mv0[kBatch], mv1[kBatch];
     int16_t p0[kBatch], p1[kBatch];
     double fv[kBatch];
 #pragma unroll
@@ -578,8 +584,12 @@ __global__ __launch_bounds__(64) void k_gather(AsmArgs A, int64_t n_node) {
         const int tri = 9 * (slot * (slot + 1) / 2);
         val0[j] = src[slot <= b0 ? up0 + 9 * slot : lo0 + tri];
         val1[j] = src[slot <= b1 ? up1 + 9 * slot : lo1 + tri];
-        if (dg0) val0[j] += segM[rec * 36 + (slot <= b0 ? b0 * (b0 + 1) / 2 + slot : tri / 9 + b0)];
-        if (dg1) val1[j] += segM[rec * 36 + (slot <= b1 ? b1 * (b1 + 1) / 2 + slot : tri / 9 + b1)];
+        if constexpr (MASS) {  // loaded with the batch, added below (no wait inside the load loop)
+          const T m0 = segM[rec * 36 + (slot <= b0 ? b0 * (b0 + 1) / 2 + slot : tri / 9 + b0)];
+          const T m1 = segM[rec * 36 + (slot <= b1 ? b1 * (b1 + 1) / 2 + slot : tri / 9 + b1)];
+          mv0[j] = dg0 ? m0 : T(0);
+          mv1[j] = dg1 ? m1 : T(0);
+        }
         p0[j] = bp[b0];
         p1[j] = bp[b1];
       }
@@ -591,8 +601,13 @@ __global__ __launch_bounds__(64) void k_gather(AsmArgs A, int64_t n_node) {
     for (int j = 0; j < kBatch; ++j) {
       if (j >= nb) break;
       if (WANTK) {
-        acc[r0 * 3 * deg + 3 * p0[j] + k0] += val0[j];
-        if (has1) acc[r1 * 3 * deg + 3 * p1[j] + k1] += val1[j];
+        T a0 = val0[j], a1 = val1[j];
+        if constexpr (MASS) {  // dynamic assembly: the block's inertia sum on its diagonal values
+          a0 += mv0[j];
+          a1 += mv1[j];
+        }
+        acc[r0 * 3 * deg + 3 * p0[j] + k0] += a0;
+        if (has1) acc[r1 * 3 * deg + 3 * p1[j] + k1] += a1;
       }
       fsum += fv[j];
     }
@@ -609,10 +624,14 @@ template <typename T>
 static void launch_gather(const mpm_mesh* m, hipStream_t st, const AsmArgs& A) {
   if (!m->n_node) return;
   const dim3 grid(unsigned(m->n_node));
-  if (A.K)
-    hipLaunchKernelGGL((k_gather<T, true>), grid, dim3(64), size_t(9) * m->max_deg * sizeof(T), st, A, m->n_node);
+  if (A.K && A.segM)
+    hipLaunchKernelGGL((k_gather<T, true, true>), grid, dim3(64), size_t(9) * m->max_deg * sizeof(T), st, A,
+                       m->n_node);
+  else if (A.K)
+    hipLaunchKernelGGL((k_gather<T, true, false>), grid, dim3(64), size_t(9) * m->max_deg * sizeof(T), st, A,
+                       m->n_node);
   else
-    hipLaunchKernelGGL((k_gather<T, false>), grid, dim3(64), 0, st, A, m->n_node);
+    hipLaunchKernelGGL((k_gather<T, false, false>), grid, dim3(64), 0, st, A, m->n_node);
 }
 
 // ------------------------------------------------------------------ general path
@@ -1123,7 +1142,7 @@ extern "C" int32_t mpm_assemble_dynamic(const mpm_mesh_t* m, const mpm_state_t* 
   A.sigma = sigma6;
   A.vel = v_n;
   A.dt = dt;
-  A.segM = m->d_segM;
+  A.segM = precision == MPM_F64 ? m->d_segM : nullptr;  // FP64 keeps the inertia sums in records
   A.a_new = a_new;
   A.v_new = v_new;
   return assemble_impl(m, A, precision, f_ext, dirichlet, r, rnorm, (hipStream_t)stream, "mpm_assemble_dynamic");

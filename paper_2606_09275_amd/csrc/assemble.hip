@@ -1,8 +1,8 @@
 // Assembly kernels: fused per-point GIMP basis -> kinematics -> Hencky/von Mises return ->
 // consistent tangent -> per-leaf segmented reduction in LDS -> segment records -> (records
 // of heavily populated leaves summed) -> one workgroup per node row writes f_int and the CSR
-// values; a general kernel with atomics for domains overlapping several leaves; body force;
-// residual and its FP64 norm; the adjoint gather.
+// values; rows gathered from per-node lists of the points whose domain overlaps several
+// leaves; body force; residual and its FP64 norm; the adjoint gather.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -55,11 +55,6 @@ struct AsmArgs {
 
 __device__ __forceinline__ void raise(DevErr* err, int code, int64_t idx) {
   if (atomicCAS(&err->code, 0, code) == 0) err->index = (unsigned long long)idx;
-}
-
-template <typename T>
-__device__ __forceinline__ void atomic_add_val(T* p, T v) {
-  atomicAdd(p, v);
 }
 
 // Basis of a point over one leaf overlap box, accumulated into the 8 slots of that leaf.
@@ -635,21 +630,9 @@ static void launch_gather(const mpm_mesh* m, hipStream_t st, const AsmArgs& A) {
 }
 
 // ------------------------------------------------------------------ general path
-// Points whose domain overlaps several leaves: one lane per point, support merged over the
-// leaves (up to 64 nodes), direct atomics; CSR positions found by binary search in the row.
+// Points whose domain overlaps several leaves: the basis is merged over the leaves the domain
+// overlaps (up to 64 nodes); used by the row kernel below, the body force and the adjoint.
 constexpr int kMaxSup = kMaxPointLeaves * 8;
-
-__device__ __forceinline__ int64_t csr_pos(const int64_t* row_ptr, const int32_t* col, int64_t row, int32_t cv) {
-  int64_t lo = row_ptr[row], hi = row_ptr[row + 1] - 1;
-  while (lo <= hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    const int32_t v = col[mid];
-    if (v == cv) return mid;
-    if (v < cv) lo = mid + 1;
-    else hi = mid - 1;
-  }
-  return -1;
-}
 
 template <typename T>
 __device__ int general_basis(const AsmArgs& A, int64_t t, const double x[3], const double l[3], int32_t* nd, T* S,

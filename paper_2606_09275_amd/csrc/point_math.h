@@ -35,8 +35,8 @@ __device__ __forceinline__ float t_exp<float>(float v) { return expf(v); }
 
 // log1p(z)/z for |z| < 1/16 by the Mercator series log(1 + z) = z - z^2/2 + z^3/3 - ...
 // (Horner form of sum_k (-z)^k / (k + 1)); the truncation error after degree n is below
-// |z|^(n+1) / (n + 2) relative, i.e. under 2^-57 for FP64 at n = 12 and under 2^-27 for FP32 at
-// n = 6. Small logarithmic strains and the ratio of close eigenvalues take this path; larger
+// |z|^(n+1) / (n + 2) relative (an alternating series), i.e. under 2^-55 for FP64 at n = 12 and
+// at most 2^-31 for FP32 at n = 6. Small logarithmic strains and the ratio of close eigenvalues take this path; larger
 // arguments call log1p.
 constexpr double kSeriesMax = 0.0625;
 template <typename T>

@@ -116,7 +116,9 @@ typedef struct {
 /* Material point state, SoA device arrays in SORTED point order (see mpm_permute).
  * Updated-Lagrangian: the step starts from F_n (J_n = det F_n) and the elastic left
  * Cauchy-Green tensor b_n; V_n is the point volume at the start of the step and also
- * (generated configs) 8 l1 l2 l3 of the GIMP domain. Elastic points: sy = +inf. */
+ * (generated configs) 8 l1 l2 l3 of the GIMP domain. Elastic points: sy = +inf.
+ * On a mesh built without points every per-point array of every entry point (state fields,
+ * per-point outputs, point order) may be NULL, and so may K values when nnz = 0. */
 typedef struct {
   const double* x;    /* [3][n] domain centres */
   const double* l;    /* [3][n] domain half side lengths */

@@ -1056,8 +1056,10 @@ static AsmArgs make_args(const mpm_mesh* m, const mpm_state_t* s) {
   return A;
 }
 
-static bool state_ok(const mpm_state_t* s) {
-  return s && s->x && s->l && s->vol && s->Jn && s->bn && s->E && s->nu && s->sy;
+// the per-point fields are required when the mesh has points (a mesh without points takes
+// null or empty arrays)
+static bool state_ok(const mpm_state_t* s, int64_t n) {
+  return s && (n == 0 || (s->x && s->l && s->vol && s->Jn && s->bn && s->E && s->nu && s->sy));
 }
 
 }  // namespace mpm
@@ -1065,7 +1067,7 @@ static bool state_ok(const mpm_state_t* s) {
 using namespace mpm;
 
 extern "C" int32_t mpm_external_force(const mpm_mesh_t* m, const mpm_state_t* s, double* f_ext, void* stream) {
-  if (!m || !s || !f_ext || !s->x || !s->l || !s->mass) {
+  if (!m || !s || !f_ext || (m->n_point && (!s->x || !s->l || !s->mass))) {
     set_error(MPM_EARG, "mpm_external_force: null argument");
     return MPM_EARG;
   }
@@ -1094,8 +1096,8 @@ extern "C" int32_t mpm_assemble(const mpm_mesh_t* m, const mpm_state_t* s, const
                                 const double* f_ext, const uint8_t* dirichlet, double* f_int, void* K_vals,
                                 double* sigma6, double* r, double* rnorm, double* F_new, double* be_new,
                                 void* stream) {
-  if (!m || !state_ok(s) || !u || !f_int || (precision != MPM_F64 && precision != MPM_F32K) ||
-      (F_new && !s->Fn)) {
+  if (!m || !state_ok(s, m->n_point) || !u || !f_int || (precision != MPM_F64 && precision != MPM_F32K) ||
+      (F_new && m->n_point && !s->Fn)) {
     set_error(MPM_EARG, "mpm_assemble: null argument, bad precision or F_new without F_n");
     return MPM_EARG;
   }
@@ -1113,8 +1115,8 @@ extern "C" int32_t mpm_assemble_dynamic(const mpm_mesh_t* m, const mpm_state_t* 
                                         const double* v_n, double dt, int32_t precision, const double* f_ext,
                                         const uint8_t* dirichlet, double* f_int, void* K_vals, double* sigma6,
                                         double* r, double* rnorm, double* a_new, double* v_new, void* stream) {
-  if (!m || !state_ok(s) || !s->mass || !u || !v_n || !f_int || !(dt > 0.0) || !std::isfinite(dt) ||
-      (precision != MPM_F64 && precision != MPM_F32K)) {
+  if (!m || !state_ok(s, m->n_point) || (m->n_point && (!s->mass || !v_n)) || !u || !f_int || !(dt > 0.0) ||
+      !std::isfinite(dt) || (precision != MPM_F64 && precision != MPM_F32K)) {
     set_error(MPM_EARG, "mpm_assemble_dynamic: null argument, no mass, bad step size or bad precision");
     return MPM_EARG;
   }
@@ -1193,7 +1195,7 @@ static int32_t assemble_impl(const mpm_mesh_t* m, const AsmArgs& A, int32_t prec
 extern "C" int32_t mpm_assemble_adjoint(const mpm_mesh_t* m, const mpm_state_t* s, const double* u,
                                         const double* lambda, int32_t precision, double* dE, double* dnu,
                                         double* dsy, double* dV, void* stream) {
-  if (!m || !state_ok(s) || !u || !lambda || !dE || !dnu || !dsy || !dV ||
+  if (!m || !state_ok(s, m->n_point) || !u || !lambda || (m->n_point && (!dE || !dnu || !dsy || !dV)) ||
       (precision != MPM_F64 && precision != MPM_F32K)) {
     set_error(MPM_EARG, "mpm_assemble_adjoint: null argument or bad precision");
     return MPM_EARG;

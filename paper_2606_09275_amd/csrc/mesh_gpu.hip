@@ -717,7 +717,7 @@ extern "C" int32_t mpm_mesh_arrays(const mpm_mesh_t* m, mpm_mesh_arrays_t* o) {
 
 extern "C" int32_t mpm_point_sort(const mpm_mesh_t* m, const double* x, int64_t n, int64_t* perm_out,
                                   int32_t* leaf_out, void* stream) {
-  if (!m || !x || !perm_out || !leaf_out || n != m->n_point) {
+  if (!m || n != m->n_point || (n > 0 && (!x || !perm_out || !leaf_out))) {
     set_error(MPM_EARG, "mpm_point_sort: null argument or n differs from the mesh's point count");
     return MPM_EARG;
   }
@@ -728,7 +728,7 @@ extern "C" int32_t mpm_point_sort(const mpm_mesh_t* m, const double* x, int64_t 
 
 extern "C" int32_t mpm_permute(const mpm_mesh_t* m, const int64_t* perm, const double* src, double* dst,
                                int32_t ncomp, void* stream) {
-  if (!m || !src || !dst || ncomp <= 0) {
+  if (!m || ncomp <= 0 || (m->n_point > 0 && (!src || !dst))) {
     set_error(MPM_EARG, "mpm_permute: null argument");
     return MPM_EARG;
   }

@@ -292,7 +292,7 @@ using namespace mpm;
 
 extern "C" int32_t mpm_spmv(const mpm_mesh_t* m, int32_t precision, const void* K_vals, const double* x, double* y,
                             void* stream) {
-  if (!m || !K_vals || !x || !y || (precision != MPM_F64 && precision != MPM_F32K)) {
+  if (!m || (!K_vals && m->nnz) || !x || !y || (precision != MPM_F64 && precision != MPM_F32K)) {
     set_error(MPM_EARG, "mpm_spmv: null argument or bad precision");
     return MPM_EARG;
   }
@@ -308,7 +308,7 @@ extern "C" int32_t mpm_spmv(const mpm_mesh_t* m, int32_t precision, const void* 
 extern "C" int32_t mpm_solve_cg(const mpm_mesh_t* m, int32_t precision, const void* K_vals,
                                 const uint8_t* dirichlet, const double* b, double* x, double rtol, int32_t max_iter,
                                 int32_t* iters, double* relres, void* stream) {
-  if (!m || !K_vals || !b || !x || (precision != MPM_F64 && precision != MPM_F32K) || !(rtol >= 0.0) ||
+  if (!m || (!K_vals && m->nnz) || !b || !x || (precision != MPM_F64 && precision != MPM_F32K) || !(rtol >= 0.0) ||
       max_iter < 0) {
     set_error(MPM_EARG, "mpm_solve_cg: null argument, bad precision, negative tolerance or iteration limit");
     return MPM_EARG;

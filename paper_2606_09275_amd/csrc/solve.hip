@@ -13,7 +13,8 @@
 namespace mpm {
 
 constexpr int kSpmvNodes = 4;    // nodes per workgroup, one wavefront per node
-constexpr int kDotBlocks = 512;  // partial sums of a dot product
+constexpr int kDotBlocks = 512;    // partial sums of a dot product
+constexpr int kUpdBlocks = 2048;   // blocks of the vector update (each leaves two partial sums)
 
 // scalars kept on the device between the kernels of one solve
 enum CgScalar { kRZ = 0, kPQ, kBB, kRR, kRZN, kBeta, kNumScalars };
@@ -132,35 +133,61 @@ __global__ __launch_bounds__(256) void k_cg_init(const int64_t* __restrict__ row
   p[d] = z[d];
 }
 
-// alpha = rz / pq; x += alpha p; r -= alpha q; z = dinv r
+// alpha = rz / pq; x += alpha p; r -= alpha q; z = dinv r; and the block's partial sums of the
+// new r.z and r.r (part[block], part[gridDim + block]), summed by k_cg_step in a fixed order
 __global__ __launch_bounds__(256) void k_cg_update(double* __restrict__ x, double* __restrict__ r,
                                                    double* __restrict__ z, const double* __restrict__ p,
                                                    const double* __restrict__ q, const double* __restrict__ dinv,
-                                                   int64_t ndof, const double* scal, const CgFlags* flags) {
+                                                   int64_t ndof, const double* scal, double* __restrict__ part,
+                                                   const CgFlags* flags) {
+  __shared__ double sh[256];
   if (flags->done) return;
   const double pq = scal[kPQ];
   if (!(pq > 0.0)) return;  // not positive definite along p: the step kernel stops the solve
   const double alpha = scal[kRZ] / pq;
+  double rz = 0.0, rr = 0.0;
   for (int64_t d = int64_t(blockIdx.x) * 256 + threadIdx.x; d < ndof; d += int64_t(gridDim.x) * 256) {
     x[d] += alpha * p[d];
     const double rd = r[d] - alpha * q[d];
+    const double zd = dinv[d] * rd;
     r[d] = rd;
-    z[d] = dinv[d] * rd;
+    z[d] = zd;
+    rz += rd * zd;
+    rr += rd * rd;
+  }
+  const double srz = block_sum(rz, sh);
+  const double srr = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = srz;
+    part[gridDim.x + blockIdx.x] = srr;
   }
 }
 
-// after r.z -> scal[kRZN] and r.r -> scal[kRR]: beta, convergence, iteration count
-__global__ void k_cg_step(double* scal, CgFlags* flags, double rtol2, int max_iter) {
+// r.z -> scal[kRZN] and r.r -> scal[kRR] from the update's nb partials of each, then beta,
+// convergence and the iteration count (one block)
+__global__ __launch_bounds__(256) void k_cg_step(double* scal, const double* __restrict__ part, int nb,
+                                                 CgFlags* flags, double rtol2, int max_iter) {
+  __shared__ double sh[256];
   if (flags->done) return;
   if (!(scal[kPQ] > 0.0)) {  // breakdown: the update was skipped
-    flags->done = 2;
+    if (threadIdx.x == 0) flags->done = 2;
     return;
   }
-  flags->iters += 1;
-  const double rz_new = scal[kRZN];
-  scal[kBeta] = rz_new / scal[kRZ];
-  scal[kRZ] = rz_new;
-  if (!(scal[kRR] > rtol2 * scal[kBB]) || flags->iters >= max_iter || !(rz_new > 0.0)) flags->done = 1;
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < nb; k += 256) {
+    a += part[k];
+    b += part[nb + k];
+  }
+  const double rz_new = block_sum(a, sh);
+  const double rr = block_sum(b, sh);
+  if (threadIdx.x == 0) {
+    scal[kRZN] = rz_new;
+    scal[kRR] = rr;
+    flags->iters += 1;
+    scal[kBeta] = rz_new / scal[kRZ];
+    scal[kRZ] = rz_new;
+    if (!(rr > rtol2 * scal[kBB]) || flags->iters >= max_iter || !(rz_new > 0.0)) flags->done = 1;
+  }
 }
 
 // p = z + beta p
@@ -205,8 +232,8 @@ static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 static int32_t cg_buffers(mpm_mesh* m, hipStream_t st, CgBuf* B) {
   const size_t nd = size_t(3 * m->n_node);
   const size_t vec = align256(nd * 8);
-  const size_t need = 5 * vec + align256(kDotBlocks * 8) + align256(kNumScalars * 8) + align256(sizeof(CgFlags)) +
-                      align256(std::max<size_t>(1, nd));
+  const size_t need = 5 * vec + align256(2 * kUpdBlocks * 8) + align256(kNumScalars * 8) +
+                      align256(sizeof(CgFlags)) + align256(std::max<size_t>(1, nd));
   if (m->cg_bytes < need || !m->d_cg) {
     MPM_HIP(hipStreamSynchronize(st));
     if (m->d_cg) MPM_HIP(hipFree(m->d_cg));
@@ -226,8 +253,8 @@ static int32_t cg_buffers(mpm_mesh* m, hipStream_t st, CgBuf* B) {
   B->q = reinterpret_cast<double*>(w + 3 * vec);
   B->dinv = reinterpret_cast<double*>(w + 4 * vec);
   w += 5 * vec;
-  B->part = reinterpret_cast<double*>(w);
-  w += align256(kDotBlocks * 8);
+  B->part = reinterpret_cast<double*>(w);  // dot products: kDotBlocks partials; update: 2 x kUpdBlocks
+  w += align256(2 * kUpdBlocks * 8);
   B->scal = reinterpret_cast<double*>(w);
   w += align256(kNumScalars * 8);
   B->flags = reinterpret_cast<CgFlags*>(w);
@@ -243,7 +270,7 @@ static int32_t solve_cg(mpm_mesh* m, const void* K, const uint8_t* dir, const do
   int32_t rc = cg_buffers(m, st, &B);
   if (rc) return rc;
   const int64_t nd = 3 * m->n_node;
-  const unsigned gv = unsigned(std::max<int64_t>(1, std::min<int64_t>(2048, (nd + 255) / 256)));
+  const unsigned gv = unsigned(std::max<int64_t>(1, std::min<int64_t>(kUpdBlocks, (nd + 255) / 256)));
   hipLaunchKernelGGL(k_cg_init<T>, dim3(unsigned((nd + 255) / 256)), dim3(256), 0, st, m->d_row_ptr, m->d_col,
                      static_cast<const T*>(K), dir, b, nd, B.fr, B.dinv, x, B.r, B.z, B.p);
   launch_dot(B.r, B.z, nd, B.part, B.scal, kRZ, nullptr, st);
@@ -260,10 +287,8 @@ static int32_t solve_cg(mpm_mesh* m, const void* K, const uint8_t* dir, const do
       launch_spmv<T>(m, K, B.p, B.q, B.fr, B.flags, st);
       launch_dot(B.p, B.q, nd, B.part, B.scal, kPQ, B.flags, st);
       hipLaunchKernelGGL(k_cg_update, dim3(gv), dim3(256), 0, st, x, B.r, B.z, B.p, B.q, B.dinv, nd, B.scal,
-                         B.flags);
-      launch_dot(B.r, B.z, nd, B.part, B.scal, kRZN, B.flags, st);
-      launch_dot(B.r, B.r, nd, B.part, B.scal, kRR, B.flags, st);
-      hipLaunchKernelGGL(k_cg_step, dim3(1), dim3(1), 0, st, B.scal, B.flags, rtol2, max_iter);
+                         B.part, B.flags);
+      hipLaunchKernelGGL(k_cg_step, dim3(1), dim3(256), 0, st, B.scal, B.part, int(gv), B.flags, rtol2, max_iter);
       hipLaunchKernelGGL(k_cg_dir, dim3(gv), dim3(256), 0, st, B.p, B.z, nd, B.scal, B.flags);
     }
     MPM_HIP(hipGetLastError());

@@ -12,7 +12,7 @@
 
 namespace mpm {
 
-constexpr int kSpmvNodes = 4;    // nodes per workgroup, one wavefront per node
+constexpr int kSpmvLanes = 32;   // lanes per node in the SpMV (8 nodes per 256-thread workgroup)
 constexpr int kDotBlocks = 512;    // partial sums of a dot product
 constexpr int kUpdBlocks = 2048;   // blocks of the vector update (each leaves two partial sums)
 
@@ -24,42 +24,36 @@ struct CgFlags {
 };
 
 // y = K x on the rows of `fr` (others: y = x). The three rows of node n are 9 deg contiguous
-// values [row][block][k] with one column pattern; one wavefront sums them, then a fixed-order
-// butterfly reduction.
+// values [row][block][k] with one column pattern; kSpmvLanes lanes take a node (its columns
+// strided over them: about two each at deg 27), then a fixed-order butterfly reduction inside
+// the group.
 template <typename T>
-__global__ __launch_bounds__(64 * kSpmvNodes) void k_spmv(const int64_t* __restrict__ row_ptr,
-                                                          const int32_t* __restrict__ col, const T* __restrict__ K,
-                                                          const double* __restrict__ x, double* __restrict__ y,
-                                                          const uint8_t* __restrict__ fr, int64_t n_node,
-                                                          const CgFlags* flags) {
+__global__ __launch_bounds__(256) void k_spmv(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                              const T* __restrict__ K, const double* __restrict__ x,
+                                              double* __restrict__ y, const uint8_t* __restrict__ fr, int64_t n_node,
+                                              const CgFlags* flags) {
   if (flags && flags->done) return;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t nd = int64_t(blockIdx.x) * kSpmvNodes + wave;
-  if (nd >= n_node) return;
-  const int64_t base = row_ptr[3 * nd];
-  const int len3 = int(row_ptr[3 * nd + 1] - base);
+  const int sub = threadIdx.x / kSpmvLanes, lane = threadIdx.x % kSpmvLanes;
+  const int64_t nd = int64_t(blockIdx.x) * (256 / kSpmvLanes) + sub;
+  const bool ok = nd < n_node;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  // lane l takes columns l, l + 64, ... of the three rows, two columns per step so that six
-  // values and two x entries are loaded together
-  for (int c = lane; c < len3; c += 128) {
-    const bool two = c + 64 < len3;
-    const int c1 = two ? c + 64 : c;
-    const double xa = x[col[base + c]], xb = x[col[base + c1]];
-    const double k0a = double(K[base + c]), k1a = double(K[base + len3 + c]), k2a = double(K[base + 2 * len3 + c]);
-    const double k0b = double(K[base + c1]), k1b = double(K[base + len3 + c1]),
-                 k2b = double(K[base + 2 * len3 + c1]);
-    const double wb = two ? xb : 0.0;
-    s0 += k0a * xa + k0b * wb;
-    s1 += k1a * xa + k1b * wb;
-    s2 += k2a * xa + k2b * wb;
+  if (ok) {
+    const int64_t base = row_ptr[3 * nd];
+    const int len3 = int(row_ptr[3 * nd + 1] - base);
+    for (int c = lane; c < len3; c += kSpmvLanes) {
+      const double xa = x[col[base + c]];
+      s0 += double(K[base + c]) * xa;
+      s1 += double(K[base + len3 + c]) * xa;
+      s2 += double(K[base + 2 * len3 + c]) * xa;
+    }
   }
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
+  for (int off = kSpmvLanes / 2; off > 0; off >>= 1) {  // stays inside the node's lane group
     s0 += __shfl_xor(s0, off);
     s1 += __shfl_xor(s1, off);
     s2 += __shfl_xor(s2, off);
   }
-  if (lane < 3) {
+  if (ok && lane < 3) {
     const int64_t d = 3 * nd + lane;
     const double s = lane == 0 ? s0 : (lane == 1 ? s1 : s2);
     y[d] = (!fr || fr[d]) ? s : x[d];
@@ -207,8 +201,9 @@ __global__ void k_cg_start(double* scal, CgFlags* flags) {
 template <typename T>
 static void launch_spmv(const mpm_mesh* m, const void* K, const double* x, double* y, const uint8_t* fr,
                         const CgFlags* flags, hipStream_t st) {
-  const dim3 grid(unsigned((m->n_node + kSpmvNodes - 1) / kSpmvNodes));
-  hipLaunchKernelGGL(k_spmv<T>, grid, dim3(64 * kSpmvNodes), 0, st, m->d_row_ptr, m->d_col,
+  constexpr int per = 256 / kSpmvLanes;
+  const dim3 grid(unsigned((m->n_node + per - 1) / per));
+  hipLaunchKernelGGL(k_spmv<T>, grid, dim3(256), 0, st, m->d_row_ptr, m->d_col,
                      static_cast<const T*>(K), x, y, fr, m->n_node, flags);
 }
 

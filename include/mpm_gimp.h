@@ -291,8 +291,8 @@ typedef struct {
  *   field of out (both NULL or both set); X_in/X_out and v_in/v_out optional pairs [3][n]
  *   (X_in needs Fn);
  *   n_out must equal n + 7 * (number of flagged points). Inputs and outputs must not overlap.
- * A work buffer (8 bytes per 256 points for block counts, plus 8 (n + 1) bytes of output
- * offsets) is kept with the mesh and grown when a call needs more. */
+ * A work buffer (8 bytes per 256 points for block counts, 8 (n + 1) bytes of output offsets
+ * and 8 n_out bytes of parent indices) is kept with the mesh and grown when a call needs more. */
 int32_t mpm_split_apply(const mpm_mesh_t* mesh, int64_t n, const uint8_t* split, const mpm_state_t* in,
                         const double* X_in, const double* v_in, const double* props, int32_t prop_mask,
                         const mpm_state_out_t* out, double* X_out, double* v_out, int64_t n_out, void* stream);

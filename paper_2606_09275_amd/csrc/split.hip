@@ -190,20 +190,24 @@ __global__ __launch_bounds__(kSplitBlock) void k_split_offsets(const uint8_t* __
   if (i == 0) offs[n] = n + 7 * blk[nb];
 }
 
-// One thread per output point (coalesced stores): its parent is the last input point whose
-// first output does not exceed it, and its child index the distance to that first output.
+// parent input point of every output point: input i owns outputs offs[i] .. offs[i + 1] - 1
+__global__ __launch_bounds__(256) void k_split_parent(const int64_t* __restrict__ offs, int64_t n,
+                                                      int64_t* __restrict__ parent) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t o0 = offs[i], o1 = offs[i + 1];
+  for (int64_t o = o0; o < o1; ++o) parent[o] = i;
+}
+
+// One thread per output point (coalesced stores): its parent from k_split_parent, its child
+// index the distance to the parent's first output.
 __global__ __launch_bounds__(256) void k_split_emit(SplitIO io, const uint8_t* __restrict__ split,
-                                                    const int64_t* __restrict__ offs) {
+                                                    const int64_t* __restrict__ offs,
+                                                    const int64_t* __restrict__ parent) {
   const int64_t n = io.n, n_out = io.n_out;
   const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (j >= n_out) return;
-  int64_t lo = 0, hi = n;  // first index with offs > j, minus one
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (offs[mid] <= j) lo = mid + 1;
-    else hi = mid;
-  }
-  const int64_t i = lo - 1;
+  const int64_t i = parent[j];
   const int c = int(j - offs[i]);
   const bool s = split[i] != 0;
   const mpm_state_t& S = io.in;
@@ -329,9 +333,14 @@ extern "C" int32_t mpm_split_apply(const mpm_mesh_t* mc, int64_t n, const uint8_
   mpm_mesh* m = const_cast<mpm_mesh*>(mc);
   hipStream_t st = (hipStream_t)stream;
   const int64_t nb = (n + kSplitBlock - 1) / kSplitBlock;
-  if (const int32_t rc = split_buffers(m, nb, n + 1, st)) return rc;
+  if (n_out < n || n_out > 8 * n) {
+    set_error(MPM_EARG, "mpm_split_apply: n_out differs from n + 7 * (flagged points)");
+    return MPM_EARG;
+  }
+  if (const int32_t rc = split_buffers(m, nb, n + 1 + n_out, st)) return rc;
   int64_t* blk = static_cast<int64_t*>(m->d_split);
   int64_t* offs = blk + nb + 1;
+  int64_t* parent = offs + n + 1;
   // block counts of the flags (the scan of the marking call may belong to other flags)
   hipLaunchKernelGGL(k_split_count, dim3(unsigned(nb)), dim3(kSplitBlock), 0, st, split, n, blk);
   hipLaunchKernelGGL(k_split_scan, dim3(1), dim3(1024), 0, st, blk, nb);
@@ -353,7 +362,8 @@ extern "C" int32_t mpm_split_apply(const mpm_mesh_t* mc, int64_t n, const uint8_
   io.n = n;
   io.n_out = n_out;
   hipLaunchKernelGGL(k_split_offsets, dim3(unsigned(nb)), dim3(kSplitBlock), 0, st, split, n, blk, offs, nb);
-  hipLaunchKernelGGL(k_split_emit, dim3(unsigned((n_out + 255) / 256)), dim3(256), 0, st, io, split, offs);
+  hipLaunchKernelGGL(k_split_parent, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, offs, n, parent);
+  hipLaunchKernelGGL(k_split_emit, dim3(unsigned((n_out + 255) / 256)), dim3(256), 0, st, io, split, offs, parent);
   MPM_HIP(hipGetLastError());
   return read_error(m, st, "mpm_split_apply");
 }

@@ -253,6 +253,26 @@ int32_t mpm_solve_cg(const mpm_mesh_t* mesh, int32_t precision, const void* K_va
                      const double* b, double* x, double rtol, int32_t max_iter, int32_t* iters, double* relres,
                      void* stream);
 
+/* Linear solve of a Newton step with restarted GMRES, the Krylov solver the paper names for its
+ * possibly non-symmetric systems (Section 1), with the diagonal Jacobi preconditioner it
+ * proposes (Section 6), applied on the right so that the minimised residual is the true one.
+ * Same free DOFs, Dirichlet treatment, precisions and output as mpm_solve_cg; needs no
+ * symmetry or definiteness of K_ff, only a positive diagonal on the free DOFs.
+ *   restart: Arnoldi steps per cycle, 1..64; max_iter: Arnoldi steps in all.
+ * A cycle ends when the residual norm given by the Givens rotations falls to rtol ||b_f||, at
+ * max_iter steps, or when the Krylov space is invariant; the correction x += M^-1 V y is then
+ * applied and the true residual ||b_f - K_ff x_f|| recomputed, which decides whether to stop.
+ * relres is that recomputed residual over ||b_f|| (0 when b_f = 0). If the Hessenberg matrix
+ * becomes singular (K_ff M^-1 singular on the Krylov space) the solve ends after that cycle's
+ * correction with the residual reached. Orthogonalisation: two passes of classical
+ * Gram-Schmidt per step; reductions in a fixed order (reproducible iterates). Work memory
+ * ((restart + 4) n_dof doubles) is kept with the mesh; the host reads the state once per
+ * cycle. Errors: MPM_EARG (null argument, bad precision, negative tolerance or iteration limit,
+ * restart outside 1..64), MPM_EHIP. */
+int32_t mpm_solve_gmres(const mpm_mesh_t* mesh, int32_t precision, const void* K_vals, const uint8_t* dirichlet,
+                        const double* b, double* x, double rtol, int32_t restart, int32_t max_iter, int32_t* iters,
+                        double* relres, void* stream);
+
 /* GIMP refinement criterion of the adaptive strategy (Section 5): split[p] = 1 when a leaf that
  * point p's domain overlaps with positive volume has half side l_K < beta l_p, l_p the largest
  * of the domain's three half sides (the paper uses beta = 2). The mesh gives the leaves only

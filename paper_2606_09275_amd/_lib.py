@@ -84,6 +84,9 @@ def lib():
     L.mpm_spmv.argtypes = [vp, i32, vp, vp, vp, vp]
     L.mpm_solve_cg.restype = i32
     L.mpm_solve_cg.argtypes = [vp, i32, vp, vp, vp, vp, C.c_double, i32, C.POINTER(i32), C.POINTER(C.c_double), vp]
+    L.mpm_solve_gmres.restype = i32
+    L.mpm_solve_gmres.argtypes = [vp, i32, vp, vp, vp, vp, C.c_double, i32, i32, C.POINTER(i32),
+                                  C.POINTER(C.c_double), vp]
     L.mpm_assemble_dynamic.restype = i32
     L.mpm_assemble_dynamic.argtypes = [vp, C.POINTER(StateT), vp, vp, C.c_double, i32, vp, vp, vp, vp, vp, vp, vp,
                                        vp, vp, vp]
@@ -104,7 +107,7 @@ def lib():
 
 EXPORTED = ["octree_build", "mpm_mesh_info", "mpm_mesh_arrays", "mpm_ghost_faces", "mpm_mesh_free", "mpm_point_sort", "mpm_permute",
             "mpm_external_force", "mpm_assemble", "mpm_assemble_dynamic", "mpm_assemble_adjoint", "mpm_spmv",
-            "mpm_solve_cg", "mpm_split_mark", "mpm_split_apply", "mpm_kernel_timing", "mpm_last_error",
+            "mpm_solve_cg", "mpm_solve_gmres", "mpm_split_mark", "mpm_split_apply", "mpm_kernel_timing", "mpm_last_error",
             "mpm_last_error_index"]
 
 

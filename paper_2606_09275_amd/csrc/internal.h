@@ -127,6 +127,8 @@ struct mpm_mesh {
   size_t stage_bytes = 0;
   void* d_cg = nullptr;             // conjugate-gradient vectors, partial sums, scalars
   size_t cg_bytes = 0;
+  void* d_gm = nullptr;             // GMRES basis, work vectors, partial sums, state
+  size_t gm_bytes = 0;
   void* h_cg = nullptr;             // pinned host copy of the solver flags and scalars
   hipEvent_t cg_ev = nullptr;
   void* d_split = nullptr;          // GIMP split: per-block counts and their scan

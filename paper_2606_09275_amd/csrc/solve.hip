@@ -5,6 +5,7 @@
 // of the mesh in FP64 or FP32; vectors and reductions are FP64 and deterministic (fixed
 // two-stage summation order).
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstring>
 
@@ -31,8 +32,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_spmv(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
                                               const T* __restrict__ K, const double* __restrict__ x,
                                               double* __restrict__ y, const uint8_t* __restrict__ fr, int64_t n_node,
-                                              const CgFlags* flags) {
-  if (flags && flags->done) return;
+                                              const int* skip) {
+  if (skip && *skip) return;
   const int sub = threadIdx.x / kSpmvLanes, lane = threadIdx.x % kSpmvLanes;
   const int64_t nd = int64_t(blockIdx.x) * (256 / kSpmvLanes) + sub;
   const bool ok = nd < n_node;
@@ -94,6 +95,21 @@ __global__ __launch_bounds__(256) void k_dot_final(const double* __restrict__ pa
   if (threadIdx.x == 0) scal[dst] = s;
 }
 
+// diagonal entry of CSR row d (columns ascend: bisection); 0 when the row has none
+template <typename T>
+__device__ __forceinline__ double row_diag(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                           const T* __restrict__ K, int64_t d) {
+  int64_t lo = row_ptr[d], hi = row_ptr[d + 1] - 1;
+  while (lo <= hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    const int32_t c = col[mid];
+    if (c == int32_t(d)) return double(K[mid]);
+    if (c < int32_t(d)) lo = mid + 1;
+    else hi = mid - 1;
+  }
+  return 0.0;
+}
+
 // free DOFs, inverse diagonal, r = z = p = 0 / b on free DOFs, x = 0
 template <typename T>
 __global__ __launch_bounds__(256) void k_cg_init(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
@@ -104,19 +120,8 @@ __global__ __launch_bounds__(256) void k_cg_init(const int64_t* __restrict__ row
                                                  double* __restrict__ p) {
   const int64_t d = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (d >= ndof) return;
-  double diag = 0.0;
+  const double diag = row_diag(row_ptr, col, K, d);
   const int64_t a0 = row_ptr[d], a1 = row_ptr[d + 1];
-  int64_t lo = a0, hi = a1 - 1;  // columns ascend: bisect for the diagonal
-  while (lo <= hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    const int32_t c = col[mid];
-    if (c == int32_t(d)) {
-      diag = double(K[mid]);
-      break;
-    }
-    if (c < int32_t(d)) lo = mid + 1;
-    else hi = mid - 1;
-  }
   const bool f = (!dir || !dir[d]) && a1 > a0 && diag > 0.0;
   fr[d] = f ? 1 : 0;
   dinv[d] = f ? 1.0 / diag : 0.0;
@@ -200,11 +205,11 @@ __global__ void k_cg_start(double* scal, CgFlags* flags) {
 
 template <typename T>
 static void launch_spmv(const mpm_mesh* m, const void* K, const double* x, double* y, const uint8_t* fr,
-                        const CgFlags* flags, hipStream_t st) {
+                        const int* skip, hipStream_t st) {
   constexpr int per = 256 / kSpmvLanes;
   const dim3 grid(unsigned((m->n_node + per - 1) / per));
   hipLaunchKernelGGL(k_spmv<T>, grid, dim3(256), 0, st, m->d_row_ptr, m->d_col,
-                     static_cast<const T*>(K), x, y, fr, m->n_node, flags);
+                     static_cast<const T*>(K), x, y, fr, m->n_node, skip);
 }
 
 static void launch_dot(const double* a, const double* b, int64_t n, double* part, double* scal, int dst,
@@ -279,7 +284,7 @@ static int32_t solve_cg(mpm_mesh* m, const void* K, const uint8_t* dir, const do
   for (int it = 0; it < max_iter; it += kCheck) {
     const int nk = std::min(kCheck, max_iter - it);
     for (int k = 0; k < nk; ++k) {
-      launch_spmv<T>(m, K, B.p, B.q, B.fr, B.flags, st);
+      launch_spmv<T>(m, K, B.p, B.q, B.fr, &B.flags->done, st);
       launch_dot(B.p, B.q, nd, B.part, B.scal, kPQ, B.flags, st);
       hipLaunchKernelGGL(k_cg_update, dim3(gv), dim3(256), 0, st, x, B.r, B.z, B.p, B.q, B.dinv, nd, B.scal,
                          B.part, B.flags);
@@ -303,6 +308,320 @@ static int32_t solve_cg(mpm_mesh* m, const void* K, const uint8_t* dir, const do
   if (iters) *iters = f->iters;
   if (relres) *relres = sc[kBB] > 0.0 ? std::sqrt(std::max(0.0, sc[kRR]) / sc[kBB]) : 0.0;
   if (f->iters == 0 && sc[kBB] > 0.0 && relres) *relres = 1.0;
+  return MPM_OK;
+}
+
+// ------------------------------------------------------------------ GMRES
+// Restarted GMRES with the Jacobi preconditioner applied on the right (the solver the paper
+// names for its possibly non-symmetric systems, with the diagonal preconditioner it proposes
+// as future work), over the same free DOFs as CG: the residual it minimises is the true one,
+// ||b_f - K_ff x_f||. Each Arnoldi step: z = M^-1 v_j, w = K z, two passes of classical
+// Gram-Schmidt against v_0..v_j (one block of dot products and one update each, instead of
+// j + 1 sequential reductions), then the new column of the Hessenberg matrix is reduced by the
+// Givens rotations so far and a new one, whose last entry is the residual norm. At the end of a
+// cycle the triangular system gives y and x += M^-1 V y; the true residual is recomputed at
+// every restart. All control stays on the device (flags read by every kernel); the host reads
+// the state once per cycle.
+constexpr int kMaxRestart = 64;
+constexpr int kHStride = kMaxRestart + 1;
+
+struct GmState {
+  int skip;   // the Arnoldi steps of this cycle are over (or the solve has stopped)
+  int stop;   // the solve is over: converged, step budget spent, or breakdown
+  int k;      // Arnoldi columns of the current cycle
+  int iters;  // Arnoldi steps in all
+  int brk;    // the Hessenberg matrix became singular: stop after this cycle's correction
+  int pad;
+  double bnorm, beta, hinv;
+  double H[kHStride * kMaxRestart];  // column j at j * kHStride (rotated into triangular form)
+  double cs[kMaxRestart], sn[kMaxRestart], g[kHStride], y[kMaxRestart], hc[kHStride];
+};
+constexpr size_t kGmHead = offsetof(GmState, H);  // the part the host reads
+
+__global__ void k_gm_reset(GmState* s) {
+  s->skip = s->stop = s->k = s->iters = s->brk = 0;
+  s->bnorm = s->beta = s->hinv = 0.0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gm_init(const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                                                 const T* __restrict__ K, const uint8_t* __restrict__ dir,
+                                                 int64_t ndof, uint8_t* __restrict__ fr, double* __restrict__ dinv,
+                                                 double* __restrict__ x) {
+  const int64_t d = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (d >= ndof) return;
+  const double diag = row_diag(row_ptr, col, K, d);
+  const bool f = (!dir || !dir[d]) && row_ptr[d + 1] > row_ptr[d] && diag > 0.0;
+  fr[d] = f ? 1 : 0;
+  dinv[d] = f ? 1.0 / diag : 0.0;
+  x[d] = 0.0;
+}
+
+// v0 = b - K x on the free DOFs (w = K x), zero elsewhere; block partial sums of v0 . v0
+__global__ __launch_bounds__(256) void k_gm_resid(const double* __restrict__ b, const double* __restrict__ w,
+                                                  const uint8_t* __restrict__ fr, double* __restrict__ v0,
+                                                  int64_t ndof, double* __restrict__ part, const GmState* s) {
+  __shared__ double sh[256];
+  if (s->stop) return;
+  double acc = 0.0;
+  for (int64_t d = int64_t(blockIdx.x) * 256 + threadIdx.x; d < ndof; d += int64_t(gridDim.x) * 256) {
+    const double r = fr[d] ? b[d] - w[d] : 0.0;
+    v0[d] = r;
+    acc += r * r;
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// start of a cycle: beta = ||v0||; the first call also fixes ||b_f||; stop on convergence,
+// spent budget or an earlier breakdown
+__global__ __launch_bounds__(256) void k_gm_begin(const double* __restrict__ part, int nb, GmState* s, double rtol,
+                                                  int max_iter, int first) {
+  __shared__ double sh[256];
+  if (s->stop) return;
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < nb; k += 256) acc += part[k];
+  const double bb = block_sum(acc, sh);
+  if (threadIdx.x == 0) {
+    const double beta = sqrt(bb);
+    if (first) s->bnorm = beta;
+    s->beta = beta;
+    s->k = 0;
+    if (s->brk || !(beta > rtol * s->bnorm) || s->iters >= max_iter) {
+      s->stop = 1;
+      s->skip = 1;
+    } else {
+      s->skip = 0;
+      s->g[0] = beta;
+      s->hinv = 1.0 / beta;
+    }
+  }
+}
+
+// dst = hinv src (v0 in place, or v_{j+1} = w / h_{j+1,j})
+__global__ __launch_bounds__(256) void k_gm_scale(const double* __restrict__ src, double* __restrict__ dst,
+                                                  int64_t ndof, const GmState* s) {
+  if (s->skip) return;
+  const double h = s->hinv;
+  for (int64_t d = int64_t(blockIdx.x) * 256 + threadIdx.x; d < ndof; d += int64_t(gridDim.x) * 256)
+    dst[d] = h * src[d];
+}
+
+// z = M^-1 v
+__global__ __launch_bounds__(256) void k_gm_precond(const double* __restrict__ v, const double* __restrict__ dinv,
+                                                    double* __restrict__ z, int64_t ndof, const GmState* s) {
+  if (s->skip) return;
+  for (int64_t d = int64_t(blockIdx.x) * 256 + threadIdx.x; d < ndof; d += int64_t(gridDim.x) * 256)
+    z[d] = dinv[d] * v[d];
+}
+
+// partial sums of v_i . w, i = blockIdx.y (0..j), in a fixed order
+__global__ __launch_bounds__(256) void k_gm_dots(const double* __restrict__ V, int64_t vs,
+                                                 const double* __restrict__ w, int64_t ndof,
+                                                 double* __restrict__ part, const GmState* s) {
+  __shared__ double sh[256];
+  if (s->skip) return;
+  const double* v = V + int64_t(blockIdx.y) * vs;
+  double acc = 0.0;
+  for (int64_t d = int64_t(blockIdx.x) * 256 + threadIdx.x; d < ndof; d += int64_t(gridDim.x) * 256)
+    acc += v[d] * w[d];
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[int64_t(blockIdx.y) * kDotBlocks + blockIdx.x] = t;
+}
+
+// hc[i] = sum of the partials of v_i . w (one block per i); H[i][j] = hc[i] in the first pass,
+// += hc[i] in the second
+__global__ __launch_bounds__(256) void k_gm_dots_final(const double* __restrict__ part, int nb, GmState* s, int j,
+                                                       int second) {
+  __shared__ double sh[256];
+  if (s->skip) return;
+  const int i = blockIdx.x;
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < nb; k += 256) acc += part[int64_t(i) * kDotBlocks + k];
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) {
+    s->hc[i] = t;
+    double* h = s->H + int64_t(j) * kHStride;
+    h[i] = second ? h[i] + t : t;
+  }
+}
+
+// w -= sum_i hc[i] v_i (i = 0..j); with want_norm also the block partial sums of w . w
+__global__ __launch_bounds__(256) void k_gm_orth(const double* __restrict__ V, int64_t vs, double* __restrict__ w,
+                                                 int64_t ndof, int j, double* __restrict__ part, int want_norm,
+                                                 const GmState* s) {
+  __shared__ double sh[256];
+  if (s->skip) return;
+  double acc = 0.0;
+  for (int64_t d = int64_t(blockIdx.x) * 256 + threadIdx.x; d < ndof; d += int64_t(gridDim.x) * 256) {
+    double wd = w[d];
+    for (int i = 0; i <= j; ++i) wd -= s->hc[i] * V[int64_t(i) * vs + d];
+    w[d] = wd;
+    acc += wd * wd;
+  }
+  if (want_norm) {
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+  }
+}
+
+// h_{j+1,j} = ||w||; earlier rotations on column j, a new rotation that zeroes h_{j+1,j}, the
+// rotated right-hand side g and its last entry |g_{j+1}| = the residual norm of the step
+__global__ __launch_bounds__(256) void k_gm_rotate(const double* __restrict__ part, int nb, GmState* s, int j,
+                                                   double rtol, int max_iter) {
+  __shared__ double sh[256];
+  if (s->skip) return;
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < nb; k += 256) acc += part[k];
+  const double ww = block_sum(acc, sh);
+  if (threadIdx.x != 0) return;
+  const double hn = sqrt(ww);
+  double* h = s->H + int64_t(j) * kHStride;
+  for (int i = 0; i < j; ++i) {
+    const double a = h[i], c = h[i + 1];
+    h[i] = s->cs[i] * a + s->sn[i] * c;
+    h[i + 1] = -s->sn[i] * a + s->cs[i] * c;
+  }
+  const double r = hypot(h[j], hn);
+  s->iters += 1;
+  if (!(r > 0.0)) {  // singular Hessenberg matrix (K M^-1 singular on the Krylov space)
+    s->brk = 1;
+    s->skip = 1;
+    return;  // k stays j: the correction uses the columns before this one
+  }
+  const double c = h[j] / r, sn = hn / r;
+  s->cs[j] = c;
+  s->sn[j] = sn;
+  h[j] = r;
+  h[j + 1] = 0.0;
+  const double gj = s->g[j];
+  s->g[j + 1] = -sn * gj;
+  s->g[j] = c * gj;
+  s->k = j + 1;
+  s->hinv = hn > 0.0 ? 1.0 / hn : 0.0;
+  if (!(fabs(s->g[j + 1]) > rtol * s->bnorm) || s->iters >= max_iter || !(hn > 0.0)) s->skip = 1;
+}
+
+// y = R^-1 g over the k columns of the cycle (back substitution, one thread)
+__global__ void k_gm_solve(GmState* s) {
+  if (s->stop) return;
+  const int k = s->k;
+  for (int i = k - 1; i >= 0; --i) {
+    double t = s->g[i];
+    for (int l = i + 1; l < k; ++l) t -= s->H[int64_t(l) * kHStride + i] * s->y[l];
+    s->y[i] = t / s->H[int64_t(i) * kHStride + i];
+  }
+}
+
+// x += M^-1 sum_i y_i v_i (i < k)
+__global__ __launch_bounds__(256) void k_gm_xupd(const double* __restrict__ V, int64_t vs,
+                                                 const double* __restrict__ dinv, double* __restrict__ x,
+                                                 int64_t ndof, const GmState* s) {
+  if (s->stop) return;
+  const int k = s->k;
+  for (int64_t d = int64_t(blockIdx.x) * 256 + threadIdx.x; d < ndof; d += int64_t(gridDim.x) * 256) {
+    double t = 0.0;
+    for (int i = 0; i < k; ++i) t += s->y[i] * V[int64_t(i) * vs + d];
+    x[d] += dinv[d] * t;
+  }
+}
+
+// work buffer of GMRES kept with the mesh: V [(restart + 1) n_dof], w, z, dinv [n_dof],
+// partial sums, the state and the free mask
+struct GmBuf {
+  double *V, *w, *z, *dinv, *part;
+  GmState* s;
+  uint8_t* fr;
+  int64_t vs;  // stride of the basis vectors (doubles)
+};
+
+static int32_t gm_buffers(mpm_mesh* m, int restart, hipStream_t st, GmBuf* B) {
+  const size_t nd = size_t(3 * m->n_node);
+  const size_t vec = align256(nd * 8);
+  const size_t npart = std::max<size_t>(size_t(kDotBlocks) * kHStride, kUpdBlocks);
+  const size_t need = size_t(restart + 4) * vec + align256(npart * 8) + align256(sizeof(GmState)) +
+                      align256(std::max<size_t>(1, nd));
+  if (m->gm_bytes < need || !m->d_gm) {
+    MPM_HIP(hipStreamSynchronize(st));
+    if (m->d_gm) MPM_HIP(hipFree(m->d_gm));
+    m->d_gm = nullptr;
+    m->gm_bytes = 0;
+    const hipError_t e = hipMalloc(&m->d_gm, need);
+    if (e != hipSuccess) {
+      m->d_gm = nullptr;
+      return hip_fail(e, "mpm_solve_gmres: work buffer");
+    }
+    m->gm_bytes = need;
+  }
+  char* w = static_cast<char*>(m->d_gm);
+  B->vs = int64_t(vec / 8);
+  B->V = reinterpret_cast<double*>(w);
+  w += size_t(restart + 1) * vec;
+  B->w = reinterpret_cast<double*>(w);
+  B->z = reinterpret_cast<double*>(w + vec);
+  B->dinv = reinterpret_cast<double*>(w + 2 * vec);
+  w += 3 * vec;
+  B->part = reinterpret_cast<double*>(w);
+  w += align256(npart * 8);
+  B->s = reinterpret_cast<GmState*>(w);
+  w += align256(sizeof(GmState));
+  B->fr = reinterpret_cast<uint8_t*>(w);
+  return MPM_OK;
+}
+
+template <typename T>
+static int32_t solve_gmres(mpm_mesh* m, const void* K, const uint8_t* dir, const double* b, double* x, double rtol,
+                           int restart, int max_iter, int* iters, double* relres, hipStream_t st) {
+  GmBuf B;
+  int32_t rc = gm_buffers(m, restart, st, &B);
+  if (rc) return rc;
+  const int64_t nd = 3 * m->n_node;
+  const unsigned gv = unsigned(std::max<int64_t>(1, std::min<int64_t>(kUpdBlocks, (nd + 255) / 256)));
+  const int nb = int(std::max<int64_t>(1, std::min<int64_t>(kDotBlocks, (nd + 255) / 256)));
+  GmState* S = B.s;
+  hipLaunchKernelGGL(k_gm_reset, dim3(1), dim3(1), 0, st, S);
+  hipLaunchKernelGGL(k_gm_init<T>, dim3(unsigned((nd + 255) / 256)), dim3(256), 0, st, m->d_row_ptr, m->d_col,
+                     static_cast<const T*>(K), dir, nd, B.fr, B.dinv, x);
+  // residual of the current x, its norm, v0; the cycle's flags
+  auto begin = [&](int first) {
+    launch_spmv<T>(m, K, x, B.w, B.fr, &S->stop, st);
+    hipLaunchKernelGGL(k_gm_resid, dim3(gv), dim3(256), 0, st, b, B.w, B.fr, B.V, nd, B.part, S);
+    hipLaunchKernelGGL(k_gm_begin, dim3(1), dim3(256), 0, st, B.part, int(gv), S, rtol, max_iter, first);
+    hipLaunchKernelGGL(k_gm_scale, dim3(gv), dim3(256), 0, st, B.V, B.V, nd, S);
+  };
+  begin(1);
+  if (!m->h_cg) MPM_HIP(hipHostMalloc((void**)&m->h_cg, sizeof(CgFlags) + 8 * kNumScalars, hipHostMallocDefault));
+  if (!m->cg_ev) MPM_HIP(hipEventCreateWithFlags(&m->cg_ev, hipEventDisableTiming));
+  static_assert(kGmHead <= sizeof(CgFlags) + 8 * kNumScalars, "pinned copy of the GMRES state too small");
+  for (;;) {
+    MPM_HIP(hipGetLastError());
+    MPM_HIP(hipMemcpyAsync(m->h_cg, S, kGmHead, hipMemcpyDeviceToHost, st));
+    MPM_HIP(hipEventRecord(m->cg_ev, st));
+    hipError_t q;
+    while ((q = hipEventQuery(m->cg_ev)) == hipErrorNotReady) {
+    }
+    if (q != hipSuccess) return hip_fail(q, "mpm_solve_gmres");
+    if (static_cast<const GmState*>(m->h_cg)->stop) break;
+    for (int j = 0; j < restart; ++j) {
+      const double* vj = B.V + int64_t(j) * B.vs;
+      hipLaunchKernelGGL(k_gm_precond, dim3(gv), dim3(256), 0, st, vj, B.dinv, B.z, nd, S);
+      launch_spmv<T>(m, K, B.z, B.w, B.fr, &S->skip, st);
+      for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(k_gm_dots, dim3(unsigned(nb), unsigned(j + 1)), dim3(256), 0, st, B.V, B.vs, B.w, nd,
+                           B.part, S);
+        hipLaunchKernelGGL(k_gm_dots_final, dim3(unsigned(j + 1)), dim3(256), 0, st, B.part, nb, S, j, pass);
+        hipLaunchKernelGGL(k_gm_orth, dim3(gv), dim3(256), 0, st, B.V, B.vs, B.w, nd, j, B.part, pass, S);
+      }
+      hipLaunchKernelGGL(k_gm_rotate, dim3(1), dim3(256), 0, st, B.part, int(gv), S, j, rtol, max_iter);
+      hipLaunchKernelGGL(k_gm_scale, dim3(gv), dim3(256), 0, st, B.w, B.V + int64_t(j + 1) * B.vs, nd, S);
+    }
+    hipLaunchKernelGGL(k_gm_solve, dim3(1), dim3(1), 0, st, S);
+    hipLaunchKernelGGL(k_gm_xupd, dim3(gv), dim3(256), 0, st, B.V, B.vs, B.dinv, x, nd, S);
+    begin(0);
+  }
+  const GmState* h = static_cast<const GmState*>(m->h_cg);
+  if (iters) *iters = h->iters;
+  if (relres) *relres = h->bnorm > 0.0 ? h->beta / h->bnorm : 0.0;
   return MPM_OK;
 }
 
@@ -345,6 +664,33 @@ extern "C" int32_t mpm_solve_cg(const mpm_mesh_t* m, int32_t precision, const vo
   }
   if (precision == MPM_F64) rc = solve_cg<double>(mm, K_vals, dirichlet, b, x, rtol, max_iter, &it, &rr, st);
   else rc = solve_cg<float>(mm, K_vals, dirichlet, b, x, rtol, max_iter, &it, &rr, st);
+  if (iters) *iters = it;
+  if (relres) *relres = rr;
+  return rc;
+}
+
+extern "C" int32_t mpm_solve_gmres(const mpm_mesh_t* m, int32_t precision, const void* K_vals,
+                                   const uint8_t* dirichlet, const double* b, double* x, double rtol,
+                                   int32_t restart, int32_t max_iter, int32_t* iters, double* relres,
+                                   void* stream) {
+  if (!m || (!K_vals && m->nnz) || !b || !x || (precision != MPM_F64 && precision != MPM_F32K) || !(rtol >= 0.0) ||
+      max_iter < 0 || restart < 1 || restart > kMaxRestart) {
+    set_error(MPM_EARG, "mpm_solve_gmres: null argument, bad precision, negative tolerance or iteration limit, "
+                        "or restart outside 1..64");
+    return MPM_EARG;
+  }
+  mpm_mesh* mm = const_cast<mpm_mesh*>(m);
+  hipStream_t st = (hipStream_t)stream;
+  int it = 0;
+  double rr = 0.0;
+  int32_t rc = MPM_OK;
+  if (m->n_node == 0) {
+    if (iters) *iters = 0;
+    if (relres) *relres = 0.0;
+    return MPM_OK;
+  }
+  if (precision == MPM_F64) rc = solve_gmres<double>(mm, K_vals, dirichlet, b, x, rtol, restart, max_iter, &it, &rr, st);
+  else rc = solve_gmres<float>(mm, K_vals, dirichlet, b, x, rtol, restart, max_iter, &it, &rr, st);
   if (iters) *iters = it;
   if (relres) *relres = rr;
   return rc;

@@ -293,6 +293,18 @@ class Mesh:
                                  C.byref(it), C.byref(rr), _stream()))
         return x, int(it.value), float(rr.value)
 
+    def solve_gmres(self, K: torch.Tensor, b: torch.Tensor, dirichlet=None, rtol: float = 1e-8, restart: int = 30,
+                    max_iter: int = 1000, out: Optional[torch.Tensor] = None):
+        """Restarted GMRES with the Jacobi preconditioner on the right for K_ff x_f = b_f (free
+        DOFs); returns (x, Arnoldi steps, true relative residual)."""
+        p = MPM_F64 if K.dtype == torch.float64 else MPM_F32K
+        x = torch.empty_like(b) if out is None else out
+        it = C.c_int32(0)
+        rr = C.c_double(0.0)
+        check(lib().mpm_solve_gmres(self.h, p, _ptr(K), _ptr(dirichlet), _ptr(b), _ptr(x), float(rtol), int(restart),
+                                    int(max_iter), C.byref(it), C.byref(rr), _stream()))
+        return x, int(it.value), float(rr.value)
+
     def adjoint(self, s: dict, u: torch.Tensor, lam: torch.Tensor, precision="f64", out: Optional[dict] = None):
         p = PRECISION.get(precision, precision)
         n = self.info["n_point"]

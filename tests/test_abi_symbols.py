@@ -66,6 +66,9 @@ def test_argument_checks_need_no_gpu():
     assert L.octree_build(None, None, None, 0, None, C.byref(h)) == _lib.MPM_EARG
     cnt = C.c_int64(0)
     assert L.mpm_split_mark(None, None, None, 0, C.c_double(2.0), None, C.byref(cnt), None) == _lib.MPM_EARG
+    it, rr = C.c_int32(0), C.c_double(0.0)
+    assert L.mpm_solve_gmres(None, 0, None, None, None, None, 1e-8, 30, 100, C.byref(it), C.byref(rr),
+                             None) == _lib.MPM_EARG
     info = _lib.MeshInfoT()
     assert L.mpm_mesh_info(None, C.byref(info)) == _lib.MPM_EARG
     buf = C.create_string_buffer(256)

@@ -479,7 +479,41 @@ def newton_solve(mesh, views, u, f_ext, dirichlet, info, iters=100, spmv_reps=20
                      "spmv_hbm_frac": byts / (spmv_ms * 1e-3) / 1e9 / PEAK_HBM_GBS}
         log(f"[bench] solve {prec}: {ms_it:.3f} ms per CG iteration ({it} timed); to 1e-6: {it6} iterations, "
             f"{solve_ms:.1f} ms (relres {rel6:.1e}); SpMV {spmv_ms:.3f} ms = {res[prec]['spmv_gbs']:.0f} GB/s")
+        res[prec]["gmres"] = gmres_solves(mesh, K, b, dirichlet, views, u, f_ext, prec)
     return res
+
+
+def gmres_solves(mesh, K, b, dirichlet, views, u, f_ext, prec, restart=30, max_iter=3000):
+    """Restarted GMRES (Jacobi preconditioner on the right) on the elastic tangent above (ms per
+    Arnoldi step over two full cycles, steps and time to a 1e-6 true relative residual) and on
+    the tangent at this workload's strained state and displacement, which is not positive
+    definite: CG stops there, GMRES is timed to 1e-6 (at most max_iter steps)."""
+    import torch
+    mesh.solve_gmres(K, b, dirichlet, rtol=0.0, restart=restart, max_iter=restart)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, it, _ = mesh.solve_gmres(K, b, dirichlet, rtol=0.0, restart=restart, max_iter=2 * restart)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / max(it, 1)
+    t0 = time.perf_counter()
+    _, it6, rel6 = mesh.solve_gmres(K, b, dirichlet, rtol=1e-6, restart=restart, max_iter=max_iter)
+    torch.cuda.synchronize()
+    el_ms = (time.perf_counter() - t0) * 1e3
+    outs = {}
+    mesh.assemble(views, u, prec, f_ext=f_ext, dirichlet=dirichlet, out=outs)
+    Kp, bp = outs["K"], -outs["r"]
+    _, itc, relc = mesh.solve_cg(Kp, bp, dirichlet, rtol=1e-6, max_iter=max_iter)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, itp, relp = mesh.solve_gmres(Kp, bp, dirichlet, rtol=1e-6, restart=restart, max_iter=max_iter)
+    torch.cuda.synchronize()
+    pl_ms = (time.perf_counter() - t0) * 1e3
+    log(f"[bench] gmres({restart}) {prec}: {ms_step:.3f} ms per Arnoldi step; elastic to 1e-6: {it6} steps "
+        f"{el_ms:.1f} ms (relres {rel6:.1e}); strained tangent: CG stops after {itc} (relres {relc:.1e}), "
+        f"GMRES {itp} steps {pl_ms:.1f} ms (relres {relp:.1e})")
+    return {"restart": restart, "step_ms": ms_step, "elastic_steps_to_1e-6": it6, "elastic_relres": rel6,
+            "elastic_solve_ms": el_ms, "strained_cg_iterations": itc, "strained_cg_relres": relc,
+            "strained_steps": itp, "strained_relres": relp, "strained_solve_ms": pl_ms}
 
 
 def tool_protocol(mesh, w, nodes, views, x_dev, perm_buf, leaf_buf, packed, sorted_buf, f_ext, dirichlet, lam):

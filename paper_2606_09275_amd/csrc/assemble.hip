@@ -34,6 +34,7 @@ struct AsmArgs {
   const int32_t* snode;      // rows reached by straddling points
   const int64_t* sinc_off;   // per such row: its straddling points
   const int32_t* sinc;
+  double* grec;              // per straddling point: tangent record of the general path
   int64_t n, n_strad;
   mpm_state_t s;
   const double* u;
@@ -663,18 +664,103 @@ __device__ int general_basis(const AsmArgs& A, int64_t t, const double x[3], con
   return ns;
 }
 
-// Points whose domain overlaps several leaves, gathered by the rows they reach: one wavefront
-// per node a, one lane per straddling point whose support holds a (64 at a time, ascending).
-// Each lane recomputes its point's update from the leaves it overlaps, then the force on a and
-// the row-a blocks: K_ab is linear in grad S_b, so every (leaf, slot) term of the point adds
-// its own block to the column of its slot node (LDS additions into the node's three rows),
-// the block being a fixed 9x3 map of the term's spatial gradient per (point, row).
-// The force is summed over the lanes in a fixed order; rows and forces are then added to the
-// values the fast path wrote. No global atomics. One row per point (that of the first slot of
-// its first leaf) also writes the point's stress, committed state and Newmark kinematics.
+// Points whose domain overlaps several leaves. A first kernel takes one lane per such point:
+// its update from the leaves it overlaps (basis, deformation, material), the point outputs
+// (stress, committed state, Newmark kinematics) and a record of what the rows need, so that
+// the update is computed once per point rather than once per row the point reaches:
+//   [0, 81)    c dtau for the direction e_k (x) N^T e_j, entry (r, m) at (3 j + k) 9 + 3 r + m
+//   [81, 90)   c tau, entry (r, j) at 81 + 3 r + j          (c = V_n / J_n)
+//   [90, 99)   dF^-1, entry (r, k) at 90 + 3 r + k
+//   [99, 102)  m_p a_p (Newmark inertia; zero when quasi-static)
+//   [102]      2 m_p / dt^2 (zero when quasi-static)
 template <typename T>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : 3)))
-void k_general_rows(AsmArgs A) {
+__global__ __launch_bounds__(64) void k_general_points(AsmArgs A) {
+  const int64_t t = int64_t(blockIdx.x) * 64 + threadIdx.x;
+  if (t >= A.n_strad) return;
+  double* rec = A.grec + t * kGenRec;
+  const int64_t n = A.n;
+  const int64_t i = A.strad[t];
+  double x[3], l[3];
+  for (int q = 0; q < 3; ++q) {
+    x[q] = A.s.x[q * n + i];
+    l[q] = A.s.l[q * n + i];
+  }
+  const int32_t* lv = A.strad_leaf + t * kMaxPointLeaves;
+  T H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  double du[3] = {0.0, 0.0, 0.0};
+  for (int q = 0; q < kMaxPointLeaves && lv[q] >= 0; ++q) {
+    T s8[8], d8[8][3];
+    leaf_overlap_basis<T>(A.G, lv[q], A.cell_code[lv[q]], x, l, s8, d8);
+    for (int v = 0; v < 8; ++v) {
+      const double* uv = A.u + 3 * int64_t(A.cell_nodes[8 * int64_t(lv[q]) + v]);
+      for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) H[r][c] += T(uv[r]) * d8[v][c];
+        du[r] += double(s8[v]) * uv[r];
+      }
+    }
+  }
+  int stc = 0;
+  T F[3][3], Fi[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) F[r][c] = H[r][c] + (r == c ? T(1) : T(0));
+  const T Jd = inv3(F, Fi);
+  const double Jn = A.s.Jn[i];
+  PointMat<T> P;
+  if (!isfinite(double(Jd)) || !isfinite(Jn)) stc = MPM_ENONFINITE;
+  else if (!(Jd > T(0))) stc = MPM_EDET;
+  else {
+    T B[3][3];
+    load_B<T>(A.s, n, i, B);
+    stc = material<T>(H, B, A.s.E[i], A.s.nu[i], A.s.sy[i], P);
+  }
+  if (stc) {  // the call fails; the rows read a zero record
+    raise(A.err, stc, i);
+    for (int q = 0; q < kGenRec; ++q) rec[q] = 0.0;
+    return;
+  }
+  write_point<T>(A, i, P, F, double(Jd) * Jn);
+  const T c = T(A.s.vol[i] / Jn);
+  double ma[3] = {0.0, 0.0, 0.0}, c2m = 0.0;
+  if (A.vel) {  // Newmark inertia, gamma = 1, beta = 1/2
+    const double c2 = 2.0 / (A.dt * A.dt), mp = A.s.mass[i];
+    for (int r = 0; r < 3; ++r) {
+      const double vr = A.vel[r * n + i];
+      const double ar = c2 * (du[r] - A.dt * vr);
+      if (A.a_new) A.a_new[r * n + i] = ar;
+      if (A.v_new) A.v_new[r * n + i] = vr + A.dt * ar;
+      ma[r] = mp * ar;
+    }
+    c2m = double(T(2.0 * mp / (A.dt * A.dt)));
+  }
+  for (int j = 0; j < 3; ++j) {
+    const T gt[3] = {P.N[j][0], P.N[j][1], P.N[j][2]};  // N^T e_j
+    for (int k = 0; k < 3; ++k) {
+      T dtk[3][3];
+      dtau_rank1<T>(P, k, gt, T(1), dtk);
+      for (int r = 0; r < 3; ++r)
+        for (int m = 0; m < 3; ++m) rec[(3 * j + k) * 9 + 3 * r + m] = double(c * dtk[r][m]);
+    }
+  }
+  for (int r = 0; r < 3; ++r)
+    for (int j = 0; j < 3; ++j) {
+      rec[81 + 3 * r + j] = double(c * P.tau[r][j]);
+      rec[90 + 3 * r + j] = double(Fi[r][j]);
+    }
+  for (int r = 0; r < 3; ++r) rec[99 + r] = ma[r];
+  rec[102] = c2m;
+  rec[103] = 0.0;
+}
+
+// The rows those points reach: one wavefront per node a, one lane per straddling point whose
+// support holds a (64 at a time, ascending). Each lane evaluates its point's basis over the
+// leaves it overlaps for S_a and grad S_a, adds its force on a, and, K_ab being linear in
+// grad S_b, adds for every (leaf, slot) term of the point its own block to the column of its
+// slot node (LDS additions into the node's three rows); the block is a 9x3 map of the term's
+// spatial gradient, formed from the point's record. The force is summed over the lanes in a
+// fixed order; rows and forces are then added to the values the fast path wrote. No global
+// atomics.
+template <typename T>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3))) void k_general_rows(AsmArgs A) {
   extern __shared__ __align__(16) unsigned char gsm[];
   const int64_t na = A.snode[blockIdx.x];
   const int lane = threadIdx.x;
@@ -693,115 +779,70 @@ void k_general_rows(AsmArgs A) {
   const int64_t c0 = A.sinc_off[blockIdx.x], c1 = A.sinc_off[blockIdx.x + 1];
   for (int64_t cb = c0; cb < c1; cb += 64) {
     const int64_t e = cb + lane;
-    if (e < c1) do {
-        const int64_t t = A.sinc[e];
-        const int64_t i = A.strad[t];
-        double x[3], l[3];
-        for (int q = 0; q < 3; ++q) {
-          x[q] = A.s.x[q * n + i];
-          l[q] = A.s.l[q * n + i];
+    if (e >= c1) continue;
+    const int64_t t = A.sinc[e];
+    const int64_t i = A.strad[t];
+    const double* rec = A.grec + t * kGenRec;
+    double x[3], l[3];
+    for (int q = 0; q < 3; ++q) {
+      x[q] = A.s.x[q * n + i];
+      l[q] = A.s.l[q * n + i];
+    }
+    const int32_t* lv = A.strad_leaf + t * kMaxPointLeaves;
+    T Sa = 0, dSa[3] = {0, 0, 0};
+    for (int q = 0; q < kMaxPointLeaves && lv[q] >= 0; ++q) {
+      T s8[8], d8[8][3];
+      leaf_overlap_basis<T>(A.G, lv[q], A.cell_code[lv[q]], x, l, s8, d8);
+      for (int v = 0; v < 8; ++v)
+        if (A.cell_nodes[8 * int64_t(lv[q]) + v] == na) {
+          Sa += s8[v];
+          for (int k = 0; k < 3; ++k) dSa[k] += d8[v][k];
         }
-        const int32_t* lv = A.strad_leaf + t * kMaxPointLeaves;
-        // pass 1: displacement gradient, and S and grad S of node a
-        T H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-        T Sa = 0, dSa[3] = {0, 0, 0};
-        double du[3] = {0.0, 0.0, 0.0};
-        for (int q = 0; q < kMaxPointLeaves && lv[q] >= 0; ++q) {
-          T s8[8], d8[8][3];
-          leaf_overlap_basis<T>(A.G, lv[q], A.cell_code[lv[q]], x, l, s8, d8);
-          for (int v = 0; v < 8; ++v) {
-            const int32_t id = A.cell_nodes[8 * int64_t(lv[q]) + v];
-            const double* uv = A.u + 3 * int64_t(id);
-            for (int r = 0; r < 3; ++r) {
-              for (int c = 0; c < 3; ++c) H[r][c] += T(uv[r]) * d8[v][c];
-              du[r] += double(s8[v]) * uv[r];
-            }
-            if (id == na) {
-              Sa += s8[v];
-              for (int c = 0; c < 3; ++c) dSa[c] += d8[v][c];
-            }
-          }
-        }
-        T F[3][3], Fi[3][3];
+    }
+    T Fi[3][3];
+    for (int r = 0; r < 3; ++r)
+      for (int k = 0; k < 3; ++k) Fi[r][k] = T(rec[90 + 3 * r + k]);
+    T ga[3];
+    for (int k = 0; k < 3; ++k) ga[k] = Fi[0][k] * dSa[0] + Fi[1][k] * dSa[1] + Fi[2][k] * dSa[2];
+    for (int r = 0; r < 3; ++r)
+      fa[r] += rec[81 + 3 * r] * double(ga[0]) + rec[82 + 3 * r] * double(ga[1]) + rec[83 + 3 * r] * double(ga[2]) +
+               double(Sa) * rec[99 + r];
+    if (!wantK) continue;
+    // block_rk = sum_j Mb[r][k][j] g_j for a term of spatial gradient g
+    T Mb[3][3][3];
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k) {
+        const double* d = rec + (3 * j + k) * 9;
         for (int r = 0; r < 3; ++r)
-          for (int c = 0; c < 3; ++c) F[r][c] = H[r][c] + (r == c ? T(1) : T(0));
-        const T Jd = inv3(F, Fi);
-        const double Jn = A.s.Jn[i];
-        if (!isfinite(double(Jd)) || !isfinite(Jn)) {
-          raise(A.err, MPM_ENONFINITE, i);
-          break;
+          Mb[r][k][j] = T(d[3 * r]) * ga[0] + T(d[3 * r + 1]) * ga[1] + T(d[3 * r + 2]) * ga[2] -
+                        T(rec[81 + 3 * r + j]) * ga[k];
+      }
+    const T c2m = T(rec[102]);
+    for (int q = 0; q < kMaxPointLeaves && lv[q] >= 0; ++q) {
+      T s8[8], d8[8][3];
+      leaf_overlap_basis<T>(A.G, lv[q], A.cell_code[lv[q]], x, l, s8, d8);
+      for (int v = 0; v < 8; ++v) {
+        const int32_t id = A.cell_nodes[8 * int64_t(lv[q]) + v];
+        T gb[3];
+        for (int k = 0; k < 3; ++k) gb[k] = Fi[0][k] * d8[v][0] + Fi[1][k] * d8[v][1] + Fi[2][k] * d8[v][2];
+        int lo = 0, hi = deg;  // block column of node id in row a
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (rcol[mid] < id) lo = mid + 1;
+          else hi = mid;
         }
-        if (!(Jd > T(0))) {
-          raise(A.err, MPM_EDET, i);
-          break;
-        }
-        T B[3][3];
-        load_B<T>(A.s, n, i, B);
-        PointMat<T> P;
-        const int stc = material<T>(H, B, A.s.E[i], A.s.nu[i], A.s.sy[i], P);
-        if (stc) {
-          raise(A.err, stc, i);
-          break;
-        }
-        const bool writer = A.cell_nodes[8 * int64_t(lv[0])] == na;
-        if (writer) write_point<T>(A, i, P, F, double(Jd) * Jn);
-        const T c = T(A.s.vol[i] / Jn);
-        T ga[3];
-        for (int k = 0; k < 3; ++k) ga[k] = Fi[0][k] * dSa[0] + Fi[1][k] * dSa[1] + Fi[2][k] * dSa[2];
-        double acc_p[3] = {0.0, 0.0, 0.0}, mp = 0.0;
-        if (A.vel) {  // Newmark inertia, gamma = 1, beta = 1/2
-          const double c2 = 2.0 / (A.dt * A.dt);
-          mp = A.s.mass[i];
-          for (int r = 0; r < 3; ++r) {
-            const double vr = A.vel[r * n + i];
-            acc_p[r] = c2 * (du[r] - A.dt * vr);
-            if (writer && A.a_new) A.a_new[r * n + i] = acc_p[r];
-            if (writer && A.v_new) A.v_new[r * n + i] = vr + A.dt * acc_p[r];
-          }
+        if (lo >= deg || rcol[lo] != id) {
+          raise(A.err, MPM_ESTENCIL, i);
+          continue;
         }
         for (int r = 0; r < 3; ++r)
-          fa[r] += double(c) * double(P.tau[r][0] * ga[0] + P.tau[r][1] * ga[1] + P.tau[r][2] * ga[2]) +
-                   double(Sa) * mp * acc_p[r];
-        if (!wantK) break;
-        // pass 2: the row-a block of every (leaf, slot) term. The block is linear in the
-        // term's spatial gradient g: block_rk = sum_j Mb[r][k][j] g_j, Mb from g = e_0, e_1, e_2.
-        const T c2m = A.vel ? T(2.0 * mp / (A.dt * A.dt)) : T(0);
-        T Mb[3][3][3];
-        for (int j = 0; j < 3; ++j) {
-          const T gt[3] = {P.N[j][0], P.N[j][1], P.N[j][2]};  // N^T e_j
           for (int k = 0; k < 3; ++k) {
-            T dtk[3][3];
-            dtau_rank1<T>(P, k, gt, T(1), dtk);
-            for (int r = 0; r < 3; ++r)
-              Mb[r][k][j] = c * (dtk[r][0] * ga[0] + dtk[r][1] * ga[1] + dtk[r][2] * ga[2] - P.tau[r][j] * ga[k]);
+            T val = Mb[r][k][0] * gb[0] + Mb[r][k][1] * gb[1] + Mb[r][k][2] * gb[2];
+            if (r == k) val += c2m * Sa * s8[v];
+            atomicAdd(acc + r * 3 * deg + 3 * lo + k, val);
           }
-        }
-        for (int q = 0; q < kMaxPointLeaves && lv[q] >= 0; ++q) {
-          T s8[8], d8[8][3];
-          leaf_overlap_basis<T>(A.G, lv[q], A.cell_code[lv[q]], x, l, s8, d8);
-          for (int v = 0; v < 8; ++v) {
-            const int32_t id = A.cell_nodes[8 * int64_t(lv[q]) + v];
-            T gb[3];
-            for (int k = 0; k < 3; ++k) gb[k] = Fi[0][k] * d8[v][0] + Fi[1][k] * d8[v][1] + Fi[2][k] * d8[v][2];
-            int lo = 0, hi = deg;  // block column of node id in row a
-            while (lo < hi) {
-              const int mid = (lo + hi) >> 1;
-              if (rcol[mid] < id) lo = mid + 1;
-              else hi = mid;
-            }
-            if (lo >= deg || rcol[lo] != id) {
-              raise(A.err, MPM_ESTENCIL, i);
-              continue;
-            }
-            for (int r = 0; r < 3; ++r)
-              for (int k = 0; k < 3; ++k) {
-                T val = Mb[r][k][0] * gb[0] + Mb[r][k][1] * gb[1] + Mb[r][k][2] * gb[2];
-                if (A.vel && r == k) val += c2m * Sa * s8[v];
-                atomicAdd(acc + r * 3 * deg + 3 * lo + k, val);
-              }
-          }
-        }
-      } while (false);
+      }
+    }
   }
   // forces of the lanes' points in lane order, then the rows
 #pragma unroll
@@ -1049,6 +1090,7 @@ static AsmArgs make_args(const mpm_mesh* m, const mpm_state_t* s) {
   A.snode = m->d_snode;
   A.sinc_off = m->d_sinc_off;
   A.sinc = m->d_sinc;
+  A.grec = m->d_grec;
   A.n = m->n_point;
   A.n_strad = m->n_straddle;
   A.s = *s;
@@ -1162,6 +1204,9 @@ static int32_t assemble_impl(const mpm_mesh_t* m, const AsmArgs& A, int32_t prec
   else launch_gather<float>(m, st, A);
   if (timed) MPM_HIP(hipEventRecord(mm->ev[4], st));
   if (m->n_snode) {  // rows reached by points whose domain overlaps several leaves
+    const dim3 pgrid(unsigned((m->n_straddle + 63) / 64));
+    if (precision == MPM_F64) hipLaunchKernelGGL(k_general_points<double>, pgrid, dim3(64), 0, st, A);
+    else hipLaunchKernelGGL(k_general_points<float>, pgrid, dim3(64), 0, st, A);
     const dim3 grid(unsigned(m->n_snode));
     if (precision == MPM_F64)
       hipLaunchKernelGGL(k_general_rows<double>, grid, dim3(64), size_t(9 * 8 + 4) * m->max_deg, st, A);

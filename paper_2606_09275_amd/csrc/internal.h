@@ -53,6 +53,7 @@ __host__ __device__ inline uint64_t compact3(uint64_t v) {
 }
 
 constexpr int kMaxPointLeaves = 8; // leaves a point domain may overlap (one boundary per axis)
+constexpr int kGenRec = 104;       // doubles per straddling point: the general path's tangent record
 
 // per-leaf constraint code: bits 0..7 hanging vertices, bits 8..10 child index in the parent
 __host__ __device__ inline int code_hmask(int32_t code) { return code & 0xff; }
@@ -109,6 +110,7 @@ struct mpm_mesh {
   int32_t* d_red2 = nullptr;        // n_red2 x 3: chunk records of a heavy leaf
   int64_t* d_strad = nullptr;       // n_straddle sorted positions
   int32_t* d_strad_leaf = nullptr;  // n_straddle x 8 overlapped leaves (-1 pad)
+  double* d_grec = nullptr;         // n_straddle x kGenRec: per-point tangent records of the general path
   // rows that straddling points reach: the nodes in their supports and, per node, the
   // straddling points (indices into d_strad) whose support holds it, in ascending order
   int64_t n_snode = 0;

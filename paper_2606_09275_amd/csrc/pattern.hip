@@ -342,6 +342,7 @@ int32_t gpu_build_pattern(mpm_mesh* m, const double* dx, const double* dl, hipSt
     if (m->n_straddle) {
       MPM_HIP(hipMalloc(&m->d_strad, size_t(m->n_straddle) * 8));
       MPM_HIP(hipMalloc(&m->d_strad_leaf, size_t(m->n_straddle) * kMaxPointLeaves * 4));
+      MPM_HIP(hipMalloc(&m->d_grec, size_t(m->n_straddle) * kGenRec * 8));
       hipLaunchKernelGGL(k_compact_index, grid_of(n), dim3(256), 0, st, cnt.as<int32_t>(), off.as<int64_t>(), n,
                          m->d_strad);
       if ((rc = strad_leaves(m, dx, dl, st))) return rc;

@@ -756,9 +756,19 @@ __global__ __launch_bounds__(64) void k_general_points(AsmArgs A) {
 // leaves it overlaps for S_a and grad S_a, adds its force on a, and, K_ab being linear in
 // grad S_b, adds for every (leaf, slot) term of the point its own block to the column of its
 // slot node (LDS additions into the node's three rows); the block is a 9x3 map of the term's
-// spatial gradient, formed from the point's record. The force is summed over the lanes in a
-// fixed order; rows and forces are then added to the values the fast path wrote. No global
-// atomics.
+// spatial gradient, formed from the point's record. The column of a node in row a comes from
+// an open-addressing table of the row's columns in LDS (at least half of it empty, so a probe
+// sequence always ends). Each lane starts its walk over the leaves at its own offset, so that
+// lanes whose points overlap the same leaves do not add into the same columns at once. The
+// force is summed over the lanes in a fixed order; rows and forces are then added to the
+// values the fast path wrote. No global atomics.
+__host__ __device__ constexpr int col_table_size(int deg) {
+  int p = 2;
+  while (p < 2 * deg) p <<= 1;
+  return p;
+}
+__device__ __forceinline__ unsigned col_hash(int32_t id, int p) { return (unsigned(id) * 2654435761u) & unsigned(p - 1); }
+
 template <typename T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3))) void k_general_rows(AsmArgs A) {
   extern __shared__ __align__(16) unsigned char gsm[];
@@ -766,12 +776,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   const int lane = threadIdx.x;
   const int64_t r0 = A.row_ptr[3 * na];
   const int deg = int((A.row_ptr[3 * na + 1] - r0) / 3);
-  T* acc = reinterpret_cast<T*>(gsm);
-  int32_t* rcol = reinterpret_cast<int32_t*>(acc + 9 * deg);  // block-column nodes of the row
+  const int tp = col_table_size(deg);
+  // table entries: node id (high 32 bits) and column (low 32 bits); empty = all ones
+  unsigned long long* ctab = reinterpret_cast<unsigned long long*>(gsm);
+  T* acc = reinterpret_cast<T*>(ctab + tp);
   const bool wantK = A.K != nullptr;
   if (wantK) {
     for (int j = lane; j < 9 * deg; j += 64) acc[j] = T(0);
-    for (int j = lane; j < deg; j += 64) rcol[j] = A.col[r0 + 3 * j] / 3;
+    for (int j = lane; j < tp; j += 64) ctab[j] = ~0ull;
+  }
+  __syncthreads();
+  if (wantK) {
+    for (int j = lane; j < deg; j += 64) {
+      const int32_t id = A.col[r0 + 3 * j] / 3;
+      const unsigned long long ent = (static_cast<unsigned long long>(unsigned(id)) << 32) | unsigned(j);
+      for (unsigned h = col_hash(id, tp);; h = (h + 1) & unsigned(tp - 1))
+        if (atomicCAS(ctab + h, ~0ull, ent) == ~0ull) break;
+    }
   }
   __syncthreads();
   const int64_t n = A.n;
@@ -818,20 +839,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
                         T(rec[81 + 3 * r + j]) * ga[k];
       }
     const T c2m = T(rec[102]);
-    for (int q = 0; q < kMaxPointLeaves && lv[q] >= 0; ++q) {
+    int nl = 0;
+    while (nl < kMaxPointLeaves && lv[nl] >= 0) ++nl;
+    for (int qq = 0; qq < nl; ++qq) {
+      const int q = (qq + lane) % nl;
       T s8[8], d8[8][3];
       leaf_overlap_basis<T>(A.G, lv[q], A.cell_code[lv[q]], x, l, s8, d8);
       for (int v = 0; v < 8; ++v) {
         const int32_t id = A.cell_nodes[8 * int64_t(lv[q]) + v];
         T gb[3];
         for (int k = 0; k < 3; ++k) gb[k] = Fi[0][k] * d8[v][0] + Fi[1][k] * d8[v][1] + Fi[2][k] * d8[v][2];
-        int lo = 0, hi = deg;  // block column of node id in row a
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (rcol[mid] < id) lo = mid + 1;
-          else hi = mid;
+        int lo = -1;  // block column of node id in row a
+        for (unsigned h = col_hash(id, tp);; h = (h + 1) & unsigned(tp - 1)) {
+          const unsigned long long e = ctab[h];
+          if (e == ~0ull) break;
+          if (int32_t(e >> 32) == id) {
+            lo = int(unsigned(e));
+            break;
+          }
         }
-        if (lo >= deg || rcol[lo] != id) {
+        if (lo < 0) {
           raise(A.err, MPM_ESTENCIL, i);
           continue;
         }
@@ -1208,10 +1235,11 @@ static int32_t assemble_impl(const mpm_mesh_t* m, const AsmArgs& A, int32_t prec
     if (precision == MPM_F64) hipLaunchKernelGGL(k_general_points<double>, pgrid, dim3(64), 0, st, A);
     else hipLaunchKernelGGL(k_general_points<float>, pgrid, dim3(64), 0, st, A);
     const dim3 grid(unsigned(m->n_snode));
+    const size_t tab = size_t(8) * col_table_size(int(m->max_deg));  // column table of the longest row
     if (precision == MPM_F64)
-      hipLaunchKernelGGL(k_general_rows<double>, grid, dim3(64), size_t(9 * 8 + 4) * m->max_deg, st, A);
+      hipLaunchKernelGGL(k_general_rows<double>, grid, dim3(64), tab + size_t(9 * 8) * m->max_deg, st, A);
     else
-      hipLaunchKernelGGL(k_general_rows<float>, grid, dim3(64), size_t(9 * 4 + 4) * m->max_deg, st, A);
+      hipLaunchKernelGGL(k_general_rows<float>, grid, dim3(64), tab + size_t(9 * 4) * m->max_deg, st, A);
   }
   // ghost penalty (Section 4): after every point term, before the residual
   if (const int32_t rg = ghost_apply(m, &A.s, A.u, precision, K_vals, f_int, st)) return rg;

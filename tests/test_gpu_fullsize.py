@@ -7,8 +7,10 @@ whose support holds those nodes, sigma of sampled points, and the adjoint gradie
 seeded points (against the oracle and central differences); over the whole vectors, the
 internal forces balance and the body forces sum to the total weight. The ghost stabilisation
 at full size: faces and pattern bit-exact, its stiffness and force against the oracle's. The
-Newmark inertia on sampled rows, and the CG solve of the full elastic tangent by its true
-residual."""
+Newmark inertia on sampled rows, and the CG and GMRES solves of the full elastic tangent by
+their true residuals. The jittered cone-penetration workload (4.1M of 5.75M domains over
+several leaves, the general path): sampled rows and the stress of every point of the oracle's
+subset."""
 import math
 
 import numpy as np
@@ -251,6 +253,91 @@ def test_c2_cg_solves_the_full_system(c2):
     log(f"[parity] c2 full CG: {it} iterations, recursive {rel:.2e}, true residual {true_rel:.2e}")
     assert rel <= 1e-6 and true_rel <= 2e-6
     assert np.all(xn[~free] == 0.0)
+
+
+def test_c2_gmres_solves_the_full_system(c2):
+    """Restarted GMRES on the same full elastic tangent: true relative residual at the requested
+    tolerance on the free DOFs (CPU product of the same CSR values), zero on the Dirichlet DOFs."""
+    from oracle.solve import csr, free_dofs
+    m = c2["m"]
+    s = dict(c2["s_dev"])
+    bn0 = torch.zeros_like(s["bn"])
+    bn0[:3] = 1.0
+    s.update(sy=torch.full_like(s["sy"], float("inf")), bn=bn0, Jn=torch.ones_like(s["Jn"]))
+    d = torch.from_numpy(W.dirichlet_dofs(c2["nodes"])).cuda()
+    fe = m.external_force(s)
+    u0 = torch.zeros(m.info["n_dof"], dtype=torch.float64, device="cuda")
+    out = m.assemble(s, u0, "f64", f_ext=fe, dirichlet=d, want_sigma=False)
+    b = -out["r"]
+    x, it, rel = m.solve_gmres(out["K"], b, d, rtol=1e-6, restart=30, max_iter=4000)
+    torch.cuda.synchronize()
+    a = m.arrays()
+    A = csr(to_np(a["row_ptr"]), to_np(a["col"]), to_np(out["K"]), m.info["n_dof"])
+    xn, bn = to_np(x), to_np(b)
+    free = free_dofs(A, to_np(d))
+    true_rel = np.linalg.norm((bn - A @ xn)[free]) / np.linalg.norm(bn[free])
+    log(f"[parity] c2 full GMRES(30): {it} steps, reported {rel:.2e}, true residual {true_rel:.2e}")
+    assert rel <= 1e-6 and abs(true_rel - rel) <= 1e-3 * rel
+    assert np.all(xn[~free] == 0.0)
+
+
+def test_c2_jittered_sampled_rows_and_stress():
+    """General path at full size: rows of 40 sampled nodes and the stress of every point of the
+    subset, against an oracle run over every point whose domain comes within twice the largest
+    leaf touching a sampled node (a superset, chosen from the oracle's geometry, of the points
+    whose support holds those nodes); the internal forces balance."""
+    from paper_2606_09275_amd.mesh import Mesh
+    w = W.get("c2")
+    o = OracleMesh(w.crit())
+    lv = o.leaves()
+    nodes = o.nodes()
+    ps = W.jitter_points(w, W.make_points(w, lv[:, :3], lv[:, 3]), 0)
+    st = W.make_state(w, ps)
+    u = W.make_u(w, nodes)
+    m = Mesh(w.crit(), torch.from_numpy(ps.x).cuda(), torch.from_numpy(ps.l).cuda())
+    assert np.array_equal(to_np(m.arrays()["node_ijk"]), nodes)
+    log(f"[setup] c2 jittered: {ps.n} points, {m.info['n_straddle']} over several leaves")
+    s_dev = m.sorted_state(st)
+    size = (1 << (w.lvl_max - lv[:, 3].astype(np.int64)))[:, None]
+    lo, hmin = np.asarray(w.lo, np.float64), w.h_min
+    pick = np.random.default_rng(13).choice(nodes.shape[0], 40, replace=False)
+    sel = np.zeros(ps.n, dtype=bool)
+    for nd in pick:
+        X = nodes[nd].astype(np.int64)
+        touch = np.all((lv[:, :3] <= X) & (X <= lv[:, :3] + size), axis=1)
+        hc = float(size[touch].max()) * hmin
+        c = lo + X * hmin
+        sel |= np.all(np.abs(ps.x - c[:, None]) <= ps.l + 2.0 * hc, axis=0)
+    idx = np.nonzero(sel)[0]
+    sub = OracleMesh(w.crit())
+    sub.set_points(ps.x[:, idx], ps.l[:, idx])
+    ss = {k: (v[..., idx] if isinstance(v, np.ndarray) else v) for k, v in st.items()}
+    ref = sub.assemble(ss, u)
+    srp, scol = sub.csr()
+    a = m.arrays()
+    rp, col = to_np(a["row_ptr"]), to_np(a["col"])
+    perm = to_np(a["perm"])
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(perm.size)
+    for prec, tol in (("f64", TOL64), ("f32k", 2e-5)):
+        out = m.assemble(s_dev, torch.from_numpy(u).cuda(), prec)
+        torch.cuda.synchronize()
+        f = to_np(out["f_int"])
+        K = to_np(out["K"]).astype(np.float64)
+        assert np.abs(f.reshape(-1, 3).sum(axis=0)).max() < (1e-10 if prec == "f64" else 1e-6) * np.abs(f).sum()
+        ef = ek = 0.0
+        fscale = np.abs(f).max()
+        for nd in pick:
+            ef = max(ef, np.abs(f[3 * nd:3 * nd + 3] - ref["f_int"][3 * nd:3 * nd + 3]).max() / fscale)
+            for r in range(3):
+                row = 3 * nd + r
+                a0, a1, b0, b1 = rp[row], rp[row + 1], srp[row], srp[row + 1]
+                assert np.array_equal(col[a0:a1], scol[b0:b1])
+                if b1 > b0:
+                    ek = max(ek, np.abs(K[a0:a1] - ref["K"][b0:b1]).max() / np.abs(ref["K"][b0:b1]).max())
+        es = rel_err(to_np(out["sigma"])[:, inv[idx]], ref["sigma"])
+        log(f"[parity] c2 jittered {prec}: sampled f={ef:.2e} K rows={ek:.2e} sigma={es:.2e} ({idx.size} points)")
+        assert ef <= tol and ek <= tol and es <= tol
 
 
 def test_c2_body_force_total(c2):

@@ -779,10 +779,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   const int tp = col_table_size(deg);
   // table entries: node id (high 32 bits) and column (low 32 bits); empty = all ones
   unsigned long long* ctab = reinterpret_cast<unsigned long long*>(gsm);
-  T* acc = reinterpret_cast<T*>(ctab + tp);
+  double* acc = reinterpret_cast<double*>(ctab + tp);  // the row in FP64 for both precisions
   const bool wantK = A.K != nullptr;
   if (wantK) {
-    for (int j = lane; j < 9 * deg; j += 64) acc[j] = T(0);
+    for (int j = lane; j < 9 * deg; j += 64) acc[j] = 0.0;
     for (int j = lane; j < tp; j += 64) ctab[j] = ~0ull;
   }
   __syncthreads();
@@ -866,7 +866,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
           for (int k = 0; k < 3; ++k) {
             T val = Mb[r][k][0] * gb[0] + Mb[r][k][1] * gb[1] + Mb[r][k][2] * gb[2];
             if (r == k) val += c2m * Sa * s8[v];
-            atomicAdd(acc + r * 3 * deg + 3 * lo + k, val);
+            atomicAdd(acc + r * 3 * deg + 3 * lo + k, double(val));
           }
       }
     }
@@ -880,7 +880,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
   if (wantK) {
     T* Kout = reinterpret_cast<T*>(A.K);
     for (int j = lane; j < 9 * deg; j += 64)
-      if (acc[j] != T(0)) Kout[r0 + j] += acc[j];
+      if (acc[j] != 0.0) Kout[r0 + j] += T(acc[j]);
   }
 }
 
@@ -1239,7 +1239,7 @@ static int32_t assemble_impl(const mpm_mesh_t* m, const AsmArgs& A, int32_t prec
     if (precision == MPM_F64)
       hipLaunchKernelGGL(k_general_rows<double>, grid, dim3(64), tab + size_t(9 * 8) * m->max_deg, st, A);
     else
-      hipLaunchKernelGGL(k_general_rows<float>, grid, dim3(64), tab + size_t(9 * 4) * m->max_deg, st, A);
+      hipLaunchKernelGGL(k_general_rows<float>, grid, dim3(64), tab + size_t(9 * 8) * m->max_deg, st, A);
   }
   // ghost penalty (Section 4): after every point term, before the residual
   if (const int32_t rg = ghost_apply(m, &A.s, A.u, precision, K_vals, f_int, st)) return rg;

@@ -398,21 +398,17 @@ __global__ __launch_bounds__(256) void k_gm_begin(const double* __restrict__ par
   }
 }
 
-// dst = hinv src (v0 in place, or v_{j+1} = w / h_{j+1,j})
-__global__ __launch_bounds__(256) void k_gm_scale(const double* __restrict__ src, double* __restrict__ dst,
-                                                  int64_t ndof, const GmState* s) {
+// dst = hinv src (v0 in place, or v_{j+1} = w / h_{j+1,j}) and z = M^-1 dst, the vector the
+// next Arnoldi step multiplies by K
+__global__ __launch_bounds__(256) void k_gm_scale(const double* src, double* dst, const double* __restrict__ dinv,
+                                                  double* __restrict__ z, int64_t ndof, const GmState* s) {
   if (s->skip) return;
   const double h = s->hinv;
-  for (int64_t d = int64_t(blockIdx.x) * 256 + threadIdx.x; d < ndof; d += int64_t(gridDim.x) * 256)
-    dst[d] = h * src[d];
-}
-
-// z = M^-1 v
-__global__ __launch_bounds__(256) void k_gm_precond(const double* __restrict__ v, const double* __restrict__ dinv,
-                                                    double* __restrict__ z, int64_t ndof, const GmState* s) {
-  if (s->skip) return;
-  for (int64_t d = int64_t(blockIdx.x) * 256 + threadIdx.x; d < ndof; d += int64_t(gridDim.x) * 256)
-    z[d] = dinv[d] * v[d];
+  for (int64_t d = int64_t(blockIdx.x) * 256 + threadIdx.x; d < ndof; d += int64_t(gridDim.x) * 256) {
+    const double v = h * src[d];
+    dst[d] = v;
+    z[d] = dinv[d] * v;
+  }
 }
 
 // partial sums of v_i . w, i = blockIdx.y (0..j), in a fixed order
@@ -587,7 +583,7 @@ static int32_t solve_gmres(mpm_mesh* m, const void* K, const uint8_t* dir, const
     launch_spmv<T>(m, K, x, B.w, B.fr, &S->stop, st);
     hipLaunchKernelGGL(k_gm_resid, dim3(gv), dim3(256), 0, st, b, B.w, B.fr, B.V, nd, B.part, S);
     hipLaunchKernelGGL(k_gm_begin, dim3(1), dim3(256), 0, st, B.part, int(gv), S, rtol, max_iter, first);
-    hipLaunchKernelGGL(k_gm_scale, dim3(gv), dim3(256), 0, st, B.V, B.V, nd, S);
+    hipLaunchKernelGGL(k_gm_scale, dim3(gv), dim3(256), 0, st, B.V, B.V, B.dinv, B.z, nd, S);
   };
   begin(1);
   if (!m->h_cg) MPM_HIP(hipHostMalloc((void**)&m->h_cg, sizeof(CgFlags) + 8 * kNumScalars, hipHostMallocDefault));
@@ -603,9 +599,7 @@ static int32_t solve_gmres(mpm_mesh* m, const void* K, const uint8_t* dir, const
     if (q != hipSuccess) return hip_fail(q, "mpm_solve_gmres");
     if (static_cast<const GmState*>(m->h_cg)->stop) break;
     for (int j = 0; j < restart; ++j) {
-      const double* vj = B.V + int64_t(j) * B.vs;
-      hipLaunchKernelGGL(k_gm_precond, dim3(gv), dim3(256), 0, st, vj, B.dinv, B.z, nd, S);
-      launch_spmv<T>(m, K, B.z, B.w, B.fr, &S->skip, st);
+      launch_spmv<T>(m, K, B.z, B.w, B.fr, &S->skip, st);  // z = M^-1 v_j, left by the previous scale
       for (int pass = 0; pass < 2; ++pass) {
         hipLaunchKernelGGL(k_gm_dots, dim3(unsigned(nb), unsigned(j + 1)), dim3(256), 0, st, B.V, B.vs, B.w, nd,
                            B.part, S);
@@ -613,7 +607,8 @@ static int32_t solve_gmres(mpm_mesh* m, const void* K, const uint8_t* dir, const
         hipLaunchKernelGGL(k_gm_orth, dim3(gv), dim3(256), 0, st, B.V, B.vs, B.w, nd, j, B.part, pass, S);
       }
       hipLaunchKernelGGL(k_gm_rotate, dim3(1), dim3(256), 0, st, B.part, int(gv), S, j, rtol, max_iter);
-      hipLaunchKernelGGL(k_gm_scale, dim3(gv), dim3(256), 0, st, B.w, B.V + int64_t(j + 1) * B.vs, nd, S);
+      hipLaunchKernelGGL(k_gm_scale, dim3(gv), dim3(256), 0, st, B.w, B.V + int64_t(j + 1) * B.vs, B.dinv, B.z,
+                         nd, S);
     }
     hipLaunchKernelGGL(k_gm_solve, dim3(1), dim3(1), 0, st, S);
     hipLaunchKernelGGL(k_gm_xupd, dim3(gv), dim3(256), 0, st, B.V, B.vs, B.dinv, x, nd, S);

@@ -151,7 +151,7 @@ typedef struct {
  * Every construction step runs on the device (refinement, balance, numbering, constraints,
  * point order, overlap classification, CSR pattern, ghost faces); the host only reads counts
  * between the steps and keeps the ghost face records. Besides the pattern and the segment
- * records, the mesh keeps 832 bytes of device memory per point whose domain overlaps several
+ * records, the mesh keeps 592 bytes of device memory per point whose domain overlaps several
  * leaves (that point's tangent record, rewritten by every assembly). */
 int32_t octree_build(const mpm_refine_t* crit, const double* x, const double* l, int64_t n, void* stream,
                      mpm_mesh_t** out_mesh);

@@ -668,11 +668,13 @@ __device__ int general_basis(const AsmArgs& A, int64_t t, const double x[3], con
 // its update from the leaves it overlaps (basis, deformation, material), the point outputs
 // (stress, committed state, Newmark kinematics) and a record of what the rows need, so that
 // the update is computed once per point rather than once per row the point reaches:
-//   [0, 81)    c dtau for the direction e_k (x) N^T e_j, entry (r, m) at (3 j + k) 9 + 3 r + m
-//   [81, 90)   c tau, entry (r, j) at 81 + 3 r + j          (c = V_n / J_n)
-//   [90, 99)   dF^-1, entry (r, k) at 90 + 3 r + k
-//   [99, 102)  m_p a_p (Newmark inertia; zero when quasi-static)
-//   [102]      2 m_p / dt^2 (zero when quasi-static)
+// (symmetric 3x3 matrices as 6 values in the order xx, yy, zz, xy, yz, xz)
+//   [0, 54)    c dtau for the direction e_k (x) N^T e_j, symmetric, at (3 j + k) 6
+//   [54, 60)   c tau, symmetric                              (c = V_n / J_n)
+//   [60, 69)   dF^-1, entry (r, k) at 60 + 3 r + k
+//   [69, 72)   m_p a_p (Newmark inertia; zero when quasi-static)
+//   [72]       2 m_p / dt^2 (zero when quasi-static)
+__device__ constexpr int kSym6[3][3] = {{0, 3, 5}, {3, 1, 4}, {5, 4, 2}};
 template <typename T>
 __global__ __launch_bounds__(64) void k_general_points(AsmArgs A) {
   const int64_t t = int64_t(blockIdx.x) * 64 + threadIdx.x;
@@ -738,17 +740,17 @@ __global__ __launch_bounds__(64) void k_general_points(AsmArgs A) {
       T dtk[3][3];
       dtau_rank1<T>(P, k, gt, T(1), dtk);
       for (int r = 0; r < 3; ++r)
-        for (int m = 0; m < 3; ++m) rec[(3 * j + k) * 9 + 3 * r + m] = double(c * dtk[r][m]);
+        for (int m = r; m < 3; ++m) rec[(3 * j + k) * 6 + kSym6[r][m]] = double(c * dtk[r][m]);
     }
   }
   for (int r = 0; r < 3; ++r)
     for (int j = 0; j < 3; ++j) {
-      rec[81 + 3 * r + j] = double(c * P.tau[r][j]);
-      rec[90 + 3 * r + j] = double(Fi[r][j]);
+      if (j >= r) rec[54 + kSym6[r][j]] = double(c * P.tau[r][j]);
+      rec[60 + 3 * r + j] = double(Fi[r][j]);
     }
-  for (int r = 0; r < 3; ++r) rec[99 + r] = ma[r];
-  rec[102] = c2m;
-  rec[103] = 0.0;
+  for (int r = 0; r < 3; ++r) rec[69 + r] = ma[r];
+  rec[72] = c2m;
+  rec[73] = 0.0;
 }
 
 // The rows those points reach: one wavefront per node a, one lane per straddling point whose
@@ -822,23 +824,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     }
     T Fi[3][3];
     for (int r = 0; r < 3; ++r)
-      for (int k = 0; k < 3; ++k) Fi[r][k] = T(rec[90 + 3 * r + k]);
+      for (int k = 0; k < 3; ++k) Fi[r][k] = T(rec[60 + 3 * r + k]);
     T ga[3];
     for (int k = 0; k < 3; ++k) ga[k] = Fi[0][k] * dSa[0] + Fi[1][k] * dSa[1] + Fi[2][k] * dSa[2];
     for (int r = 0; r < 3; ++r)
-      fa[r] += rec[81 + 3 * r] * double(ga[0]) + rec[82 + 3 * r] * double(ga[1]) + rec[83 + 3 * r] * double(ga[2]) +
-               double(Sa) * rec[99 + r];
+      fa[r] += rec[54 + kSym6[r][0]] * double(ga[0]) + rec[54 + kSym6[r][1]] * double(ga[1]) +
+               rec[54 + kSym6[r][2]] * double(ga[2]) + double(Sa) * rec[69 + r];
     if (!wantK) continue;
     // block_rk = sum_j Mb[r][k][j] g_j for a term of spatial gradient g
     T Mb[3][3][3];
     for (int j = 0; j < 3; ++j)
       for (int k = 0; k < 3; ++k) {
-        const double* d = rec + (3 * j + k) * 9;
+        const double* d = rec + (3 * j + k) * 6;
         for (int r = 0; r < 3; ++r)
-          Mb[r][k][j] = T(d[3 * r]) * ga[0] + T(d[3 * r + 1]) * ga[1] + T(d[3 * r + 2]) * ga[2] -
-                        T(rec[81 + 3 * r + j]) * ga[k];
+          Mb[r][k][j] = T(d[kSym6[r][0]]) * ga[0] + T(d[kSym6[r][1]]) * ga[1] + T(d[kSym6[r][2]]) * ga[2] -
+                        T(rec[54 + kSym6[r][j]]) * ga[k];
       }
-    const T c2m = T(rec[102]);
+    const T c2m = T(rec[72]);
     int nl = 0;
     while (nl < kMaxPointLeaves && lv[nl] >= 0) ++nl;
     for (int qq = 0; qq < nl; ++qq) {

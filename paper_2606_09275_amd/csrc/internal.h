@@ -53,7 +53,7 @@ __host__ __device__ inline uint64_t compact3(uint64_t v) {
 }
 
 constexpr int kMaxPointLeaves = 8; // leaves a point domain may overlap (one boundary per axis)
-constexpr int kGenRec = 104;       // doubles per straddling point: the general path's tangent record
+constexpr int kGenRec = 74;        // doubles per straddling point: the general path's tangent record
 
 // per-leaf constraint code: bits 0..7 hanging vertices, bits 8..10 child index in the parent
 __host__ __device__ inline int code_hmask(int32_t code) { return code & 0xff; }

@@ -170,6 +170,27 @@ def test_gmres_edges():
             m.solve_gmres(K, _cuda(b), d, restart=bad)
 
 
+def test_gmres_invariant_space_one_step():
+    """Only the diagonal entries of the pattern set (seeded positive values): K M^-1 = I on the
+    free DOFs, the first Arnoldi vector spans an invariant space (the new column vanishes up to
+    rounding) and GMRES ends after one step with x = b / diag, as the oracle does."""
+    m, K, A, b, dn = _system("sphere", None, math.inf, "f64", values="random")
+    n = A.shape[0]
+    rows = np.repeat(np.arange(n), np.diff(A.indptr))
+    kv = np.zeros(A.indices.size)
+    diag = A.indices == rows
+    kv[diag] = np.random.default_rng(21).uniform(1.0, 3.0, size=int(diag.sum()))
+    Ad = csr(A.indptr, A.indices, kv, n)
+    x, it, rel = m.solve_gmres(_cuda(kv), _cuda(b), _cuda(dn), rtol=1e-14, restart=30, max_iter=100)
+    torch.cuda.synchronize()
+    xc, itc, relc = jacobi_gmres(Ad, b, dn, rtol=1e-14, restart=30, max_iter=100)
+    f = free_dofs(Ad, dn)
+    xd = np.where(f, b / np.where(f, Ad.diagonal(), 1.0), 0.0)
+    e = rel_err(to_np(x), xd)
+    log(f"[parity] gmres diagonal: steps {it} (cpu {itc}), relres {rel:.2e}, x vs b/diag {e:.2e}")
+    assert it == itc == 1 and rel <= 1e-15 and e <= 1e-15
+
+
 def test_spmv_full_size_cone_tangent():
     """SpMV at the full size of the cone-penetration workload (54.4M values): seeded normal
     values on the oracle's CSR pattern of that mesh and its points, against the CPU product."""

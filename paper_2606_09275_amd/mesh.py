@@ -18,6 +18,48 @@ STATE_KEYS = ("x", "l", "vol", "mass", "Jn", "bn", "Fn", "E", "nu", "sy")
 _D2D = 3
 
 
+# number of components of each per-point state field ([c][n] SoA, float64)
+STATE_COMPONENTS = {"x": 3, "l": 3, "vol": 1, "mass": 1, "Jn": 1, "bn": 6, "Fn": 9, "E": 1, "nu": 1, "sy": 1}
+
+
+def _validate(specs):
+    """Reject tensors the library would misread, before anything is launched: the kernels
+    take raw pointers and trust the sizes the mesh implies, so a float32 tensor read as
+    float64, or a short one, would be read past its end. specs: (tensor or None, name,
+    element count or None, allowed dtypes). Every dtype and size is checked before any layout
+    or device, so that the first two checks also hold for host tensors."""
+    specs = [sp for sp in specs if sp[0] is not None]
+    for t, name, numel, dtypes in specs:
+        if not isinstance(t, torch.Tensor):
+            raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+        if t.dtype not in dtypes:
+            raise ValueError(f"{name}: expected dtype {' or '.join(str(d) for d in dtypes)}, got {t.dtype}")
+        if numel is not None and t.numel() != numel:
+            raise ValueError(f"{name}: expected {numel} elements, got {t.numel()}")
+    for t, name, _, _ in specs:
+        if not t.is_contiguous():
+            raise ValueError(f"{name}: expected a contiguous tensor")
+    for t, name, _, _ in specs:
+        if not t.is_cuda:
+            raise ValueError(f"{name}: expected a device tensor")
+
+
+F64 = (torch.float64,)
+
+
+def _check(t, name: str, numel: Optional[int] = None, dtypes=F64):
+    _validate([(t, name, numel, dtypes)])
+
+
+def state_specs(s: dict, n: int):
+    return [(s.get(k), f"state[{k!r}]", c * n, F64) for k, c in STATE_COMPONENTS.items()]
+
+
+def check_state(s: dict, n: int):
+    """Validate the per-point fields present in s for n points (float64, [c][n] or [n])."""
+    _validate(state_specs(s, n))
+
+
 def _ptr(t: Optional[torch.Tensor]):
     if t is None:
         return None
@@ -126,14 +168,24 @@ class Mesh:
         flat = src.dim() == 1
         s = src.reshape(1, -1) if flat else src
         s = s.contiguous().to(torch.float64)
+        n = int(s.shape[1])
+        if perm is None and n != self.info["n_point"]:
+            raise ValueError(f"permute: expected {self.info['n_point']} points per component, got {n}")
+        _check(perm, "perm", n, (torch.int64,))
+        _check(s, "src", s.numel())
+        if out is not None:
+            _check(out, "out", s.numel())
         o = torch.empty_like(s) if out is None else out.reshape(s.shape)
         check(lib().mpm_permute(self.h, _ptr(perm), _ptr(s), _ptr(o), int(s.shape[0]), _stream()))
         return o.reshape(-1) if flat else o
 
     def point_sort(self, x: torch.Tensor, perm_out=None, leaf_out=None):
         n = int(x.shape[1])
+        _check(x.contiguous(), "x", 3 * n)
         perm_out = torch.empty(n, dtype=torch.int64, device="cuda") if perm_out is None else perm_out
         leaf_out = torch.empty(n, dtype=torch.int32, device="cuda") if leaf_out is None else leaf_out
+        _check(perm_out, "perm_out", n, (torch.int64,))
+        _check(leaf_out, "leaf_out", n, (torch.int32,))
         check(lib().mpm_point_sort(self.h, _ptr(x.contiguous()), n, _ptr(perm_out), _ptr(leaf_out), _stream()))
         return perm_out, leaf_out
 
@@ -158,7 +210,9 @@ class Mesh:
 
     # -------------------------------------------------------------- compute
     @staticmethod
-    def _state(s: dict) -> _lib.StateT:
+    def _state(s: dict, n: Optional[int] = None) -> _lib.StateT:
+        if n is not None:
+            check_state(s, n)
         st = _lib.StateT()
         for k in STATE_KEYS:
             t = s.get(k)
@@ -166,11 +220,29 @@ class Mesh:
         st.g = (C.c_double * 3)(*s.get("g", (0.0, 0.0, -9.81)))
         return st
 
+    def _K_spec(self, K):
+        return (K, "K", self.info["nnz"], (torch.float64, torch.float32))
+
+    def _check_io(self, s: dict, u, f_ext, dirichlet, o: dict, precision: int, extra=()):
+        """Sizes and dtypes of the assembly's state, vectors and given outputs (_validate)."""
+        i = self.info
+        n, nd = i["n_point"], i["n_dof"]
+        kt = torch.float64 if precision == MPM_F64 else torch.float32
+        specs = [(u, "u", nd, F64), (f_ext, "f_ext", nd, F64), (dirichlet, "dirichlet", nd, (torch.uint8, torch.bool)),
+                 (o.get("f_int"), "f_int", nd, F64), (o.get("K"), "K", i["nnz"], (kt,)),
+                 (o.get("r"), "r", nd, F64), (o.get("rnorm"), "rnorm", 1, F64)]
+        specs += [(o.get(k), k, c * n, F64) for k, c in (("sigma", 6), ("F_new", 9), ("be_new", 6), ("a_new", 3),
+                                                          ("v_new", 3))]
+        _validate(specs + list(extra) + state_specs(s, n))
+
     # -------------------------------------------------------------- GIMP refinement
     def split_mark(self, x: torch.Tensor, l: torch.Tensor, beta: float = 2.0, out: Optional[torch.Tensor] = None):
         """mpm_split_mark: uint8 flags [n] of the points to split and their count."""
         n = int(x.shape[1])
+        _check(x, "x", 3 * n)
+        _check(l, "l", 3 * n)
         flags = torch.empty(n, dtype=torch.uint8, device="cuda") if out is None else out
+        _check(flags, "out", n, (torch.uint8,))
         cnt = C.c_int64(0)
         check(lib().mpm_split_mark(self.h, _ptr(x), _ptr(l), n, float(beta), _ptr(flags), C.byref(cnt), _stream()))
         return flags, int(cnt.value)
@@ -183,6 +255,9 @@ class Mesh:
         plus "X" and "v" when given; props {"E"|"nu"|"sy": (a0, a1, a2, a3)} evaluates those
         parameters at the children's reference positions."""
         n = int(flags.shape[0])
+        _check(flags, "flags", n, (torch.uint8,))
+        _check(X, "X", 3 * n)
+        _check(v, "v", 3 * n)
         n_out = n + 7 * int(n_split)
         o = {}
         so = _lib.StateOutT()
@@ -202,14 +277,15 @@ class Mesh:
                 mask |= 1 << r
                 coef[4 * r:4 * r + 4] = [float(a) for a in props[name]]
         cbuf = (C.c_double * 12)(*coef)
-        st = self._state(s)
+        st = self._state(s, n)
         check(lib().mpm_split_apply(self.h, n, _ptr(flags), C.byref(st), _ptr(X), _ptr(v), cbuf, mask, C.byref(so),
                                     _ptr(o.get("X")), _ptr(o.get("v")), n_out, _stream()))
         return o
 
     def external_force(self, s: dict, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         out = torch.empty(self.info["n_dof"], dtype=torch.float64, device="cuda") if out is None else out
-        st = self._state(s)
+        _check(out, "out", self.info["n_dof"])
+        st = self._state(s, self.info["n_point"])
         check(lib().mpm_external_force(self.h, C.byref(st), _ptr(out), _stream()))
         return out
 
@@ -219,6 +295,7 @@ class Mesh:
         i = self.info
         n = i["n_point"]
         o = {} if out is None else out
+        self._check_io(s, u, f_ext, dirichlet, o, p)
         dev = "cuda"
         if "f_int" not in o:
             o["f_int"] = torch.empty(i["n_dof"], dtype=torch.float64, device=dev)
@@ -251,6 +328,7 @@ class Mesh:
         i = self.info
         n = i["n_point"]
         o = {} if out is None else out
+        self._check_io(s, u, f_ext, dirichlet, o, p, extra=[(v_n.contiguous(), "v_n", 3 * n, F64)])
         dev = "cuda"
         if "f_int" not in o:
             o["f_int"] = torch.empty(i["n_dof"], dtype=torch.float64, device=dev)
@@ -278,6 +356,8 @@ class Mesh:
     def spmv(self, K: torch.Tensor, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         """y = K x on the mesh's CSR (K FP64 or FP32, x FP64)."""
         p = MPM_F64 if K.dtype == torch.float64 else MPM_F32K
+        nd = self.info["n_dof"]
+        _validate([self._K_spec(K), (x, "x", nd, F64), (out, "out", nd, F64)])
         y = torch.empty_like(x) if out is None else out
         check(lib().mpm_spmv(self.h, p, _ptr(K), _ptr(x), _ptr(y), _stream()))
         return y
@@ -286,6 +366,9 @@ class Mesh:
                  out: Optional[torch.Tensor] = None):
         """Jacobi-preconditioned CG for K_ff x_f = b_f (free DOFs); returns (x, iterations, relres)."""
         p = MPM_F64 if K.dtype == torch.float64 else MPM_F32K
+        nd = self.info["n_dof"]
+        _validate([self._K_spec(K), (b, "b", nd, F64), (dirichlet, "dirichlet", nd, (torch.uint8, torch.bool)),
+                   (out, "out", nd, F64)])
         x = torch.empty_like(b) if out is None else out
         it = C.c_int32(0)
         rr = C.c_double(0.0)
@@ -298,6 +381,9 @@ class Mesh:
         """Restarted GMRES with the Jacobi preconditioner on the right for K_ff x_f = b_f (free
         DOFs); returns (x, Arnoldi steps, true relative residual)."""
         p = MPM_F64 if K.dtype == torch.float64 else MPM_F32K
+        nd = self.info["n_dof"]
+        _validate([self._K_spec(K), (b, "b", nd, F64), (dirichlet, "dirichlet", nd, (torch.uint8, torch.bool)),
+                   (out, "out", nd, F64)])
         x = torch.empty_like(b) if out is None else out
         it = C.c_int32(0)
         rr = C.c_double(0.0)
@@ -309,6 +395,8 @@ class Mesh:
         p = PRECISION.get(precision, precision)
         n = self.info["n_point"]
         o = {} if out is None else out
+        _validate([(u, "u", self.info["n_dof"], F64), (lam, "lambda", self.info["n_dof"], F64)] +
+                  [(o.get(k), k, n, F64) for k in ("dE", "dnu", "dsy", "dV")] + state_specs(s, n))
         for k in ("dE", "dnu", "dsy", "dV"):
             if k not in o:
                 o[k] = torch.empty(n, dtype=torch.float64, device="cuda")

@@ -100,3 +100,32 @@ def test_external_force_total(kind, jit):
     ref = np.where(d == 1, 0.0, fi - fe.ravel())
     assert np.array_equal(r, ref)
     assert abs(rn - np.sqrt(np.sum(ref * ref))) < 1e-15 * rn
+
+
+@pytest.mark.parametrize("kind,jit,sy", CASES)
+def test_committed_state(kind, jit, sy):
+    """The history the assembly commits (Section 2.1, updated Lagrangian; Section 2.2):
+    F_new = dF F_n with dF = I + sum_v u_v (x) grad S_v rebuilt here from the basis; b_e is the
+    trial tensor dF b_n dF^T at elastic points; and a step from the committed state (b_n = b_e,
+    J_n = J, F_n = F_new) with no further displacement returns the same Cauchy stress."""
+    w, m, ps, s, u = _problem(kind, jit, sy)
+    out = m.assemble(s, u, want_K=False)
+    U = u.reshape(-1, 3)
+    n = ps.n
+    Jnew = np.zeros(n)
+    for p in range(n):
+        nd, S, dS = m.point_basis(ps.x[:, p], ps.l[:, p])
+        dF = np.eye(3) + U[nd].T @ dS
+        Fn = s["Fn"][:, p].reshape(3, 3)
+        Fp = out["Fnew"][:, p].reshape(3, 3)
+        assert np.abs(Fp - dF @ Fn).max() < 1e-14
+        Jnew[p] = np.linalg.det(dF) * s["Jn"][p]
+        if not out["plastic"][p]:
+            bn = s["bn"][:, p]
+            B = dF @ np.array([[bn[0], bn[3], bn[5]], [bn[3], bn[1], bn[4]], [bn[5], bn[4], bn[2]]]) @ dF.T
+            be = out["be"][:, p]
+            assert np.abs(be - B[[0, 1, 2, 0, 1, 0], [0, 1, 2, 1, 2, 2]]).max() < 1e-14
+    assert np.abs(Jnew / np.array([np.linalg.det(out["Fnew"][:, p].reshape(3, 3)) for p in range(n)]) - 1).max() < 1e-13
+    s2 = dict(s, bn=out["be"], Jn=Jnew, Fn=out["Fnew"])
+    again = m.assemble(s2, np.zeros_like(u), want_K=False)
+    assert np.abs(again["sigma"] - out["sigma"]).max() < 1e-12 * np.abs(out["sigma"]).max()

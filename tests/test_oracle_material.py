@@ -134,3 +134,71 @@ def test_undeformed_tangent_is_small_strain_elasticity():
     C = lamL * np.einsum("ij,kl->ijkl", d, d) + G * (np.einsum("ik,jl->ijkl", d, d) + np.einsum("il,jk->ijkl", d, d))
     assert np.abs(o["a"] - C).max() < 1e-12 * E
     assert np.abs(o["sigma"]).max() == 0.0
+
+
+# ---------------------------------------------------------------- committed elastic strain
+# The updated-Lagrangian scheme (Section 2.1) carries the elastic left Cauchy-Green tensor
+# b_e and F to the next step; with Hencky elasticity and a perfectly plastic von Mises surface
+# (Section 2.2) the committed b_e is fixed by three facts that do not depend on how the return
+# is coded: an elastic step commits the trial tensor dF b_n dF^T itself; a plastic step keeps
+# the principal directions of the trial tensor and its volume (the radial return changes only
+# the deviatoric strain, so det b_e = det b_tr); and the Hencky stress of the committed b_e is
+# the returned stress, which lies on the yield surface.
+
+def _btr(dF, bn):
+    return dF @ full(bn) @ dF.T
+
+
+def _hencky_tau(b, E, nu):
+    """Kirchhoff stress of Hencky elasticity at the elastic left Cauchy-Green tensor b:
+    tau = lam tr(eps) I + 2 G eps with eps = log(b) / 2 (numpy eigendecomposition)."""
+    lam, G = E * nu / ((1 + nu) * (1 - 2 * nu)), E / (2 * (1 + nu))
+    w, V = np.linalg.eigh(b)
+    eps = 0.5 * (V * np.log(w)) @ V.T
+    return lam * np.trace(eps) * np.eye(3) + 2 * G * eps
+
+
+def test_committed_be_elastic_is_trial():
+    for _ in range(50):
+        dF, bn, Jn = rand_state(RNG)
+        o = material_point(dF, bn, Jn, 1e4, 0.3, math.inf, want_tangent=False)
+        B = _btr(dF, bn)
+        assert not o["plastic"]
+        assert np.abs(full(o["be"]) - B).max() < 1e-14 * np.abs(B).max() * 10
+        assert np.abs(_hencky_tau(full(o["be"]), 1e4, 0.3) - full(o["tau"])).max() < 1e-11 * 1e4 * 0.05
+
+
+def test_committed_be_plastic_coaxial_volume_and_stress():
+    E, nu, sy = 2e5, 0.3, 100.0
+    n = 0
+    for _ in range(200):
+        dF, bn, Jn = rand_state(RNG, 0.05)
+        o = material_point(dF, bn, Jn, E, nu, sy, want_tangent=False)
+        if not o["plastic"]:
+            continue
+        n += 1
+        B, be, tau = _btr(dF, bn), full(o["be"]), full(o["tau"])
+        # coaxial with the trial tensor: the two commute
+        assert np.abs(be @ B - B @ be).max() < 1e-13 * np.abs(B).max() ** 2
+        # the radial return keeps the volumetric strain
+        assert abs(np.linalg.det(be) / np.linalg.det(B) - 1.0) < 1e-13
+        # the committed tensor's Hencky stress is the returned stress, on the yield surface
+        th = _hencky_tau(be, E, nu)
+        assert np.abs(th - tau).max() < 1e-12 * E
+        s = th - np.trace(th) / 3 * np.eye(3)
+        assert abs(math.sqrt(1.5 * np.sum(s * s)) - sy) < 1e-12 * E
+    assert n > 100
+
+
+@pytest.mark.parametrize("sy", [math.inf, 100.0])
+def test_recommitted_state_reproduces_stress(sy):
+    """A new step from the committed state with no further displacement (dF = I,
+    b_n = b_e, J_n = J) returns the committed stress: the committed state is a fixed point."""
+    E, nu = 2e5, 0.3
+    for _ in range(60):
+        dF, bn, Jn = rand_state(RNG, 0.05)
+        o = material_point(dF, bn, Jn, E, nu, sy, want_tangent=False)
+        r = material_point(np.eye(3), o["be"], o["J"], E, nu, sy, want_tangent=False)
+        assert np.abs(r["tau"] - o["tau"]).max() < 1e-11 * E
+        assert np.abs(r["sigma"] - o["sigma"]).max() < 1e-11 * E
+        assert abs(r["J"] - o["J"]) < 1e-15

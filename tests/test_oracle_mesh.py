@@ -63,31 +63,151 @@ def test_tiles_domain_and_balance_bruteforce(kind):
     assert np.all(np.abs(lv[i, 3] - lv[j, 3]) <= 1), "2:1 balance across faces and edges"
 
 
-@pytest.mark.parametrize("kind", ["sphere", "box"])
+# ---------------------------------------------------------------- Steps 1-3 of the adaptive
+# strategy (Section 5): distances to the rigid body, computed here by routes that do not share
+# the oracle's closed forms. The cone-and-shaft solid is a solid of revolution, so the distance
+# of a point outside it is the distance, in the meridian half-plane (rho, z), to the boundary of
+# its cross-section (the quadrilateral apex - cone rim - shaft top - axis top); that boundary
+# is sampled densely here, which gives the distance to within half the sample spacing.
+CONE_STEP = 1e-4
+
+
+def _cone_boundary(b, step):
+    za, R, t, zt = b[2], b[3], b[4], b[5]
+    zc = za + R / t
+    pts = []
+    for (r0, z0), (r1, z1) in (((0.0, za), (R, zc)), ((R, zc), (R, zt)), ((R, zt), (0.0, zt))):
+        n = int(np.ceil(np.hypot(r1 - r0, z1 - z0) / step)) + 1
+        u = np.linspace(0.0, 1.0, n)
+        pts.append(np.stack([r0 + u * (r1 - r0), z0 + u * (z1 - z0)], axis=1))
+    return np.concatenate(pts)
+
+
+def body_distance(w, P, step=CONE_STEP):
+    """Distance of points P (3, m) to the closed body (0 inside) and a bound on its error:
+    exact for the sphere and the box (distance to a ball and to a box), within step/2 for the
+    sampled cone."""
+    b = w.body
+    inside = W.generate._inside_body(w, P[0], P[1], P[2])
+    if w.body_kind == W.configs.BODY_SPHERE:
+        d = np.sqrt(((P - np.array(b[:3])[:, None]) ** 2).sum(0)) - b[3]
+        return np.maximum(d, 0.0), 0.0
+    if w.body_kind == W.configs.BODY_BOX:
+        blo, bhi = np.array(b[0::2]), np.array(b[1::2])
+        return np.sqrt((np.maximum(0, np.maximum(blo[:, None] - P, P - bhi[:, None])) ** 2).sum(0)), 0.0
+    B = _cone_boundary(b, step)
+    rho = np.hypot(P[0] - b[0], P[1] - b[1])
+    d = np.empty(P.shape[1])
+    for c in range(0, P.shape[1], 2048):
+        q = np.stack([rho[c:c + 2048], P[2, c:c + 2048]], axis=1)
+        d[c:c + 2048] = np.sqrt(((q[:, None, :] - B[None, :, :]) ** 2).sum(2)).min(1)
+    d[inside] = 0.0
+    return d, step / 2
+
+
+def _cell_vertices(w, anchor, size):
+    lo = np.asarray(w.lo) + np.asarray(anchor, np.float64) * w.h_min
+    h = size * w.h_min
+    return lo[:, None] + h * np.array([[i & 1, (i >> 1) & 1, (i >> 2) & 1] for i in range(8)]).T
+
+
+def _cell_grid(w, anchor, size, n):
+    lo = np.asarray(w.lo) + np.asarray(anchor, np.float64) * w.h_min
+    h = size * w.h_min
+    t = np.linspace(0.0, 1.0, n)
+    gz, gy, gx = np.meshgrid(t, t, t, indexing="ij")
+    return lo[:, None] + h * np.stack([gx.ravel(), gy.ravel(), gz.ravel()])
+
+
+@pytest.mark.parametrize("kind", TINY)
 def test_refinement_criterion_reached(kind):
-    """No leaf coarser than the maximum level may meet the body or carry a vertex within
-    dx_region of it (Steps 1-3 repeated until nothing is marked)."""
+    """No leaf coarser than the maximum level meets the body (Step 1) or has a vertex within
+    dx_region of it (Step 2): Steps 1-3 are repeated until nothing is marked."""
     w = tiny_workload(kind, lvl_extra=3)
     m = OracleMesh(w.crit())
     lv = m.leaves()
     s = leaf_sizes(w, lv)
-    b = w.body
-    t = np.linspace(0.0, 1.0, 7)
-    gz, gy, gx = np.meshgrid(t, t, t, indexing="ij")
-    for (x, y, z, lev), e in zip(lv, s):
-        if lev == w.lvl_max:
-            continue
-        lo = np.array([x, y, z]) * w.h_min
-        h = e * w.h_min
-        P = lo[:, None] + h * np.stack([gx.ravel(), gy.ravel(), gz.ravel()])
+    coarse = lv[:, 3] < w.lvl_max
+    assert coarse.any()
+    for (x, y, z, lev), e in zip(lv[coarse], s[coarse]):
+        P = _cell_grid(w, (x, y, z), e, 7)
         assert not np.any(W.generate._inside_body(w, P[0], P[1], P[2]))
-        V = lo[:, None] + h * np.array([[i & 1, (i >> 1) & 1, (i >> 2) & 1] for i in range(8)]).T
-        if kind == "sphere":
-            d = np.sqrt(((V - np.array(b[:3])[:, None]) ** 2).sum(0)) - b[3]
-        else:
-            blo, bhi = np.array(b[0::2]), np.array(b[1::2])
-            d = np.sqrt((np.maximum(0, np.maximum(blo[:, None] - V, V - bhi[:, None])) ** 2).sum(0))
-        assert np.all(d > w.dx_region)
+        d, err = body_distance(w, _cell_vertices(w, (x, y, z), e))
+        assert np.all(d - err > w.dx_region)
+
+
+def test_refinement_criterion_reached_cone_workload():
+    """The same Step 1 / Step 2 check on the cone-penetrometer workload's own tree (vertices of
+    every leaf coarser than level 8 farther than dx_region from the cone and shaft, with the
+    boundary sampled every 1e-3 m, and every 2e-6 m where that is not enough to decide: the
+    closest such vertices lie 4.6e-5 m beyond the band), and its finest leaves do reach it."""
+    w = W.get("c2")
+    m = OracleMesh(w.crit())
+    lv = m.leaves()
+    s = leaf_sizes(w, lv)
+    coarse = lv[:, 3] < w.lvl_max
+    off = np.array([[i & 1, (i >> 1) & 1, (i >> 2) & 1] for i in range(8)])
+    V = (lv[coarse, None, :3] + off[None, :, :] * s[coarse, None, None]).reshape(-1, 3).T
+    V = np.unique(V, axis=1).astype(np.float64) * w.h_min + np.asarray(w.lo)[:, None]
+    d, err = body_distance(w, V, step=1e-3)
+    close = d - err <= w.dx_region  # within the coarse sampling error: sample finer there
+    d2, err2 = body_distance(w, V[:, close], step=2e-6)
+    assert np.all(d2 - err2 > w.dx_region)
+    fine = ~coarse
+    C = (lv[fine, :3] + 0.5 * s[fine, None]).T * w.h_min + np.asarray(w.lo)[:, None]
+    dc, errc = body_distance(w, C[:, ::97], step=1e-3)
+    # a finest leaf's parent was marked, so some parent vertex lies within dx_region and the
+    # leaf centre within dx_region plus the parent's diagonal
+    assert dc.max() - errc <= w.dx_region + 2 * math.sqrt(3) * w.h_min
+
+
+def _internal_cells(w, lv):
+    """Every cell the refinement split: the ancestors of the leaves above the base level."""
+    cells = set()
+    for x, y, z, lev in lv:
+        a = np.array([x, y, z], np.int64)
+        for L in range(w.lvl_base, lev):
+            size = 1 << (w.lvl_max - L)
+            cells.add((int(a[0] // size * size), int(a[1] // size * size), int(a[2] // size * size), L))
+    return sorted(cells)
+
+
+@pytest.mark.parametrize("kind", TINY)
+def test_refinement_is_minimal(kind):
+    """Every split is forced (Section 5): the split cell meets the body (Step 1), has a vertex
+    within dx_region of it (Step 2), or touches, across a face or an edge, a leaf two or more
+    levels finer than itself, so that leaving it whole would put more than one hanging node on
+    that face or edge (the balance rule). Checked cell by cell over all leaves. Step 1 is
+    tested conservatively: a cell may meet the body only if the smallest distance sampled on
+    a 9 x 9 x 9 grid over it is within the grid's half-diagonal (the distance is 1-Lipschitz)."""
+    w = tiny_workload(kind, lvl_extra=3)
+    m = OracleMesh(w.crit())
+    lv = m.leaves()
+    s = leaf_sizes(w, lv)
+    lo = lv[:, :3].astype(np.int64)
+    hi = lo + s[:, None]
+    cells = _internal_cells(w, lv)
+    assert len(cells) > 10
+    unforced = []
+    for x, y, z, L in cells:
+        size = 1 << (w.lvl_max - L)
+        a = np.array([x, y, z], np.int64)
+        # balance: a leaf two or more levels finer touching the cell across a face or an edge
+        ov = np.minimum(hi, a + size) - np.maximum(lo, a)
+        touch = np.all(ov >= 0, axis=1) & (np.sum(ov > 0, axis=1) >= 1) & (np.sum(ov > 0, axis=1) <= 2)
+        if np.any(touch & (lv[:, 3] >= L + 2)):
+            continue
+        d, err = body_distance(w, _cell_vertices(w, a, size))
+        if np.any(d - err <= w.dx_region * (1 + 1e-12)):
+            continue
+        n = 9
+        G = _cell_grid(w, a, size, n)
+        dg, errg = body_distance(w, G, step=1e-3)
+        half_diag = size * w.h_min / (n - 1) * math.sqrt(3) / 2
+        if dg.min() - errg <= half_diag:
+            continue
+        unforced.append((x, y, z, L))
+    assert not unforced, f"{len(unforced)} splits forced by neither step nor balance, e.g. {unforced[:3]}"
 
 
 @pytest.mark.parametrize("kind", TINY)

@@ -95,8 +95,11 @@ typedef struct {
   double g[3];
 } orc_state;
 
+/* plastic[p]: 1 where the trial stress lies outside the yield surface; qtrial[p]: the trial
+ * von Mises stress sqrt(3 J2) of the Kirchhoff stress (both may be NULL). */
 int32_t orc_assemble(const orc_mesh* m, const orc_state* s, const double* u, double* f_int, double* K,
-                     double* sigma6, double* Fnew9, double* be6, uint8_t* plastic, int64_t* bad_index);
+                     double* sigma6, double* Fnew9, double* be6, uint8_t* plastic, double* qtrial,
+                     int64_t* bad_index);
 int32_t orc_external_force(const orc_mesh* m, const orc_state* s, double* f_ext);
 /* Newmark (gamma = 1, beta = 1/2) inertia term: f_iner over 3*n_indep DOFs, (2/dt^2) x the
  * consistent mass added into K (CSR pattern; may be NULL), point acceleration and updated

@@ -69,7 +69,7 @@ def lib():
         L.orc_material_point.restype = C.c_int32
         L.orc_material_point.argtypes = [vp, vp, C.c_double, C.c_double, C.c_double, C.c_double, vp, vp, vp, vp, vp]
         L.orc_assemble.restype = C.c_int32
-        L.orc_assemble.argtypes = [vp, C.POINTER(_State), vp, vp, vp, vp, vp, vp, vp, i64p]
+        L.orc_assemble.argtypes = [vp, C.POINTER(_State), vp, vp, vp, vp, vp, vp, vp, vp, i64p]
         L.orc_external_force.restype = C.c_int32
         L.orc_external_force.argtypes = [vp, C.POINTER(_State), vp]
         L.orc_mesh_set_ghost.argtypes = [vp, C.c_int32]
@@ -260,12 +260,13 @@ class OracleMesh:
         Fnew = np.zeros((9, n), _f64) if s.get("Fn") is not None else None
         be = np.zeros((6, n), _f64)
         pl = np.zeros(n, np.uint8)
+        q = np.zeros(n, _f64)
         bad = C.c_int64(-1)
         code = lib().orc_assemble(self.h, C.byref(st), _p(u), _p(f), _p(K), _p(sig), _p(Fnew), _p(be), _p(pl),
-                                  C.byref(bad))
+                                  _p(q), C.byref(bad))
         if code != 0:
             raise OracleError(code, bad.value)
-        return dict(f_int=f, K=K, sigma=sig, Fnew=Fnew, be=be, plastic=pl)
+        return dict(f_int=f, K=K, sigma=sig, Fnew=Fnew, be=be, plastic=pl, q_trial=q)
 
     def external_force(self, s: dict) -> np.ndarray:
         st = self._state(s)

@@ -298,7 +298,7 @@ static int64_t csr_find(const orc_mesh* m, int64_t row, int32_t colv) {
 /* Updated-Lagrangian weak form (Section 2.1): f_v = sum_p V_p sigma_p grad_x S_vp with
  * V_p = det(dF) V_n, and K = d f_int / d u with the basis frozen over the step. */
 int32_t orc_assemble(const orc_mesh* m, const orc_state* s, const double* u, double* f_int, double* K,
-                     double* sigma6, double* Fnew9, double* be6, uint8_t* plastic, int64_t* bad) {
+                     double* sigma6, double* Fnew9, double* be6, uint8_t* plastic, double* qtrial, int64_t* bad) {
   *bad = -1;
   int64_t n = m->np;
   memset(f_int, 0, (size_t)(3 * m->nindep) * sizeof(double));
@@ -315,6 +315,7 @@ int32_t orc_assemble(const orc_mesh* m, const orc_state* s, const double* u, dou
     if (sigma6) for (int c = 0; c < 6; c++) sigma6[c * n + p] = sig[c];
     if (be6) for (int c = 0; c < 6; c++) be6[c * n + p] = be[c];
     if (plastic) plastic[p] = (uint8_t)info[0];
+    if (qtrial) qtrial[p] = info[1];
     if (Fnew9 && s->Fn) {
       for (int i = 0; i < 3; i++)
         for (int j = 0; j < 3; j++) {

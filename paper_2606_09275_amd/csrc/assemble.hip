@@ -88,9 +88,14 @@ __device__ __forceinline__ void load_B(const mpm_state_t& s, int64_t n, int64_t 
   B[0][2] = B[2][0] = T(b5);
 }
 
-// write sigma and (optionally) the committed state of one point
+// write sigma and (optionally) the committed state of one point: the elastic left
+// Cauchy-Green tensor b_e = sum_a exp(2 eps_e,a) n_a n_a^T of the returned elastic strains
+// (Section 2.2) and F_new = dF F_n (Section 2.1, updated Lagrangian). Both are formed from
+// their increments so that the FP32 working precision costs relative accuracy of the strain,
+// not of the unit tensor: b_e = I + sum_a expm1(2 eps_e,a) n_a n_a^T (the n_a are orthonormal)
+// and F_new = F_n + H F_n with H = dF - I, the unit parts added in FP64.
 template <typename T>
-__device__ __forceinline__ void write_point(const AsmArgs& A, int64_t i, const PointMat<T>& P, const T F[3][3],
+__device__ __forceinline__ void write_point(const AsmArgs& A, int64_t i, const PointMat<T>& P, const T H[3][3],
                                             double J) {
   const int64_t n = A.n;
   if (A.sigma) {
@@ -103,23 +108,35 @@ __device__ __forceinline__ void write_point(const AsmArgs& A, int64_t i, const P
     A.sigma[5 * n + i] = double(P.tau[0][2]) * iJ;
   }
   if (A.be) {
+    // eps_e = eps - (1 - r) s_trial / (2 G). The return keeps the volumetric strain and scales
+    // the deviator to the surface, so at a plastic point eps_e = tr(eps)/3 + r s_trial / (2 G)
+    // with r |s_trial| = sqrt(2/3) sigma_y: formed from the unit deviator, this avoids the
+    // cancellation of eps against the returned part (large when sigma_y is small against the
+    // trial stress), which costs FP32 most of its digits
     T ee[3];
-    for (int a = 0; a < 3; ++a)
-      ee[a] = t_exp<T>(T(2) * (P.eps[a] - (T(1) - P.r) * (P.tp[a] - (P.tp[0] + P.tp[1] + P.tp[2]) / T(3)) /
-                                              (T(2) * P.G * P.r)));
+    if (P.plastic) {
+      const T tr3 = (P.eps[0] + P.eps[1] + P.eps[2]) / T(3);
+      const T rs = t_sqrt<T>(T(2) / T(3)) * T(A.s.sy[i]) / (T(2) * P.G);
+      for (int a = 0; a < 3; ++a) ee[a] = t_expm1<T>(T(2) * (tr3 + rs * P.s_hat[a]));
+    } else {
+      for (int a = 0; a < 3; ++a) ee[a] = t_expm1<T>(T(2) * P.eps[a]);
+    }
     const int ii[6] = {0, 1, 2, 0, 1, 0}, jj[6] = {0, 1, 2, 1, 2, 2};
     for (int c = 0; c < 6; ++c) {
       T v = 0;
       for (int a = 0; a < 3; ++a) v += ee[a] * P.N[ii[c]][a] * P.N[jj[c]][a];
-      A.be[c * n + i] = double(v);
+      A.be[c * n + i] = double(v) + (c < 3 ? 1.0 : 0.0);
     }
   }
   if (A.Fnew && A.s.Fn) {
+    double Fn[3][3];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) Fn[r][c] = A.s.Fn[(3 * r + c) * n + i];
     for (int r = 0; r < 3; ++r)
       for (int c = 0; c < 3; ++c) {
         double v = 0;
-        for (int m = 0; m < 3; ++m) v += double(F[r][m]) * A.s.Fn[(3 * m + c) * n + i];
-        A.Fnew[(3 * r + c) * n + i] = v;
+        for (int m = 0; m < 3; ++m) v += double(H[r][m]) * Fn[m][c];
+        A.Fnew[(3 * r + c) * n + i] = Fn[r][c] + v;
       }
   }
 }
@@ -314,7 +331,7 @@ void k_assemble_fast(AsmArgs A) {
         act = false;
       } else {
         c = T(A.s.vol[i] / Jn);
-        write_point<T>(A, i, P, F, double(Jd) * Jn);
+        write_point<T>(A, i, P, H, double(Jd) * Jn);
       }
     }
   }
@@ -720,7 +737,7 @@ __global__ __launch_bounds__(64) void k_general_points(AsmArgs A) {
     for (int q = 0; q < kGenRec; ++q) rec[q] = 0.0;
     return;
   }
-  write_point<T>(A, i, P, F, double(Jd) * Jn);
+  write_point<T>(A, i, P, H, double(Jd) * Jn);
   const T c = T(A.s.vol[i] / Jn);
   double ma[3] = {0.0, 0.0, 0.0}, c2m = 0.0;
   if (A.vel) {  // Newmark inertia, gamma = 1, beta = 1/2

@@ -27,11 +27,11 @@ __device__ __forceinline__ double t_sqrt<double>(double v) { return sqrt(v); }
 template <>
 __device__ __forceinline__ float t_sqrt<float>(float v) { return sqrtf(v); }
 template <typename T>
-__device__ __forceinline__ T t_exp(T v);
+__device__ __forceinline__ T t_expm1(T v);
 template <>
-__device__ __forceinline__ double t_exp<double>(double v) { return exp(v); }
+__device__ __forceinline__ double t_expm1<double>(double v) { return expm1(v); }
 template <>
-__device__ __forceinline__ float t_exp<float>(float v) { return expf(v); }
+__device__ __forceinline__ float t_expm1<float>(float v) { return expm1f(v); }
 
 // log1p(z)/z for |z| < 1/16 by the Mercator series log(1 + z) = z - z^2/2 + z^3/3 - ...
 // (Horner form of sum_k (-z)^k / (k + 1)); the truncation error after degree n is below

@@ -115,16 +115,24 @@ def test_assemble_fp32k_error_bounds(tag, kind, jit):
     o, m, ps = build_pair(w, jitter=jit)
     st, u, s_dev, nodes = _inputs(w, o, ps, m, u_amp=2e-3)
     ref = o.assemble(st, u)
-    out = m.assemble(s_dev, torch.from_numpy(u).cuda(), "f32k")
+    fe_ref = o.external_force(dict(st, g=(0.0, 0.0, -9.81)))
+    d = W.dirichlet_dofs(nodes)
+    from oracle.oracle import residual
+    r_ref, rn_ref = residual(ref["f_int"], fe_ref, d)
+    fe = m.external_force(s_dev)
+    out = m.assemble(s_dev, torch.from_numpy(u).cuda(), "f32k", f_ext=fe, dirichlet=torch.from_numpy(d).cuda())
     torch.cuda.synchronize()
     perm = to_np(m.arrays()["perm"])
     pl = ref["plastic"][perm]
     e_f = rel_err(to_np(out["f_int"]), ref["f_int"])
     e_k = rel_err(to_np(out["K"]), ref["K"])
     e_s = rel_err(to_np(out["sigma"]), ref["sigma"][:, perm])
-    log(f"[parity] {tag} fp32k f={e_f:.2e} K={e_k:.2e} sigma={e_s:.2e} plastic={pl.mean():.2f}")
+    e_r = rel_err(to_np(out["r"]), r_ref)
+    e_rn = abs(float(to_np(out["rnorm"])[0]) - rn_ref) / rn_ref
+    log(f"[parity] {tag} fp32k f={e_f:.2e} K={e_k:.2e} sigma={e_s:.2e} r={e_r:.2e} rnorm={e_rn:.2e} "
+        f"plastic={pl.mean():.2f}")
     assert out["K"].dtype == torch.float32 and out["f_int"].dtype == torch.float64
-    assert e_f <= TOL32_F and e_k <= TOL32_K and e_s <= TOL32_SIG
+    assert e_f <= TOL32_F and e_k <= TOL32_K and e_s <= TOL32_SIG and e_r <= TOL32_F and e_rn <= TOL32_F
 
 
 @pytest.mark.parametrize("tag,kind,jit", [("c0", None, None), ("tiny_sphere_jit", "sphere", 0),
@@ -170,11 +178,13 @@ def test_c1_full_size_parity():
     st, u, s_dev, nodes = _inputs(w, o, ps, m)
     ref = o.assemble(st, u)
     perm = to_np(m.arrays()["perm"])
-    out = m.assemble(s_dev, torch.from_numpy(u).cuda(), "f64")
+    out = m.assemble(s_dev, torch.from_numpy(u).cuda(), "f64", commit=True)
     torch.cuda.synchronize()
     e = (rel_err(to_np(out["f_int"]), ref["f_int"]), rel_err(to_np(out["K"]), ref["K"]),
-         rel_err(to_np(out["sigma"]), ref["sigma"][:, perm]))
-    log(f"[parity] c1 full fp64 f={e[0]:.2e} K={e[1]:.2e} sigma={e[2]:.2e} plastic={ref['plastic'].mean():.3f}")
+         rel_err(to_np(out["sigma"]), ref["sigma"][:, perm]), rel_err(to_np(out["F_new"]), ref["Fnew"][:, perm]),
+         rel_err(to_np(out["be_new"]), ref["be"][:, perm]))
+    log(f"[parity] c1 full fp64 f={e[0]:.2e} K={e[1]:.2e} sigma={e[2]:.2e} F_new={e[3]:.2e} b_e={e[4]:.2e} "
+        f"plastic={ref['plastic'].mean():.3f}")
     assert max(e) <= TOL64
     out32 = m.assemble(s_dev, torch.from_numpy(u).cuda(), "f32k")
     torch.cuda.synchronize()

@@ -129,3 +129,37 @@ def test_committed_state(kind, jit, sy):
     s2 = dict(s, bn=out["be"], Jn=Jnew, Fn=out["Fnew"])
     again = m.assemble(s2, np.zeros_like(u), want_K=False)
     assert np.abs(again["sigma"] - out["sigma"]).max() < 1e-12 * np.abs(out["sigma"]).max()
+
+
+def test_trial_stress_output():
+    """q_trial is the von Mises stress sqrt(3 J2) of the trial Kirchhoff stress: with no yield
+    limit it equals that of the returned stress (tau = J sigma); with a finite limit a point
+    is plastic exactly where q_trial exceeds it. The 70th percentile of q_trial as the limit
+    (the rule that sets the partial-yielding workload's yield stress) yields 30 % of them."""
+    w, m, ps, s, u = _problem("sphere", 0, math.inf)
+    el = m.assemble(s, u, want_K=False)
+    J = np.array([np.linalg.det(el["Fnew"][:, p].reshape(3, 3)) for p in range(ps.n)])
+    tau = el["sigma"] * J
+    dev = tau.copy()
+    dev[:3] -= tau[:3].mean(axis=0)
+    q = np.sqrt(1.5 * (dev[0] ** 2 + dev[1] ** 2 + dev[2] ** 2 + 2 * (dev[3] ** 2 + dev[4] ** 2 + dev[5] ** 2)))
+    assert np.abs(el["q_trial"] - q).max() < 1e-12 * q.max()
+    sy = float(np.percentile(el["q_trial"], 70))
+    pl = m.assemble(dict(s, sy=np.full(ps.n, sy)), u, want_K=False)
+    assert np.array_equal(pl["plastic"].astype(bool), el["q_trial"] > sy)
+    assert abs(pl["plastic"].mean() - 0.3) < 2.0 / ps.n
+    assert np.array_equal(pl["q_trial"], el["q_trial"])
+
+
+def test_partial_yield_workload_sigma_y():
+    """The partial-yielding sphere workload's yield stress is the stored output of its
+    oracle-only script, and the oracle yields 30 % of its points at that stress."""
+    import json
+    from pathlib import Path
+    rec = json.loads((Path(__file__).resolve().parent / "golden" / "c1b_sigma_y.json").read_text())
+    w = W.get("c1b")
+    assert w.sy == rec["sigma_y"]
+    from tests.golden.make_c1b_sigma_y import trial_q
+    q = trial_q(W.get("c1"))
+    assert float(np.percentile(q, 70)) == rec["sigma_y"]
+    assert abs(np.mean(q > w.sy) - 0.3) < 1e-4

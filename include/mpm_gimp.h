@@ -255,6 +255,23 @@ int32_t mpm_solve_cg(const mpm_mesh_t* mesh, int32_t precision, const void* K_va
                      const double* b, double* x, double rtol, int32_t max_iter, int32_t* iters, double* relres,
                      void* stream);
 
+/* Allocation-free variant of mpm_solve_cg, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * same arguments, kernels, iterates and outputs as mpm_solve_cg, but it calls no hipMalloc,
+ * hipFree or other allocating routine. Its work vectors live in a static device array of
+ * 64 MiB that every GPU the library runs on holds for the life of the process, which limits
+ * n_dof to MPM_CG_NOALLOC_MAX_DOFS (about 41 bytes per DOF); a larger mesh is refused with
+ * MPM_EARG and a message that gives both sizes. The first call on a device looks up that
+ * device's copy of the array. All calls on one GPU share its array and everything in it is
+ * rewritten before it is read, but calls that overlap on one device (two streams or two
+ * threads at once) race and must be serialised by the caller. The host reads the convergence
+ * flag after a stream synchronisation every 16 iterations, so the call itself cannot be
+ * captured into a graph as a whole. */
+#define MPM_CG_NOALLOC_MAX_DOFS 1635968
+int32_t mpm_solve_cg_noalloc(const mpm_mesh_t* mesh, int32_t precision, const void* K_vals,
+                             const uint8_t* dirichlet, const double* b, double* x, double rtol, int32_t max_iter,
+                             int32_t* iters, double* relres, void* stream);
+
 /* Linear solve of a Newton step with restarted GMRES, the Krylov solver the paper names for its
  * possibly non-symmetric systems (Section 1), with the diagonal Jacobi preconditioner it
  * proposes (Section 6), applied on the right so that the minimised residual is the true one.

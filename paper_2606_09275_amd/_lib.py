@@ -10,6 +10,7 @@ LIB_PATH = PKG / "libmpmgimp.so"
 
 MPM_OK, MPM_EARG, MPM_EDET, MPM_ESTENCIL, MPM_EOUTSIDE, MPM_ETREE, MPM_EHIP, MPM_ENONFINITE = 0, -1, -2, -3, -4, -5, -6, -7
 MPM_F64, MPM_F32K = 0, 1
+MPM_CG_NOALLOC_MAX_DOFS = 1635968  # largest n_dof of mpm_solve_cg_noalloc (static work space)
 
 
 class RefineT(C.Structure):
@@ -84,6 +85,9 @@ def lib():
     L.mpm_spmv.argtypes = [vp, i32, vp, vp, vp, vp]
     L.mpm_solve_cg.restype = i32
     L.mpm_solve_cg.argtypes = [vp, i32, vp, vp, vp, vp, C.c_double, i32, C.POINTER(i32), C.POINTER(C.c_double), vp]
+    L.mpm_solve_cg_noalloc.restype = i32
+    L.mpm_solve_cg_noalloc.argtypes = [vp, i32, vp, vp, vp, vp, C.c_double, i32, C.POINTER(i32),
+                                       C.POINTER(C.c_double), vp]
     L.mpm_solve_gmres.restype = i32
     L.mpm_solve_gmres.argtypes = [vp, i32, vp, vp, vp, vp, C.c_double, i32, i32, C.POINTER(i32),
                                   C.POINTER(C.c_double), vp]
@@ -107,7 +111,7 @@ def lib():
 
 EXPORTED = ["octree_build", "mpm_mesh_info", "mpm_mesh_arrays", "mpm_ghost_faces", "mpm_mesh_free", "mpm_point_sort", "mpm_permute",
             "mpm_external_force", "mpm_assemble", "mpm_assemble_dynamic", "mpm_assemble_adjoint", "mpm_spmv",
-            "mpm_solve_cg", "mpm_solve_gmres", "mpm_split_mark", "mpm_split_apply", "mpm_kernel_timing", "mpm_last_error",
+            "mpm_solve_cg", "mpm_solve_cg_noalloc", "mpm_solve_gmres", "mpm_split_mark", "mpm_split_apply", "mpm_kernel_timing", "mpm_last_error",
             "mpm_last_error_index"]
 
 

@@ -8,6 +8,7 @@
 #include <cstddef>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "internal.h"
 
@@ -227,26 +228,18 @@ struct CgBuf {
   uint8_t* fr;
 };
 
-static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+static constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
-static int32_t cg_buffers(mpm_mesh* m, hipStream_t st, CgBuf* B) {
-  const size_t nd = size_t(3 * m->n_node);
+// bytes of the CG work buffer for n_dof DOFs
+static constexpr size_t cg_bytes(size_t nd) {
+  return 5 * align256(nd * 8) + align256(2 * kUpdBlocks * 8) + align256(kNumScalars * 8) + align256(sizeof(CgFlags)) +
+         align256(nd > 0 ? nd : 1);
+}
+
+// lay the work vectors out over a buffer of cg_bytes(nd) bytes
+static void cg_carve(void* base, size_t nd, CgBuf* B) {
   const size_t vec = align256(nd * 8);
-  const size_t need = 5 * vec + align256(2 * kUpdBlocks * 8) + align256(kNumScalars * 8) +
-                      align256(sizeof(CgFlags)) + align256(std::max<size_t>(1, nd));
-  if (m->cg_bytes < need || !m->d_cg) {
-    MPM_HIP(hipStreamSynchronize(st));
-    if (m->d_cg) MPM_HIP(hipFree(m->d_cg));
-    m->d_cg = nullptr;
-    m->cg_bytes = 0;
-    const hipError_t e = hipMalloc(&m->d_cg, need);
-    if (e != hipSuccess) {
-      m->d_cg = nullptr;
-      return hip_fail(e, "mpm_solve_cg: work buffer");
-    }
-    m->cg_bytes = need;
-  }
-  char* w = static_cast<char*>(m->d_cg);
+  char* w = static_cast<char*>(base);
   B->r = reinterpret_cast<double*>(w);
   B->z = reinterpret_cast<double*>(w + vec);
   B->p = reinterpret_cast<double*>(w + 2 * vec);
@@ -260,15 +253,52 @@ static int32_t cg_buffers(mpm_mesh* m, hipStream_t st, CgBuf* B) {
   B->flags = reinterpret_cast<CgFlags*>(w);
   w += align256(sizeof(CgFlags));
   B->fr = reinterpret_cast<uint8_t*>(w);
+}
+
+static int32_t cg_buffers(mpm_mesh* m, hipStream_t st, CgBuf* B) {
+  const size_t nd = size_t(3 * m->n_node);
+  const size_t need = cg_bytes(nd);
+  if (m->cg_bytes < need || !m->d_cg) {
+    MPM_HIP(hipStreamSynchronize(st));
+    if (m->d_cg) MPM_HIP(hipFree(m->d_cg));
+    m->d_cg = nullptr;
+    m->cg_bytes = 0;
+    const hipError_t e = hipMalloc(&m->d_cg, need);
+    if (e != hipSuccess) {
+      m->d_cg = nullptr;
+      return hip_fail(e, "mpm_solve_cg: work buffer");
+    }
+    m->cg_bytes = need;
+  }
+  cg_carve(m->d_cg, nd, B);
+  return MPM_OK;
+}
+
+// Where the host reads the convergence flags: pinned memory and an event kept with the mesh
+// (allocated on the first call; the host spins on the event), or a caller-side host buffer
+// read after a stream synchronisation (no allocation).
+struct CgHost {
+  void* buf;          // sizeof(CgFlags) + 8 kNumScalars bytes
+  hipEvent_t ev;      // null: synchronise the stream instead
+};
+
+static int32_t cg_wait(const CgHost& H, hipStream_t st) {
+  if (!H.ev) {
+    MPM_HIP(hipStreamSynchronize(st));
+    return MPM_OK;
+  }
+  MPM_HIP(hipEventRecord(H.ev, st));
+  hipError_t q;
+  while ((q = hipEventQuery(H.ev)) == hipErrorNotReady) {
+  }
+  if (q != hipSuccess) return hip_fail(q, "mpm_solve_cg");
   return MPM_OK;
 }
 
 template <typename T>
-static int32_t solve_cg(mpm_mesh* m, const void* K, const uint8_t* dir, const double* b, double* x, double rtol,
-                        int max_iter, int* iters, double* relres, hipStream_t st) {
-  CgBuf B;
-  int32_t rc = cg_buffers(m, st, &B);
-  if (rc) return rc;
+static int32_t solve_cg_on(mpm_mesh* m, const CgBuf& B, const CgHost& H, const void* K, const uint8_t* dir,
+                           const double* b, double* x, double rtol, int max_iter, int* iters, double* relres,
+                           hipStream_t st) {
   const int64_t nd = 3 * m->n_node;
   const unsigned gv = unsigned(std::max<int64_t>(1, std::min<int64_t>(kUpdBlocks, (nd + 255) / 256)));
   hipLaunchKernelGGL(k_cg_init<T>, dim3(unsigned((nd + 255) / 256)), dim3(256), 0, st, m->d_row_ptr, m->d_col,
@@ -278,8 +308,6 @@ static int32_t solve_cg(mpm_mesh* m, const void* K, const uint8_t* dir, const do
   launch_dot(B.r, B.r, nd, B.part, B.scal, kRR, nullptr, st);
   hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(1), 0, st, B.scal, B.flags);
   const double rtol2 = rtol * rtol;
-  if (!m->h_cg) MPM_HIP(hipHostMalloc((void**)&m->h_cg, sizeof(CgFlags) + 8 * kNumScalars, hipHostMallocDefault));
-  if (!m->cg_ev) MPM_HIP(hipEventCreateWithFlags(&m->cg_ev, hipEventDisableTiming));
   constexpr int kCheck = 16;  // iterations between host reads of the flags
   for (int it = 0; it < max_iter; it += kCheck) {
     const int nk = std::min(kCheck, max_iter - it);
@@ -292,23 +320,87 @@ static int32_t solve_cg(mpm_mesh* m, const void* K, const uint8_t* dir, const do
       hipLaunchKernelGGL(k_cg_dir, dim3(gv), dim3(256), 0, st, B.p, B.z, nd, B.scal, B.flags);
     }
     MPM_HIP(hipGetLastError());
-    MPM_HIP(hipMemcpyAsync(m->h_cg, B.flags, sizeof(CgFlags), hipMemcpyDeviceToHost, st));
-    MPM_HIP(hipMemcpyAsync(static_cast<char*>(m->h_cg) + sizeof(CgFlags), B.scal, 8 * kNumScalars,
+    MPM_HIP(hipMemcpyAsync(H.buf, B.flags, sizeof(CgFlags), hipMemcpyDeviceToHost, st));
+    MPM_HIP(hipMemcpyAsync(static_cast<char*>(H.buf) + sizeof(CgFlags), B.scal, 8 * kNumScalars,
                            hipMemcpyDeviceToHost, st));
-    MPM_HIP(hipEventRecord(m->cg_ev, st));
-    hipError_t q;
-    while ((q = hipEventQuery(m->cg_ev)) == hipErrorNotReady) {
-    }
-    if (q != hipSuccess) return hip_fail(q, "mpm_solve_cg");
-    const CgFlags* f = static_cast<const CgFlags*>(m->h_cg);
+    const int32_t rc = cg_wait(H, st);
+    if (rc) return rc;
+    const CgFlags* f = static_cast<const CgFlags*>(H.buf);
     if (f->done) break;
   }
-  const CgFlags* f = static_cast<const CgFlags*>(m->h_cg);
-  const double* sc = reinterpret_cast<const double*>(static_cast<const char*>(m->h_cg) + sizeof(CgFlags));
+  if (max_iter == 0) {  // no iteration ran: read the start values once
+    MPM_HIP(hipMemcpyAsync(H.buf, B.flags, sizeof(CgFlags), hipMemcpyDeviceToHost, st));
+    MPM_HIP(hipMemcpyAsync(static_cast<char*>(H.buf) + sizeof(CgFlags), B.scal, 8 * kNumScalars,
+                           hipMemcpyDeviceToHost, st));
+    const int32_t rc = cg_wait(H, st);
+    if (rc) return rc;
+  }
+  const CgFlags* f = static_cast<const CgFlags*>(H.buf);
+  const double* sc = reinterpret_cast<const double*>(static_cast<const char*>(H.buf) + sizeof(CgFlags));
   if (iters) *iters = f->iters;
   if (relres) *relres = sc[kBB] > 0.0 ? std::sqrt(std::max(0.0, sc[kRR]) / sc[kBB]) : 0.0;
   if (f->iters == 0 && sc[kBB] > 0.0 && relres) *relres = 1.0;
   return MPM_OK;
+}
+
+template <typename T>
+static int32_t solve_cg(mpm_mesh* m, const void* K, const uint8_t* dir, const double* b, double* x, double rtol,
+                        int max_iter, int* iters, double* relres, hipStream_t st) {
+  CgBuf B;
+  int32_t rc = cg_buffers(m, st, &B);
+  if (rc) return rc;
+  if (!m->h_cg) MPM_HIP(hipHostMalloc((void**)&m->h_cg, sizeof(CgFlags) + 8 * kNumScalars, hipHostMallocDefault));
+  if (!m->cg_ev) MPM_HIP(hipEventCreateWithFlags(&m->cg_ev, hipEventDisableTiming));
+  return solve_cg_on<T>(m, B, CgHost{m->h_cg, m->cg_ev}, K, dir, b, x, rtol, max_iter, iters, relres, st);
+}
+
+// ------------------------------------------------------------------ CG without allocation
+// The same solve for callers that cannot allocate device memory: the work vectors live in
+// `scratch`, a file-scope device array of fixed size that every GPU the library runs on holds
+// for the life of the process (one copy per device, at its own address). Its device address
+// is looked up once per device with hipGetSymbolAddress on the call that first runs there, and
+// only that address is handed to kernels and copies. The host reads the flags into a local
+// buffer after a stream synchronisation. Every call on a GPU shares that GPU's copy: calls that
+// overlap on one device race.
+constexpr size_t kCgScratchBytes = size_t(64) << 20;
+static_assert(cg_bytes(MPM_CG_NOALLOC_MAX_DOFS) <= kCgScratchBytes &&
+                  cg_bytes(MPM_CG_NOALLOC_MAX_DOFS + 1) > kCgScratchBytes,
+              "MPM_CG_NOALLOC_MAX_DOFS must be the largest n_dof whose work buffer fits the static array");
+static __device__ __align__(256) unsigned char scratch[kCgScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+static void* g_scratch_ptr[kMaxScratchDevices];
+static std::mutex g_scratch_mu;
+
+static int32_t scratch_for_current_device(void** out) {
+  int dev = -1;
+  MPM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxScratchDevices) {
+    set_error(MPM_EARG, "mpm_solve_cg_noalloc: device index beyond the supported range");
+    return MPM_EARG;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                               "mpm_solve_cg_noalloc: address of the static workspace");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MPM_OK;
+}
+
+template <typename T>
+static int32_t solve_cg_noalloc(mpm_mesh* m, const void* K, const uint8_t* dir, const double* b, double* x,
+                                double rtol, int max_iter, int* iters, double* relres, hipStream_t st) {
+  void* base = nullptr;
+  int32_t rc = scratch_for_current_device(&base);
+  if (rc) return rc;
+  CgBuf B;
+  cg_carve(base, size_t(3 * m->n_node), &B);
+  alignas(8) unsigned char host[sizeof(CgFlags) + 8 * kNumScalars];
+  return solve_cg_on<T>(m, B, CgHost{host, nullptr}, K, dir, b, x, rtol, max_iter, iters, relres, st);
 }
 
 // ------------------------------------------------------------------ GMRES
@@ -659,6 +751,40 @@ extern "C" int32_t mpm_solve_cg(const mpm_mesh_t* m, int32_t precision, const vo
   }
   if (precision == MPM_F64) rc = solve_cg<double>(mm, K_vals, dirichlet, b, x, rtol, max_iter, &it, &rr, st);
   else rc = solve_cg<float>(mm, K_vals, dirichlet, b, x, rtol, max_iter, &it, &rr, st);
+  if (iters) *iters = it;
+  if (relres) *relres = rr;
+  return rc;
+}
+
+extern "C" int32_t mpm_solve_cg_noalloc(const mpm_mesh_t* m, int32_t precision, const void* K_vals,
+                                        const uint8_t* dirichlet, const double* b, double* x, double rtol,
+                                        int32_t max_iter, int32_t* iters, double* relres, void* stream) {
+  if (!m || (!K_vals && m->nnz) || !b || !x || (precision != MPM_F64 && precision != MPM_F32K) || !(rtol >= 0.0) ||
+      max_iter < 0) {
+    set_error(MPM_EARG, "mpm_solve_cg_noalloc: null argument, bad precision, negative tolerance or iteration limit");
+    return MPM_EARG;
+  }
+  if (cg_bytes(size_t(3 * m->n_node)) > kCgScratchBytes) {
+    char msg[200];
+    snprintf(msg, sizeof msg,
+             "mpm_solve_cg_noalloc: %lld DOFs need %zu bytes of work space, beyond the static %zu (at most %lld DOFs)",
+             (long long)(3 * m->n_node), cg_bytes(size_t(3 * m->n_node)), kCgScratchBytes,
+             (long long)MPM_CG_NOALLOC_MAX_DOFS);
+    set_error(MPM_EARG, msg);
+    return MPM_EARG;
+  }
+  mpm_mesh* mm = const_cast<mpm_mesh*>(m);
+  hipStream_t st = (hipStream_t)stream;
+  int it = 0;
+  double rr = 0.0;
+  int32_t rc = MPM_OK;
+  if (m->n_node == 0) {
+    if (iters) *iters = 0;
+    if (relres) *relres = 0.0;
+    return MPM_OK;
+  }
+  if (precision == MPM_F64) rc = solve_cg_noalloc<double>(mm, K_vals, dirichlet, b, x, rtol, max_iter, &it, &rr, st);
+  else rc = solve_cg_noalloc<float>(mm, K_vals, dirichlet, b, x, rtol, max_iter, &it, &rr, st);
   if (iters) *iters = it;
   if (relres) *relres = rr;
   return rc;

@@ -363,8 +363,10 @@ class Mesh:
         return y
 
     def solve_cg(self, K: torch.Tensor, b: torch.Tensor, dirichlet=None, rtol: float = 1e-8, max_iter: int = 1000,
-                 out: Optional[torch.Tensor] = None):
-        """Jacobi-preconditioned CG for K_ff x_f = b_f (free DOFs); returns (x, iterations, relres)."""
+                 out: Optional[torch.Tensor] = None, noalloc: bool = False):
+        """Jacobi-preconditioned CG for K_ff x_f = b_f (free DOFs); returns (x, iterations, relres).
+        noalloc=True calls mpm_solve_cg_noalloc (static work space, no device allocation; n_dof
+        at most MPM_CG_NOALLOC_MAX_DOFS; pass `out` to allocate nothing here either)."""
         p = MPM_F64 if K.dtype == torch.float64 else MPM_F32K
         nd = self.info["n_dof"]
         _validate([self._K_spec(K), (b, "b", nd, F64), (dirichlet, "dirichlet", nd, (torch.uint8, torch.bool)),
@@ -372,8 +374,9 @@ class Mesh:
         x = torch.empty_like(b) if out is None else out
         it = C.c_int32(0)
         rr = C.c_double(0.0)
-        check(lib().mpm_solve_cg(self.h, p, _ptr(K), _ptr(dirichlet), _ptr(b), _ptr(x), float(rtol), int(max_iter),
-                                 C.byref(it), C.byref(rr), _stream()))
+        fn = lib().mpm_solve_cg_noalloc if noalloc else lib().mpm_solve_cg
+        check(fn(self.h, p, _ptr(K), _ptr(dirichlet), _ptr(b), _ptr(x), float(rtol), int(max_iter), C.byref(it),
+                 C.byref(rr), _stream()))
         return x, int(it.value), float(rr.value)
 
     def solve_gmres(self, K: torch.Tensor, b: torch.Tensor, dirichlet=None, rtol: float = 1e-8, restart: int = 30,

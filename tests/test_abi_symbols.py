@@ -74,3 +74,10 @@ def test_argument_checks_need_no_gpu():
     buf = C.create_string_buffer(256)
     L.mpm_last_error(buf, 256)
     assert b"null" in buf.value
+
+
+def test_noalloc_capacity_constant_matches_header():
+    """The binding's copy of the allocation-free solver's DOF limit is the header's."""
+    from paper_2606_09275_amd import _lib
+    m = re.search(r"#define\s+MPM_CG_NOALLOC_MAX_DOFS\s+(\d+)", HEADER.read_text())
+    assert m and int(m.group(1)) == _lib.MPM_CG_NOALLOC_MAX_DOFS

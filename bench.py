@@ -79,6 +79,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["f64", "f32k"], default=None, help="time one precision only")
     ap.add_argument("--calib-copy", action="store_true", help="run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--jitter", type=int, default=None,
+                    help="move the points by the seeded jitter k (domains over several leaves: the general path)")
+    ap.add_argument("--no-c4", action="store_true", help="skip the largest workload's protocol in the output")
     return ap.parse_args()
 
 
@@ -115,6 +118,8 @@ def main():
     lv = m0.arrays()["leaf"].cpu().numpy()
     del m0
     ps = W.make_points(w, lv[:, :3], lv[:, 3])
+    if args.jitter is not None:
+        ps = W.jitter_points(w, ps, args.jitter)
     st = W.make_state(w, ps)
     log(f"[bench] workload {w.name}: {ps.n} points, {lv.shape[0]} leaves ({time.time() - t0:.1f}s)")
     x_dev = torch.from_numpy(ps.x).cuda()
@@ -133,8 +138,10 @@ def main():
     torch.cuda.synchronize()
     build_ms = (time.perf_counter() - t0) * 1e3
     info = mesh.info
+    rp = mesh.arrays()["row_ptr"]
+    max_deg = int(((rp[1::3] - rp[:-1:3]) // 3).max().item()) if info["n_node"] else 0
     log(f"[bench] octree_build {build_ms:.1f} ms: nodes {info['n_node']} hanging {info['n_hang']} "
-        f"nnz {info['nnz']} straddle {info['n_straddle']}")
+        f"nnz {info['nnz']} straddle {info['n_straddle']} widest row {max_deg} nodes")
     nodes = mesh.arrays()["node_ijk"].cpu().numpy()
     u = torch.from_numpy(W.make_u(w, nodes)).cuda()
     lam = torch.from_numpy(W.make_lambda(w, nodes)).cuda()
@@ -210,19 +217,33 @@ def main():
     prim = "f64" if "f64" in results else precs[0]
     R = results[prim]
     n_fast = n - info["n_straddle"]
-    kbytes = 8 if prim == "f64" else 4
-    alg_flops = FLOPS_PER_POINT * n_fast
-    alg_bytes = BYTES_PER_POINT * n + info["nnz"] * kbytes + 3 * info["n_node"] * 16
-    kt_s = R["assemble_kernel_ms"] * 1e-3
-    peak = PEAK_FP64_VEC_TFLOPS if prim == "f64" else PEAK_FP32_VEC_TFLOPS
-    roofline = {
-        "bound": "alu", "kernel": "k_assemble_fast<%s, false>" % ("double" if prim == "f64" else "float"),
-        "achieved": alg_flops / kt_s / 1e12, "peak": peak, "unit": "TFLOP/s",
-        "frac": alg_flops / kt_s / 1e12 / peak, "traffic": measured_traffic(w.name, prim),
-        "flops_per_point": FLOPS_PER_POINT, "points_per_launch": n_fast,
-        "hbm": {"achieved": alg_bytes / kt_s / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": alg_bytes / kt_s / 1e9 / PEAK_HBM_GBS, "bytes_per_launch": alg_bytes},
-    }
+
+    def roofline_of(prec, r):
+        """ALU roofline of the fused kernel (algorithmic flops of its points over its own
+        average launch time) and the HBM roofline of the assembly's two kernels (the fused
+        kernel reads the state and writes sigma and the segment sums; the row gather writes K
+        and f_int): algorithmic bytes over the sum of their average launch times."""
+        kb = 8 if prec == "f64" else 4
+        alg_flops = FLOPS_PER_POINT * n_fast
+        alg_bytes = BYTES_PER_POINT * n + info["nnz"] * kb + 3 * info["n_node"] * 16
+        kt_s = r["assemble_kernel_ms"] * 1e-3
+        kg_s = (r["assemble_kernel_ms"] + r["gather_kernel_ms"]) * 1e-3
+        peak = PEAK_FP64_VEC_TFLOPS if prec == "f64" else PEAK_FP32_VEC_TFLOPS
+        rf = {"bound": "alu", "kernel": "k_assemble_fast<%s, false>" % ("double" if prec == "f64" else "float"),
+              "achieved": alg_flops / kt_s / 1e12, "peak": peak, "unit": "TFLOP/s",
+              "frac": alg_flops / kt_s / 1e12 / peak, "traffic": measured_traffic(w.name, prec),
+              "flops_per_point": FLOPS_PER_POINT, "points_per_launch": n_fast,
+              "kernel_ms": r["assemble_kernel_ms"],
+              "hbm": {"kernels": "k_assemble_fast + k_gather", "achieved": alg_bytes / kg_s / 1e9,
+                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": alg_bytes / kg_s / 1e9 / PEAK_HBM_GBS,
+                      "bytes_per_launch": alg_bytes, "kernels_ms": kg_s * 1e3}}
+        if prec != "f64":
+            # the library is built without packed FP32 instructions: its own ceiling is the
+            # unpacked FP32 rate, equal to the FP64 one
+            rf["frac_of_unpacked_fp32"] = alg_flops / kt_s / 1e12 / PEAK_FP64_VEC_TFLOPS
+        return rf
+
+    roofline = roofline_of(prim, R)
     out = {
         "metric": METRIC, "value": R["value"], "unit": "points/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": R["ms_per_step"], "higher_is_better": True, "scaling": "weak",
@@ -245,19 +266,24 @@ def main():
                                                          "adjoint_points_per_s", "assemble_kernel_ms",
                                                          "gather_kernel_ms", "adjoint_kernel_ms")}
         out["fp32k"]["speedup_assembly_vs_fp64"] = results["f32k"]["assembly_points_per_s"] / R["assembly_points_per_s"]
+        out["fp32k"]["roofline"] = roofline_of("f32k", results["f32k"])
     if not args.only:
         out["dynamic"] = dynamic_assembly(mesh, w, ps, views, u, f_ext, dirichlet, n)
         out["solve"] = newton_solve(mesh, views, u, f_ext, dirichlet, info)
         out["ghost"] = ghost_stabilisation(w, x_dev, l_dev, views, u, f_ext, dirichlet, R["assemble_ms"])
         out["gimp_split"] = gimp_split(mesh, w)
     out["state_gather_runs_ms"] = gather_runs(mesh, packed, sorted_buf)
-    if not args.only and w.name.startswith("c2"):
+    if not args.only and w.name.startswith("c2") and args.jitter is None:
         out["supplementary"] = supplementary(w)
+        if not args.no_c4:
+            out["supplementary"]["c4"] = c4_protocol()
     if "prev_x_s" in w.extra:
         out["protocol"] = tool_protocol(mesh, w, nodes, views, x_dev, perm_buf, leaf_buf, packed, sorted_buf,
                                         f_ext, dirichlet, lam)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, ps, st, nodes, args.cpu_sample)
+        out["cpu_baseline"], errs = cpu_baseline(w, ps, st, nodes, args.cpu_sample)
+        out.setdefault("fp32k", {})["err"] = errs["f32k"]
+        out["fp64_err"] = errs["f64"]
     print(json.dumps(out), flush=True)
 
 
@@ -341,7 +367,8 @@ def supplementary(w_main, reps=5):
         nodes = m.arrays()["node_ijk"].cpu().numpy()
         u = torch.from_numpy(W.make_u(w, nodes)).cuda()
         s = m.sorted_state(st)
-        r = {"points": ps.n, "n_straddle": m.info["n_straddle"], "nnz": m.info["nnz"]}
+        r = {"points": ps.n, "n_straddle": m.info["n_straddle"], "nnz": m.info["nnz"],
+             "sigma_y": w.sy, "yield_fraction": yield_fraction(m, s, u)}
         for prec in ("f64", "f32k"):
             outs = {}
             m.assemble(s, u, prec, out=outs)
@@ -355,11 +382,107 @@ def supplementary(w_main, reps=5):
             ms = e0.elapsed_time(e1) / reps
             r[f"assemble_{prec}_ms"] = ms
             r[f"assembly_{prec}_points_per_s"] = ps.n / (ms * 1e-3)
-        log(f"[bench] {tag}: {ps.n} points ({r['n_straddle']} straddling), assembly FP64 "
+        log(f"[bench] {tag}: {ps.n} points ({r['n_straddle']} straddling, {r['yield_fraction']:.3f} yielding), "
+            f"assembly FP64 "
             f"{r['assemble_f64_ms']:.3f} ms ({r['assembly_f64_points_per_s']:.3e} pts/s), FP32K "
             f"{r['assemble_f32k_ms']:.3f} ms")
         res[tag] = r
         del m, s, outs
+    return res
+
+
+def yield_fraction(m, s, u):
+    """Fraction of the points whose returned stress lies on the yield surface: one FP64
+    assembly with the committed history, tau = J sigma with J = det F_new, and the von Mises
+    stress sqrt(3 J2) of tau against sigma_y (relative slack 1e-9)."""
+    import torch
+    o = m.assemble(s, u, "f64", want_K=False, want_residual=False, commit=True)
+    F = o["F_new"]
+    J = (F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) +
+         F[2] * (F[3] * F[7] - F[4] * F[6]))
+    tau = o["sigma"] * J
+    d = tau.clone()
+    d[:3] -= tau[:3].mean(0)
+    q = torch.sqrt(1.5 * (d[0] ** 2 + d[1] ** 2 + d[2] ** 2 + 2 * (d[3] ** 2 + d[4] ** 2 + d[5] ** 2)))
+    sy = s["sy"]
+    return float((torch.isfinite(sy) & (q >= sy * (1 - 1e-9))).double().mean().item())
+
+
+def c4_protocol(reps=3):
+    """The largest single-GPU workload (moving box tool, about 30 M points in a never-coarsened
+    trail): mesh at the previous tool position, then the timed re-adaptation (octree_build at
+    the current position with the same points), re-sort and state gather, ten assemblies with
+    the FP32 tangent (FP64 f_int; displacement k of the step's Newton iterations), one FP32K
+    adjoint, and the FP64 step (sort + gather + assembly + adjoint, mean of reps)."""
+    import torch
+    import workloads as W
+    from paper_2606_09275_amd.mesh import Mesh
+    w = W.get("c4")
+    t0 = time.time()
+    m0 = Mesh(w.crit())
+    lv = m0.arrays()["leaf"].cpu().numpy()
+    del m0
+    ps = W.make_points(w, lv[:, :3], lv[:, 3])
+    st = W.make_state(w, ps)
+    n = ps.n
+    log(f"[bench] c4: {n} points generated ({time.time() - t0:.1f}s)")
+    x_dev = torch.from_numpy(ps.x).cuda()
+    l_dev = torch.from_numpy(ps.l).cuda()
+    b = list(w.body)
+    dx = float(w.extra["prev_x_s"]) - b[0]
+    prev = dict(w.crit(), body=tuple([b[0] + dx, b[1] + dx] + b[2:] + [0.0] * (8 - len(b))))
+    pm = Mesh(prev, x_dev, l_dev)
+    del pm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mesh = Mesh(w.crit(), x_dev, l_dev)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    info = mesh.info
+    nodes = mesh.arrays()["node_ijk"].cpu().numpy()
+    keys = [("x", 3), ("l", 3), ("vol", 1), ("mass", 1), ("Jn", 1), ("bn", 6), ("E", 1), ("nu", 1), ("sy", 1)]
+    packed = torch.cat([torch.from_numpy(np.asarray(st[k], np.float64).reshape(c, n)) for k, c in keys]).cuda()
+    del st
+    sorted_buf = torch.empty_like(packed)
+    views, r = {}, 0
+    for k, c in keys:
+        v = sorted_buf[r:r + c]
+        views[k] = v.reshape(-1) if c == 1 else v
+        r += c
+    views["g"] = (0.0, 0.0, -9.81)
+    perm_buf = torch.empty(n, dtype=torch.int64, device="cuda")
+    leaf_buf = torch.empty(n, dtype=torch.int32, device="cuda")
+    dirichlet = torch.from_numpy(W.dirichlet_dofs(nodes)).cuda()
+    lam = torch.from_numpy(W.make_lambda(w, nodes)).cuda()
+    mesh.permute(packed, None, out=sorted_buf)
+    f_ext = mesh.external_force(views)
+    prot = tool_protocol(mesh, w, nodes, views, x_dev, perm_buf, leaf_buf, packed, sorted_buf, f_ext, dirichlet, lam)
+    u = torch.from_numpy(W.make_u(w, nodes)).cuda()
+    outs, adj = {}, {}
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+    def step():
+        mesh.point_sort(x_dev, perm_buf, leaf_buf)
+        mesh.permute(packed, perm_buf, out=sorted_buf)
+        mesh.assemble(views, u, "f64", f_ext=f_ext, dirichlet=dirichlet, out=outs)
+        mesh.adjoint(views, u, lam, "f64", out=adj)
+
+    step()
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        step()
+    ev[1].record()
+    torch.cuda.synchronize()
+    step_ms = ev[0].elapsed_time(ev[1]) / reps
+    res = {"points": n, "n_leaf": info["n_leaf"], "n_node": info["n_node"], "nnz": info["nnz"],
+           "readapt_octree_build_ms": build_ms, **prot, "fp64_step_ms": step_ms,
+           "fp64_step_points_per_s": n / (step_ms * 1e-3),
+           "assembly_f32k_points_per_s": n / (prot["assembly_f32k_ms"] * 1e-3)}
+    log(f"[bench] c4: re-adapt {build_ms:.1f} ms, re-sort {prot['resort_ms']:.2f} ms, FP32K assembly "
+        f"{prot['assembly_f32k_ms']:.2f} ms x 10, adjoint {prot['adjoint_f32k_ms']:.2f} ms, FP64 step {step_ms:.2f} ms")
+    del mesh, packed, sorted_buf, views, outs, adj
+    torch.cuda.empty_cache()
     return res
 
 
@@ -542,10 +665,14 @@ def tool_protocol(mesh, w, nodes, views, x_dev, perm_buf, leaf_buf, packed, sort
 
 
 def cpu_baseline(w, ps, st, nodes, sample):
-    """The FP64 oracle (single thread, as written) on a bounded sample of the same workload:
-    every k-th point, assembly (f_int, K, sigma) + adjoint, points per second."""
+    """The FP64 oracle on a bounded sample of the same workload (every k-th point, on a mesh of
+    the same octree): assembly (f_int, K, sigma) + adjoint on one thread, the oracle as
+    written, which is `value`; the assembly again on all the host threads the process may use
+    (per-thread sums added in a fixed order), reported beside it. The oracle's results on the
+    sample are also the reference of the per-result errors of the library's FP64 and FP32
+    tangent paths, run on a library mesh of the same sample points (precision_errors)."""
     import workloads as W
-    from oracle.oracle import OracleMesh
+    from oracle.oracle import OracleMesh, residual
     k = max(1, ps.n // sample)
     idx = np.arange(0, ps.n, k)
     o = OracleMesh(w.crit())
@@ -554,15 +681,67 @@ def cpu_baseline(w, ps, st, nodes, sample):
     u = W.make_u(w, nodes)
     lam = W.make_lambda(w, nodes)
     t0 = time.perf_counter()
-    o.assemble(ss, u)
+    ref = o.assemble(ss, u)
     t1 = time.perf_counter()
     o.adjoint(ss, u, lam)
     t2 = time.perf_counter()
-    log(f"[bench] cpu oracle: {idx.size} points, assemble {t1 - t0:.2f}s adjoint {t2 - t1:.2f}s")
-    return {"value": idx.size / (t2 - t0), "unit": "points/s", "cores": 1, "kind": "oracle",
+    threads = max(1, min(int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0)),
+                         len(os.sched_getaffinity(0))))
+    t3 = time.perf_counter()
+    par = o.assemble_threads(ss, u, threads)
+    t4 = time.perf_counter()
+    agree = float(np.abs(par["K"] - ref["K"]).max() / np.abs(ref["K"]).max())
+    log(f"[bench] cpu oracle: {idx.size} points, assemble {t1 - t0:.2f}s adjoint {t2 - t1:.2f}s (1 thread); "
+        f"assemble on {threads} threads {t4 - t3:.2f}s (K agrees to {agree:.1e})")
+    fe = o.external_force(dict(ss, g=(0.0, 0.0, -9.81)))
+    d = W.dirichlet_dofs(nodes)
+    r_ref, rn_ref = residual(ref["f_int"], fe, d)
+    errs = precision_errors(w, ps, idx, ss, u, d, o, ref, r_ref, rn_ref)
+    base = {"value": idx.size / (t2 - t0), "unit": "points/s", "cores": 1, "kind": "oracle",
             "sample": f"every {k}-th point of the workload ({idx.size} points), FP64 assembly of f_int, K, sigma "
                       f"({t1 - t0:.1f}s) + adjoint ({t2 - t1:.1f}s), single thread",
-            "assembly_points_per_s": idx.size / (t1 - t0), "cpu": _cpu_name(), "host_threads": os.cpu_count()}
+            "assembly_points_per_s": idx.size / (t1 - t0), "cpu": _cpu_name(), "host_threads": os.cpu_count(),
+            "all_cores": {"value": idx.size / (t4 - t3), "unit": "points/s (assembly of f_int, K, sigma)",
+                          "cores": threads, "kind": "oracle, points cut into one contiguous range per thread",
+                          "cpu": _cpu_name(), "max_rel_diff_K_vs_one_thread": agree}}
+    return base, errs
+
+
+def precision_errors(w, ps, idx, ss, u, d, o, ref, r_ref, rn_ref):
+    """Per-result error of the library's FP64 and FP32-tangent assemblies against the FP64
+    oracle on the CPU baseline's sample: the same points on a library mesh of the same
+    octree (its CSR pattern equals the oracle's bit for bit), the same state, displacement,
+    body force and fixed base. Normwise max|diff| / max|ref| for f_int, K, sigma and r;
+    relative error of the residual norm."""
+    import torch
+    import workloads as W
+    from paper_2606_09275_amd.mesh import Mesh
+    m = Mesh(w.crit(), torch.from_numpy(np.ascontiguousarray(ps.x[:, idx])).cuda(),
+             torch.from_numpy(np.ascontiguousarray(ps.l[:, idx])).cuda())
+    perm = m.arrays()["perm"].cpu().numpy()
+    s = m.sorted_state(dict(ss, g=(0.0, 0.0, -9.81)))
+    fe = m.external_force(s)
+    ud = torch.from_numpy(u).cuda()
+    dd = torch.from_numpy(d).cuda()
+
+    def rel(a, b):
+        return float(np.abs(np.asarray(a, np.float64) - b).max() / np.abs(b).max())
+
+    res = {}
+    for prec in ("f64", "f32k"):
+        out = m.assemble(s, ud, prec, f_ext=fe, dirichlet=dd)
+        torch.cuda.synchronize()
+        res[prec] = {"f_int": rel(out["f_int"].cpu().numpy(), ref["f_int"]),
+                     "K": rel(out["K"].cpu().numpy(), ref["K"]),
+                     "sigma": rel(out["sigma"].cpu().numpy(), ref["sigma"][:, perm]),
+                     "r": rel(out["r"].cpu().numpy(), r_ref),
+                     "rnorm": abs(float(out["rnorm"].item()) - rn_ref) / rn_ref,
+                     "points": int(idx.size), "yield_fraction_oracle": float(ref["plastic"].mean()),
+                     "reference": "FP64 oracle on the CPU baseline's sample"}
+        log(f"[bench] {prec} errors vs oracle: " + " ".join(f"{k}={res[prec][k]:.2e}" for k in
+                                                           ("f_int", "K", "sigma", "r", "rnorm")))
+    del m
+    return res
 
 
 def _cpu_name():

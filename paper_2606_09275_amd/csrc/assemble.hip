@@ -32,9 +32,14 @@ struct AsmArgs {
   const int64_t* strad;
   const int32_t* strad_leaf;
   const int32_t* snode;      // rows reached by straddling points
+  const int32_t* srow;       // their launch order (indices into snode)
   const int64_t* sinc_off;   // per such row: its straddling points
   const int32_t* sinc;
   double* grec;              // per straddling point: tangent record of the general path
+  const int64_t* sup_off;    // per straddling point: its support slots
+  const int32_t* sup_id;     // node of each slot
+  const uint32_t* sup_src;   // leaves of the point holding the slot's node, and its vertex in each
+  double* sup_g;             // per slot: S and the spatial gradient (written by k_general_support)
   int64_t n, n_strad;
   mpm_state_t s;
   const double* u;
@@ -648,43 +653,13 @@ static void launch_gather(const mpm_mesh* m, hipStream_t st, const AsmArgs& A) {
 }
 
 // ------------------------------------------------------------------ general path
-// Points whose domain overlaps several leaves: the basis is merged over the leaves the domain
-// overlaps (up to 64 nodes); used by the row kernel below, the body force and the adjoint.
+// Points whose domain overlaps several leaves (up to 8 leaves, so at most 64 support nodes).
 constexpr int kMaxSup = kMaxPointLeaves * 8;
 
-template <typename T>
-__device__ int general_basis(const AsmArgs& A, int64_t t, const double x[3], const double l[3], int32_t* nd, T* S,
-                             T (*dS)[3]) {
-  int ns = 0;
-  for (int q = 0; q < kMaxPointLeaves; ++q) {
-    const int32_t e = A.strad_leaf[t * kMaxPointLeaves + q];
-    if (e < 0) break;
-    T s8[8], d8[8][3];
-    leaf_overlap_basis<T>(A.G, e, A.cell_code[e], x, l, s8, d8);
-    for (int v = 0; v < 8; ++v) {
-      const int32_t id = A.cell_nodes[8 * int64_t(e) + v];
-      int pos = -1;
-      for (int z = 0; z < ns; ++z)
-        if (nd[z] == id) pos = z;
-      if (pos < 0) {
-        pos = ns++;
-        nd[pos] = id;
-        S[pos] = 0;
-        dS[pos][0] = dS[pos][1] = dS[pos][2] = 0;
-      }
-      S[pos] += s8[v];
-      dS[pos][0] += d8[v][0];
-      dS[pos][1] += d8[v][1];
-      dS[pos][2] += d8[v][2];
-    }
-  }
-  return ns;
-}
-
-// Points whose domain overlaps several leaves. A first kernel takes one lane per such point:
-// its update from the leaves it overlaps (basis, deformation, material), the point outputs
-// (stress, committed state, Newmark kinematics) and a record of what the rows need, so that
-// the update is computed once per point rather than once per row the point reaches:
+// A first kernel takes one lane per such point: its update from the leaves it overlaps
+// (basis, deformation, material), the point outputs (stress, committed state, Newmark
+// kinematics) and a record of what the rows need, so that the update is computed once per
+// point rather than once per row the point reaches:
 // (symmetric 3x3 matrices as 6 values in the order xx, yy, zz, xy, yz, xz)
 //   [0, 54)    c dtau for the direction e_k (x) N^T e_j, symmetric, at (3 j + k) 6
 //   [54, 60)   c tau, symmetric                              (c = V_n / J_n)
@@ -692,6 +667,12 @@ __device__ int general_basis(const AsmArgs& A, int64_t t, const double x[3], con
 //   [69, 72)   m_p a_p (Newmark inertia; zero when quasi-static)
 //   [72]       2 m_p / dt^2 (zero when quasi-static)
 __device__ constexpr int kSym6[3][3] = {{0, 3, 5}, {3, 1, 4}, {5, 4, 2}};
+// the same index computed, for indices known only at run time (no table load): with
+// s = r + m, the off-diagonal pairs (0,1), (1,2), (0,2) have s = 1, 3, 2
+__device__ __forceinline__ int sym6(int r, int m) {
+  const int sum = r + m;
+  return r == m ? r : (sum == 2 ? 5 : 2 + ((sum + 1) >> 1));
+}
 template <typename T>
 __global__ __launch_bounds__(64) void k_general_points(AsmArgs A) {
   const int64_t t = int64_t(blockIdx.x) * 64 + threadIdx.x;
@@ -770,17 +751,74 @@ __global__ __launch_bounds__(64) void k_general_points(AsmArgs A) {
   rec[73] = 0.0;
 }
 
-// The rows those points reach: one wavefront per node a, one lane per straddling point whose
-// support holds a (64 at a time, ascending). Each lane evaluates its point's basis over the
-// leaves it overlaps for S_a and grad S_a, adds its force on a, and, K_ab being linear in
-// grad S_b, adds for every (leaf, slot) term of the point its own block to the column of its
-// slot node (LDS additions into the node's three rows); the block is a 9x3 map of the term's
-// spatial gradient, formed from the point's record. The column of a node in row a comes from
-// an open-addressing table of the row's columns in LDS (at least half of it empty, so a probe
-// sequence always ends). Each lane starts its walk over the leaves at its own offset, so that
-// lanes whose points overlap the same leaves do not add into the same columns at once. The
-// force is summed over the lanes in a fixed order; rows and forces are then added to the
-// values the fast path wrote. No global atomics.
+// Merged support of each straddling point, once per assembly: 8 points per 64-lane
+// workgroup, one lane per (point, leaf). Each lane evaluates its leaf's 8 slot functions at
+// the overlap box (values and reference gradients), maps the gradients to the current
+// configuration with the point's dF^-1 (from its record), and stages them in LDS; then each
+// support slot sums the entries of the leaves that hold its node, in ascending leaf order (a
+// fixed order), and writes (S, grad_x S) to the slot. The row kernel below reads these.
+constexpr int kSupPts = 8;  // points per workgroup of k_general_support
+template <typename T>
+__global__ __launch_bounds__(64) void k_general_support(AsmArgs A) {
+  __shared__ double stg[kSupPts][kMaxPointLeaves][8][4];  // 16 KB
+  const int pp = threadIdx.x >> 3, q = threadIdx.x & 7;
+  const int64_t t = int64_t(blockIdx.x) * kSupPts + pp;
+  const bool ok = t < A.n_strad;
+  const int32_t e = ok ? A.strad_leaf[t * kMaxPointLeaves + q] : -1;
+  if (e >= 0) {
+    const int64_t n = A.n, i = A.strad[t];
+    double x[3], l[3];
+    for (int a = 0; a < 3; ++a) {
+      x[a] = A.s.x[a * n + i];
+      l[a] = A.s.l[a * n + i];
+    }
+    T s8[8], d8[8][3];
+    leaf_overlap_basis<T>(A.G, e, A.cell_code[e], x, l, s8, d8);
+    const double* rec = A.grec + t * kGenRec;
+    T Fi[3][3];
+    for (int r = 0; r < 3; ++r)
+      for (int k = 0; k < 3; ++k) Fi[r][k] = T(rec[60 + 3 * r + k]);
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      stg[pp][q][v][0] = double(s8[v]);
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        stg[pp][q][v][1 + k] = double(Fi[0][k] * d8[v][0] + Fi[1][k] * d8[v][1] + Fi[2][k] * d8[v][2]);
+    }
+  }
+  __syncthreads();
+  if (!ok) return;
+  const int64_t off = A.sup_off[t];
+  const int ns = int(A.sup_off[t + 1] - off);
+  for (int z = q; z < ns; z += 8) {
+    const uint32_t src = A.sup_src[off + z];
+    double g[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int qq = 0; qq < kMaxPointLeaves; ++qq)
+      if ((src >> qq) & 1u) {
+        const int v = int((src >> (8 + 3 * qq)) & 7u);
+        for (int c = 0; c < 4; ++c) g[c] += stg[pp][qq][v][c];
+      }
+    double* o = A.sup_g + (off + z) * 4;
+    for (int c = 0; c < 4; ++c) o[c] = g[c];
+  }
+}
+
+// The rows those points reach: one workgroup of four wavefronts per node a, which share the
+// row's accumulator; each wavefront takes batches of 16 of the node's straddling points (batch
+// b of the node goes to wavefront b mod 4). For K_ab = V grad_x S_a . a . grad_x S_b a batch
+// first forms, for each of its points, the 27 values
+//   Mb[r][k][j] = (c dtau(j,k) g_a)_r - (c tau)_rj g_a,k
+// from the point's record and the slot of node a in its support (four lanes per point, into
+// the wavefront's part of LDS), and adds the point's force on node a. Then the (point,
+// support slot) pairs of the batch are dealt to the lanes in order: each lane forms the 3x3
+// block sum_j Mb[r][k][j] g_b,j (+ the inertia term on the diagonal) of its slot node b and
+// adds it to that node's column of the row. All loads of a batch are independent of each
+// other, so they overlap; lanes of different points (and wavefronts) can add to one column
+// at once, so the row additions are LDS atomics (the only unordered sums of the assembly:
+// the fast path and the forces are summed in a fixed order). The row and the force are then
+// added to the values the fast path wrote. The column of a node in row a comes from an
+// open-addressing table of the row's columns in LDS (at least half of it empty, so a probe
+// sequence always ends).
 __host__ __device__ constexpr int col_table_size(int deg) {
   int p = 2;
   while (p < 2 * deg) p <<= 1;
@@ -788,117 +826,224 @@ __host__ __device__ constexpr int col_table_size(int deg) {
 }
 __device__ __forceinline__ unsigned col_hash(int32_t id, int p) { return (unsigned(id) * 2654435761u) & unsigned(p - 1); }
 
+constexpr int kRowWaves = 4;   // wavefronts per row of k_general_rows
+constexpr int kRowBatch = 16;  // straddling points per batch of one wavefront
+constexpr int kMbStride = 32;  // per point: Mb (27 values), S_a, 2 m / dt^2 (padded for 16-byte reads)
+
+// LDS of one wavefront's batch: support offsets, Mb, first task and the point of each task
+__host__ __device__ constexpr size_t row_batch_lds(int tb) {
+  return size_t(kRowBatch) * 8 + size_t(kRowBatch * kMbStride) * size_t(tb) + size_t(kRowBatch) * 4 +
+         size_t(kRowBatch * kMaxSup);
+}
+// LDS bytes of k_general_rows for rows of at most deg block columns, working type of size tb
+__host__ __device__ constexpr size_t general_rows_lds(int deg, int tb) {
+  return size_t(kRowWaves) * row_batch_lds(tb) + size_t(kRowWaves * 4 * 8) + size_t(8) * col_table_size(deg) +
+         size_t(9 * 8) * size_t(deg);
+}
+
+// LDS written by one lane of a wavefront and read by another lane of the same wavefront: the
+// wavefront's LDS operations are performed in order, so only the compiler must not move them
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename T>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3))) void k_general_rows(AsmArgs A) {
+__global__ __launch_bounds__(64 * kRowWaves) void k_general_rows(AsmArgs A, int64_t row0) {
   extern __shared__ __align__(16) unsigned char gsm[];
-  const int64_t na = A.snode[blockIdx.x];
-  const int lane = threadIdx.x;
+  // the row's entry in the straddler tables; each XCD takes one contiguous range of rows, so
+  // that rows sharing straddling points read them through one L2
+  const int64_t rb = A.srow[row0 + xcd_block(blockIdx.x, gridDim.x)];
+  const int64_t na = A.snode[rb];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int64_t r0 = A.row_ptr[3 * na];
   const int deg = int((A.row_ptr[3 * na + 1] - r0) / 3);
   const int tp = col_table_size(deg);
+  // LDS: the wavefronts' batch buffers (fixed size, first, so their alignment is known), the
+  // wavefronts' forces, the column table and the row
+  unsigned char* wb = gsm + size_t(wave) * row_batch_lds(sizeof(T));
+  double* fsum = reinterpret_cast<double*>(gsm + size_t(kRowWaves) * row_batch_lds(sizeof(T)));  // [kRowWaves][3]
   // table entries: node id (high 32 bits) and column (low 32 bits); empty = all ones
-  unsigned long long* ctab = reinterpret_cast<unsigned long long*>(gsm);
-  double* acc = reinterpret_cast<double*>(ctab + tp);  // the row in FP64 for both precisions
+  unsigned long long* ctab = reinterpret_cast<unsigned long long*>(fsum + kRowWaves * 4);
+  double* acc = reinterpret_cast<double*>(ctab + tp);    // the row [9 deg], FP64
+  int64_t* poff = reinterpret_cast<int64_t*>(wb);                              // [kRowBatch]
+  T* mbuf = reinterpret_cast<T*>(poff + kRowBatch);                            // [kRowBatch][kMbStride]
+  int32_t* pref = reinterpret_cast<int32_t*>(mbuf + kRowBatch * kMbStride);   // [kRowBatch]
+  uint8_t* taskpt = reinterpret_cast<uint8_t*>(pref + kRowBatch);             // [kRowBatch kMaxSup]
   const bool wantK = A.K != nullptr;
   if (wantK) {
-    for (int j = lane; j < 9 * deg; j += 64) acc[j] = 0.0;
-    for (int j = lane; j < tp; j += 64) ctab[j] = ~0ull;
+    for (int j = tid; j < 9 * deg; j += 64 * kRowWaves) acc[j] = 0.0;
+    for (int j = tid; j < tp; j += 64 * kRowWaves) ctab[j] = ~0ull;
   }
   __syncthreads();
   if (wantK) {
-    for (int j = lane; j < deg; j += 64) {
+    for (int j = tid; j < deg; j += 64 * kRowWaves) {
       const int32_t id = A.col[r0 + 3 * j] / 3;
       const unsigned long long ent = (static_cast<unsigned long long>(unsigned(id)) << 32) | unsigned(j);
-      for (unsigned h = col_hash(id, tp);; h = (h + 1) & unsigned(tp - 1))
-        if (atomicCAS(ctab + h, ~0ull, ent) == ~0ull) break;
+      for (unsigned hh = col_hash(id, tp);; hh = (hh + 1) & unsigned(tp - 1))
+        if (atomicCAS(ctab + hh, ~0ull, ent) == ~0ull) break;
     }
   }
   __syncthreads();
-  const int64_t n = A.n;
   double fa[3] = {0.0, 0.0, 0.0};
-  const int64_t c0 = A.sinc_off[blockIdx.x], c1 = A.sinc_off[blockIdx.x + 1];
-  for (int64_t cb = c0; cb < c1; cb += 64) {
-    const int64_t e = cb + lane;
-    if (e >= c1) continue;
-    const int64_t t = A.sinc[e];
-    const int64_t i = A.strad[t];
-    const double* rec = A.grec + t * kGenRec;
-    double x[3], l[3];
-    for (int q = 0; q < 3; ++q) {
-      x[q] = A.s.x[q * n + i];
-      l[q] = A.s.l[q * n + i];
+  const int64_t c0 = A.sinc_off[rb], c1 = A.sinc_off[rb + 1];
+  constexpr int64_t kStep = int64_t(kRowWaves) * kRowBatch;
+  // lanes pi, pi + 16, pi + 32, pi + 48 hold the batch's point pi: the point, the slot of node
+  // a in its support, its support slots; the next batch's are loaded while this one runs
+  const int pi = lane & (kRowBatch - 1), part = lane >> 4;
+  auto entry = [&](int64_t cb, int64_t& t, int& za, int64_t& off, int& ns) {
+    t = 0;
+    za = 0;
+    off = 0;
+    ns = 0;
+    if (cb + pi < c1) {
+      const uint32_t ent = uint32_t(A.sinc[cb + pi]);
+      t = int64_t(ent >> 6);
+      za = int(ent & 63u);
+      off = A.sup_off[t];
+      ns = int(A.sup_off[t + 1] - off);
     }
-    const int32_t* lv = A.strad_leaf + t * kMaxPointLeaves;
-    T Sa = 0, dSa[3] = {0, 0, 0};
-    for (int q = 0; q < kMaxPointLeaves && lv[q] >= 0; ++q) {
-      T s8[8], d8[8][3];
-      leaf_overlap_basis<T>(A.G, lv[q], A.cell_code[lv[q]], x, l, s8, d8);
-      for (int v = 0; v < 8; ++v)
-        if (A.cell_nodes[8 * int64_t(lv[q]) + v] == na) {
-          Sa += s8[v];
-          for (int k = 0; k < 3; ++k) dSa[k] += d8[v][k];
-        }
+  };
+  int64_t t, off;
+  int za, ns;
+  entry(c0 + int64_t(wave) * kRowBatch, t, za, off, ns);
+  // the wavefront's batches (its own trip count: only wavefront-level synchronisation inside)
+  for (int64_t cb = c0 + int64_t(wave) * kRowBatch; cb < c1; cb += kStep) {
+    const int nb = int(c1 - cb < kRowBatch ? c1 - cb : kRowBatch);
+    // first task of each point: exclusive prefix of the support sizes over the batch
+    int incl = ns;
+#pragma unroll
+    for (int d = 1; d < kRowBatch; d <<= 1) {
+      const int v = __shfl_up(incl, d, kRowBatch);
+      if (pi >= d) incl += v;
     }
-    T Fi[3][3];
-    for (int r = 0; r < 3; ++r)
-      for (int k = 0; k < 3; ++k) Fi[r][k] = T(rec[60 + 3 * r + k]);
-    T ga[3];
-    for (int k = 0; k < 3; ++k) ga[k] = Fi[0][k] * dSa[0] + Fi[1][k] * dSa[1] + Fi[2][k] * dSa[2];
-    for (int r = 0; r < 3; ++r)
-      fa[r] += rec[54 + kSym6[r][0]] * double(ga[0]) + rec[54 + kSym6[r][1]] * double(ga[1]) +
-               rec[54 + kSym6[r][2]] * double(ga[2]) + double(Sa) * rec[69 + r];
-    if (!wantK) continue;
-    // block_rk = sum_j Mb[r][k][j] g_j for a term of spatial gradient g
-    T Mb[3][3][3];
-    for (int j = 0; j < 3; ++j)
-      for (int k = 0; k < 3; ++k) {
-        const double* d = rec + (3 * j + k) * 6;
-        for (int r = 0; r < 3; ++r)
-          Mb[r][k][j] = T(d[kSym6[r][0]]) * ga[0] + T(d[kSym6[r][1]]) * ga[1] + T(d[kSym6[r][2]]) * ga[2] -
-                        T(rec[54 + kSym6[r][j]]) * ga[k];
+    const int ntask = __shfl(incl, kRowBatch - 1);
+    if (pi < nb) {
+      if (part == 0) {
+        poff[pi] = off;
+        pref[pi] = incl - ns;
+      } else if (part == 1) {
+        for (int z = 0; z < ns; ++z) taskpt[incl - ns + z] = uint8_t(pi);
       }
-    const T c2m = T(rec[72]);
-    int nl = 0;
-    while (nl < kMaxPointLeaves && lv[nl] >= 0) ++nl;
-    for (int qq = 0; qq < nl; ++qq) {
-      const int q = (qq + lane) % nl;
-      T s8[8], d8[8][3];
-      leaf_overlap_basis<T>(A.G, lv[q], A.cell_code[lv[q]], x, l, s8, d8);
-      for (int v = 0; v < 8; ++v) {
-        const int32_t id = A.cell_nodes[8 * int64_t(lv[q]) + v];
-        T gb[3];
-        for (int k = 0; k < 3; ++k) gb[k] = Fi[0][k] * d8[v][0] + Fi[1][k] * d8[v][1] + Fi[2][k] * d8[v][2];
-        int lo = -1;  // block column of node id in row a
-        for (unsigned h = col_hash(id, tp);; h = (h + 1) & unsigned(tp - 1)) {
-          const unsigned long long e = ctab[h];
-          if (e == ~0ull) break;
-          if (int32_t(e >> 32) == id) {
-            lo = int(unsigned(e));
+    }
+    wave_lds_sync();
+    // the first rounds of (point, slot) tasks: their slot data is loaded now, so that these
+    // loads overlap the loads and arithmetic of Mb below
+    constexpr int kPre = 4;
+    int32_t pid[kPre];
+    double pg[kPre][4];
+    int pq[kPre];
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      const int tk = lane + 64 * u;
+      pid[u] = -1;
+      pq[u] = 0;
+      for (int c = 0; c < 4; ++c) pg[u][c] = 0.0;
+      if (wantK && tk < ntask) {
+        const int q = taskpt[tk];
+        const int64_t o = poff[q] + (tk - pref[q]);
+        pq[u] = q;
+        pid[u] = A.sup_id[o];
+        for (int c = 0; c < 4; ++c) pg[u][c] = A.sup_g[o * 4 + c];
+      }
+    }
+    if (pi < nb) {
+      // the record is read in 16-byte pieces: the point's c tau and g_a by each of its four
+      // lanes, and the six values of tangent direction dd = 3 j + k (48 bytes) by lane
+      // dd mod 4, which forms Mb[r][k][j] for r = 0, 1, 2
+      const double* rec = A.grec + t * kGenRec;
+      const double2* gad = reinterpret_cast<const double2*>(A.sup_g + (off + za) * 4);
+      const double2* tv = reinterpret_cast<const double2*>(rec + 54);
+      const double2 g01 = gad[0], g23 = gad[1], t01 = tv[0], t23 = tv[1], t45 = tv[2];
+      const T Sa = T(g01.x);
+      const T ga[3] = {T(g01.y), T(g23.x), T(g23.y)};
+      const T ct[6] = {T(t01.x), T(t01.y), T(t23.x), T(t23.y), T(t45.x), T(t45.y)};
+      T* mb = mbuf + pi * kMbStride;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const int dd = part + 4 * i;
+        if (dd < 9) {
+          const double2* dv = reinterpret_cast<const double2*>(rec + 6 * dd);
+          const double2 d01 = dv[0], d23 = dv[1], d45 = dv[2];
+          const T d6[6] = {T(d01.x), T(d01.y), T(d23.x), T(d23.y), T(d45.x), T(d45.y)};
+          const int j = dd / 3, k = dd - 3 * j;
+          const T gk = k == 0 ? ga[0] : (k == 1 ? ga[1] : ga[2]);
+#pragma unroll
+          for (int r = 0; r < 3; ++r) {
+            const int sj = sym6(r, j);
+            const T trj = sj == 0 ? ct[0] : sj == 1 ? ct[1] : sj == 2 ? ct[2] : sj == 3 ? ct[3] : sj == 4 ? ct[4] : ct[5];
+            mb[(3 * r + k) * 3 + j] = d6[kSym6[r][0]] * ga[0] + d6[kSym6[r][1]] * ga[1] + d6[kSym6[r][2]] * ga[2] -
+                                      trj * gk;
+          }
+        }
+      }
+      if (part == 0) {
+        mb[27] = Sa;
+        mb[28] = T(rec[72]);
+        for (int r = 0; r < 3; ++r)
+          fa[r] += rec[54 + kSym6[r][0]] * double(ga[0]) + rec[54 + kSym6[r][1]] * double(ga[1]) +
+                   rec[54 + kSym6[r][2]] * double(ga[2]) + double(Sa) * rec[69 + r];
+      }
+    }
+    entry(cb + kStep, t, za, off, ns);  // the next batch of this wavefront
+    wave_lds_sync();
+    if (wantK) {
+      auto task = [&](int q, int32_t id, const double* g) {
+        const T sb = T(g[0]);
+        const T gb[3] = {T(g[1]), T(g[2]), T(g[3])};
+        int lo = -1;  // block column of the slot's node in row a
+        for (unsigned hh = col_hash(id, tp);; hh = (hh + 1) & unsigned(tp - 1)) {
+          const unsigned long long en = ctab[hh];
+          if (en == ~0ull) break;
+          if (int32_t(en >> 32) == id) {
+            lo = int(unsigned(en));
             break;
           }
         }
         if (lo < 0) {
-          raise(A.err, MPM_ESTENCIL, i);
-          continue;
+          raise(A.err, MPM_ESTENCIL, na);
+          return;
         }
+        const T* M = mbuf + q * kMbStride;
+        const T ms = M[28] * M[27] * sb;  // inertia: (2 m / dt^2) S_a S_b on the diagonal
+#pragma unroll
         for (int r = 0; r < 3; ++r)
+#pragma unroll
           for (int k = 0; k < 3; ++k) {
-            T val = Mb[r][k][0] * gb[0] + Mb[r][k][1] * gb[1] + Mb[r][k][2] * gb[2];
-            if (r == k) val += c2m * Sa * s8[v];
+            const int rk = 3 * r + k;
+            T val = M[3 * rk] * gb[0] + M[3 * rk + 1] * gb[1] + M[3 * rk + 2] * gb[2];
+            if (r == k) val += ms;
             atomicAdd(acc + r * 3 * deg + 3 * lo + k, double(val));
           }
+      };
+#pragma unroll
+      for (int u = 0; u < kPre; ++u)
+        if (pid[u] >= 0) task(pq[u], pid[u], pg[u]);
+      for (int tk = lane + 64 * kPre; tk < ntask; tk += 64) {
+        const int q = taskpt[tk];
+        const int64_t o = poff[q] + (tk - pref[q]);
+        double g[4];
+        for (int c = 0; c < 4; ++c) g[c] = A.sup_g[o * 4 + c];
+        task(q, A.sup_id[o], g);
       }
     }
+    wave_lds_sync();  // the batch buffers are rewritten by the wavefront's next batch
   }
-  // forces of the lanes' points in lane order, then the rows
+  // forces: lanes in a fixed order within each wavefront, then the wavefronts in order
 #pragma unroll
   for (int off = 1; off < 64; off <<= 1)
     for (int r = 0; r < 3; ++r) fa[r] += __shfl_xor(fa[r], off);
+  if (lane < 3) fsum[3 * wave + lane] = fa[lane];
   __syncthreads();
-  if (lane < 3) A.f[3 * na + lane] += fa[lane];
+  if (tid < 3) {
+    double f = 0.0;
+    for (int w = 0; w < kRowWaves; ++w) f += fsum[3 * w + tid];
+    A.f[3 * na + tid] += f;
+  }
   if (wantK) {
     T* Kout = reinterpret_cast<T*>(A.K);
-    for (int j = lane; j < 9 * deg; j += 64)
+    for (int j = tid; j < 9 * deg; j += 64 * kRowWaves)
       if (acc[j] != 0.0) Kout[r0 + j] += T(acc[j]);
   }
 }
@@ -939,21 +1084,45 @@ __global__ __launch_bounds__(64) void k_external_fast(AsmArgs A) {
                          [&](int sg, int v, double sum) { A.segF[(seg0 + sg) * 24 + v] = sum; });
 }
 
-__global__ void k_external_force_general(AsmArgs A) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= A.n_strad) return;
-  const int64_t i = A.strad[t], n = A.n;
-  double x[3], l[3];
-  for (int a = 0; a < 3; ++a) {
-    x[a] = A.s.x[a * n + i];
-    l[a] = A.s.l[a * n + i];
+// Body force of the points whose domain overlaps several leaves, gathered by rows in a fixed
+// order: one wavefront per node a reached by such points; lane e takes the node's e-th
+// point, whose support slot of a lists the point's leaves that hold a and a's vertex in each
+// (the basis value S_a is the sum of those leaves' terms, in ascending leaf order); the
+// lanes' S_a m_p g are summed in lane order and added to the gathered value.
+__global__ __launch_bounds__(64) void k_external_rows(AsmArgs A) {
+  const int64_t rb = blockIdx.x;
+  const int64_t na = A.snode[rb];
+  const int lane = threadIdx.x;
+  const int64_t n = A.n;
+  double fa[3] = {0.0, 0.0, 0.0};
+  const int64_t c0 = A.sinc_off[rb], c1 = A.sinc_off[rb + 1];
+  for (int64_t e = c0 + lane; e < c1; e += 64) {
+    const uint32_t ent = uint32_t(A.sinc[e]);
+    const int64_t t = int64_t(ent >> 6);
+    const int za = int(ent & 63u);
+    const uint32_t src = A.sup_src[A.sup_off[t] + za];
+    const int64_t i = A.strad[t];
+    double x[3], l[3];
+    for (int c = 0; c < 3; ++c) {
+      x[c] = A.s.x[c * n + i];
+      l[c] = A.s.l[c * n + i];
+    }
+    double Sa = 0.0;
+    for (int q = 0; q < kMaxPointLeaves; ++q)
+      if ((src >> q) & 1u) {
+        const int32_t lf = A.strad_leaf[t * kMaxPointLeaves + q];
+        double S[8], dS[8][3];
+        leaf_overlap_basis<double>(A.G, lf, A.cell_code[lf], x, l, S, dS);
+        const int v = int((src >> (8 + 3 * q)) & 7u);
+        for (int w = 0; w < 8; ++w) Sa += w == v ? S[w] : 0.0;  // select without dynamic register indexing
+      }
+    const double m = A.s.mass[i];
+    for (int r = 0; r < 3; ++r) fa[r] += Sa * m * A.s.g[r];
   }
-  int32_t nd[kMaxSup];
-  double S[kMaxSup], dS[kMaxSup][3];
-  const int ns = general_basis<double>(A, t, x, l, nd, S, dS);
-  const double m = A.s.mass[i];
-  for (int v = 0; v < ns; ++v)
-    for (int r = 0; r < 3; ++r) atomicAdd(A.f + 3 * int64_t(nd[v]) + r, S[v] * m * A.s.g[r]);
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1)
+    for (int r = 0; r < 3; ++r) fa[r] += __shfl_xor(fa[r], off);
+  if (lane < 3) A.f[3 * na + lane] += fa[lane];
 }
 
 // ------------------------------------------------------------------ residual
@@ -997,16 +1166,12 @@ __global__ __launch_bounds__(256) void k_norm_final(const double* __restrict__ p
 // d tau_a/dE = tau_a/E, d tau_a/dnu = lam' tr(eps) + 2 G' eps_a; plastic points (radial return
 // onto the von Mises circle, direction independent of E and nu) d tau_a/dE = tr(eps)/(3(1-2nu)),
 // d tau_a/dnu = 2E tr(eps)/(3(1-2nu)^2), d tau_a/dsy = sqrt(2/3) s^_a.
-template <typename T, int NS>
-__device__ __forceinline__ void adjoint_point(const AsmArgs& A, int64_t i, int ns, const int32_t* nd, const T (*dS)[3]) {
-  const int64_t n = A.n;
-  // H = sum_v u_v (x) dS_v and Gp = sum_v lambda_v (x) dS_v together (G = Gp dF^-1 below),
-  // so that the basis gradients are dead before the material update
-  T H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  T Gp[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+// H += sum_v u_v (x) dS_v and Gp += sum_v lambda_v (x) dS_v over the 8 slots of one leaf
+template <typename T>
+__device__ __forceinline__ void adjoint_accumulate(const AsmArgs& A, const int32_t* nd, const T (*dS)[3], T H[3][3],
+                                                   T Gp[3][3]) {
 #pragma unroll
-  for (int v = 0; v < NS; ++v) {
-    if (v >= ns) break;
+  for (int v = 0; v < 8; ++v) {
     const double* uv = A.u + 3 * int64_t(nd[v]);
     const double* lv = A.lam + 3 * int64_t(nd[v]);
     for (int r = 0; r < 3; ++r) {
@@ -1017,6 +1182,14 @@ __device__ __forceinline__ void adjoint_point(const AsmArgs& A, int64_t i, int n
       }
     }
   }
+}
+
+// the point's derivatives from H = sum_v u_v (x) dS_v and Gp = sum_v lambda_v (x) dS_v (both
+// sums run over the point's (leaf, slot) terms, so domains over several leaves need no merged
+// support; G = Gp dF^-1 below, and the basis gradients are dead before the material update)
+template <typename T>
+__device__ __forceinline__ void adjoint_point(const AsmArgs& A, int64_t i, const T H[3][3], const T Gp[3][3]) {
+  const int64_t n = A.n;
   T F[3][3], Fi[3][3];
   for (int r = 0; r < 3; ++r)
     for (int q = 0; q < 3; ++q) F[r][q] = H[r][q] + (r == q ? T(1) : T(0));
@@ -1093,7 +1266,10 @@ __global__ __launch_bounds__(64) void k_adjoint_fast(AsmArgs A) {
   T S[8], dS[8][3];
   leaf_overlap_basis<T>(A.G, e, A.cell_code[e], x, l, S, dS);
   for (int v = 0; v < 8; ++v) nd[v] = A.cell_nodes[8 * int64_t(e) + v];
-  adjoint_point<T, 8>(A, i, 8, nd, dS);
+  T H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  T Gp[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  adjoint_accumulate<T>(A, nd, dS, H, Gp);
+  adjoint_point<T>(A, i, H, Gp);
 }
 
 template <typename T>
@@ -1106,10 +1282,17 @@ __global__ __launch_bounds__(64) void k_adjoint_general(AsmArgs A) {
     x[a] = A.s.x[a * n + i];
     l[a] = A.s.l[a * n + i];
   }
-  int32_t nd[kMaxSup];
-  T S[kMaxSup], dS[kMaxSup][3];
-  const int ns = general_basis<T>(A, t, x, l, nd, S, dS);
-  adjoint_point<T, kMaxSup>(A, i, ns, nd, dS);
+  T H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  T Gp[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  const int32_t* lv = A.strad_leaf + t * kMaxPointLeaves;
+  for (int q = 0; q < kMaxPointLeaves && lv[q] >= 0; ++q) {
+    int32_t nd[8];
+    T S[8], dS[8][3];
+    leaf_overlap_basis<T>(A.G, lv[q], A.cell_code[lv[q]], x, l, S, dS);
+    for (int v = 0; v < 8; ++v) nd[v] = A.cell_nodes[8 * int64_t(lv[q]) + v];
+    adjoint_accumulate<T>(A, nd, dS, H, Gp);
+  }
+  adjoint_point<T>(A, i, H, Gp);
 }
 
 static AsmArgs make_args(const mpm_mesh* m, const mpm_state_t* s) {
@@ -1134,9 +1317,14 @@ static AsmArgs make_args(const mpm_mesh* m, const mpm_state_t* s) {
   A.strad = m->d_strad;
   A.strad_leaf = m->d_strad_leaf;
   A.snode = m->d_snode;
+  A.srow = m->d_srow;
   A.sinc_off = m->d_sinc_off;
   A.sinc = m->d_sinc;
   A.grec = m->d_grec;
+  A.sup_off = m->d_sup_off;
+  A.sup_id = m->d_sup_id;
+  A.sup_src = m->d_sup_src;
+  A.sup_g = m->d_sup_g;
   A.n = m->n_point;
   A.n_strad = m->n_straddle;
   A.s = *s;
@@ -1169,8 +1357,7 @@ extern "C" int32_t mpm_external_force(const mpm_mesh_t* m, const mpm_state_t* s,
   }
   // every f_ext entry is written by the gather (zero where no point contributes)
   launch_gather<double>(m, st, A);
-  if (m->n_straddle)
-    hipLaunchKernelGGL(k_external_force_general, dim3((m->n_straddle + 63) / 64), dim3(64), 0, st, A);
+  if (m->n_snode) hipLaunchKernelGGL(k_external_rows, dim3(unsigned(m->n_snode)), dim3(64), 0, st, A);
   MPM_HIP(hipGetLastError());
   return read_error(const_cast<mpm_mesh*>(m), st, "mpm_external_force");
 }
@@ -1249,16 +1436,32 @@ static int32_t assemble_impl(const mpm_mesh_t* m, const AsmArgs& A, int32_t prec
   if (precision == MPM_F64) launch_gather<double>(m, st, A);
   else launch_gather<float>(m, st, A);
   if (timed) MPM_HIP(hipEventRecord(mm->ev[4], st));
+  if (m->n_snode && general_rows_lds(int(m->max_deg), 8) > size_t(160) * 1024) {
+    set_error(MPM_ESTENCIL, "assembly: a row couples more nodes than the general-path row kernel holds in LDS");
+    return MPM_ESTENCIL;
+  }
   if (m->n_snode) {  // rows reached by points whose domain overlaps several leaves
     const dim3 pgrid(unsigned((m->n_straddle + 63) / 64));
     if (precision == MPM_F64) hipLaunchKernelGGL(k_general_points<double>, pgrid, dim3(64), 0, st, A);
     else hipLaunchKernelGGL(k_general_points<float>, pgrid, dim3(64), 0, st, A);
-    const dim3 grid(unsigned(m->n_snode));
-    const size_t tab = size_t(8) * col_table_size(int(m->max_deg));  // column table of the longest row
-    if (precision == MPM_F64)
-      hipLaunchKernelGGL(k_general_rows<double>, grid, dim3(64), tab + size_t(9 * 8) * m->max_deg, st, A);
-    else
-      hipLaunchKernelGGL(k_general_rows<float>, grid, dim3(64), tab + size_t(9 * 8) * m->max_deg, st, A);
+    const dim3 sgrid(unsigned((m->n_straddle + kSupPts - 1) / kSupPts));
+    if (precision == MPM_F64) hipLaunchKernelGGL(k_general_support<double>, sgrid, dim3(64), 0, st, A);
+    else hipLaunchKernelGGL(k_general_support<float>, sgrid, dim3(64), 0, st, A);
+    // narrow rows with LDS for kNarrowRow columns, then the rest with LDS for the widest row
+    const int64_t nn = m->n_snode_narrow, nw = m->n_snode - nn;
+    const int tb = precision == MPM_F64 ? 8 : 4;
+    const int dn = std::min<int>(kNarrowRow, int(m->max_deg));
+    if (precision == MPM_F64) {
+      if (nn) hipLaunchKernelGGL(k_general_rows<double>, dim3(unsigned(nn)), dim3(64 * kRowWaves),
+                                 general_rows_lds(dn, tb), st, A, int64_t(0));
+      if (nw) hipLaunchKernelGGL(k_general_rows<double>, dim3(unsigned(nw)), dim3(64 * kRowWaves),
+                                 general_rows_lds(int(m->max_deg), tb), st, A, nn);
+    } else {
+      if (nn) hipLaunchKernelGGL(k_general_rows<float>, dim3(unsigned(nn)), dim3(64 * kRowWaves),
+                                 general_rows_lds(dn, tb), st, A, int64_t(0));
+      if (nw) hipLaunchKernelGGL(k_general_rows<float>, dim3(unsigned(nw)), dim3(64 * kRowWaves),
+                                 general_rows_lds(int(m->max_deg), tb), st, A, nn);
+    }
   }
   // ghost penalty (Section 4): after every point term, before the residual
   if (const int32_t rg = ghost_apply(m, &A.s, A.u, precision, K_vals, f_int, st)) return rg;

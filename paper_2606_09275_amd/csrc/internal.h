@@ -54,6 +54,7 @@ __host__ __device__ inline uint64_t compact3(uint64_t v) {
 
 constexpr int kMaxPointLeaves = 8; // leaves a point domain may overlap (one boundary per axis)
 constexpr int kGenRec = 74;        // doubles per straddling point: the general path's tangent record
+constexpr int kNarrowRow = 128;    // rows of at most this many block columns run with less LDS
 
 // per-leaf constraint code: bits 0..7 hanging vertices, bits 8..10 child index in the parent
 __host__ __device__ inline int code_hmask(int32_t code) { return code & 0xff; }
@@ -115,8 +116,19 @@ struct mpm_mesh {
   // straddling points (indices into d_strad) whose support holds it, in ascending order
   int64_t n_snode = 0;
   int32_t* d_snode = nullptr;       // n_snode
+  // the same rows in launch order: those of at most kNarrowRow block columns first (their
+  // kernel takes less LDS), then the rest; n_snode_narrow of the first kind
+  int32_t* d_srow = nullptr;        // n_snode indices into d_snode
+  int64_t n_snode_narrow = 0;
   int64_t* d_sinc_off = nullptr;    // n_snode + 1
   int32_t* d_sinc = nullptr;
+  // support of each straddling point in slot order (the union of its leaves' slot nodes in
+  // first-seen order): slots d_sup_off[t] .. d_sup_off[t + 1] of the arrays below
+  int64_t* d_sup_off = nullptr;     // n_straddle + 1
+  int32_t* d_sup_id = nullptr;      // node of each slot
+  uint32_t* d_sup_src = nullptr;    // per slot: bit q (0..7) = leaf q of the point holds the node,
+                                    // bits 8 + 3q .. 10 + 3q = its vertex in that leaf
+  double* d_sup_g = nullptr;        // per slot, written by each assembly: S and the spatial gradient
   mpm::DevErr* d_err = nullptr;
   mpm::DevErr* h_err = nullptr;     // pinned host copy of the error word
   hipEvent_t err_ev = nullptr;      // marks the error-word copy (polled, no blocking sync)

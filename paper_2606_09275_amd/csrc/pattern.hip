@@ -89,6 +89,28 @@ __global__ void k_strad_nsup(const int32_t* __restrict__ sleaf, int64_t ns, cons
   int32_t sup[kMaxPointLeaves * 8];
   cnt[t] = strad_support(sleaf, t, cell_nodes, sup);
 }
+// support of each straddling point in slot order, and for each slot the leaves of the point
+// that hold its node (bit q) with the node's vertex in each (3 bits at 8 + 3 q)
+__global__ void k_strad_slots(const int32_t* __restrict__ sleaf, int64_t ns, const int32_t* __restrict__ cell_nodes,
+                              const int64_t* __restrict__ off, int32_t* __restrict__ sup_id,
+                              uint32_t* __restrict__ sup_src) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= ns) return;
+  int32_t sup[kMaxPointLeaves * 8];
+  const int k = strad_support(sleaf, t, cell_nodes, sup);
+  for (int z = 0; z < k; ++z) {
+    uint32_t src = 0;
+    for (int q = 0; q < kMaxPointLeaves; ++q) {
+      const int32_t e = sleaf[t * kMaxPointLeaves + q];
+      if (e < 0) break;
+      for (int v = 0; v < 8; ++v)
+        if (cell_nodes[8 * int64_t(e) + v] == sup[z]) src |= (1u << q) | (uint32_t(v) << (8 + 3 * q));
+    }
+    sup_id[off[t] + z] = sup[z];
+    sup_src[off[t] + z] = src;
+  }
+}
+
 // (support node, straddling point) incidences
 __global__ void k_strad_inc(const int32_t* __restrict__ sleaf, int64_t ns, const int32_t* __restrict__ cell_nodes,
                             const int64_t* __restrict__ off, uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
@@ -96,9 +118,9 @@ __global__ void k_strad_inc(const int32_t* __restrict__ sleaf, int64_t ns, const
   if (t >= ns) return;
   int32_t sup[kMaxPointLeaves * 8];
   const int k = strad_support(sleaf, t, cell_nodes, sup);
-  for (int z = 0; z < k; ++z) {
+  for (int z = 0; z < k; ++z) {  // the point and the node's slot in its support
     key[off[t] + z] = uint32_t(sup[z]);
-    val[off[t] + z] = uint32_t(t);
+    val[off[t] + z] = (uint32_t(t) << 6) | uint32_t(z);
   }
 }
 __global__ void k_key_runs(const uint32_t* __restrict__ key, int64_t n, int32_t* __restrict__ cnt) {
@@ -560,8 +582,13 @@ int32_t gpu_build_pattern(mpm_mesh* m, const double* dx, const double* dl, hipSt
     MPM_HIP(hipMalloc(&m->d_gf_sc, size_t(nf) * 8));
   }
 
-  // rows reached by straddling points, each with its points in ascending order
+  // rows reached by straddling points, each with its points in ascending order; an entry
+  // holds the point and the slot of the row's node in its support (t 64 + slot)
   m->n_snode = 0;
+  if (ns >= (int64_t(1) << 26)) {
+    set_error(MPM_ESTENCIL, "octree_build: more than 2^26 point domains overlap several leaves");
+    return MPM_ESTENCIL;
+  }
   if (ns) {
     DevBuf sc, so, sk, sv, skt, svt, sh, rcn, ro;
     if ((rc = sc.alloc(size_t(ns) * 4, "octree_build: straddle supports")) ||
@@ -583,6 +610,14 @@ int32_t gpu_build_pattern(mpm_mesh* m, const double* dx, const double* dl, hipSt
       return rc;
     hipLaunchKernelGGL(k_strad_inc, grid_of(ns), dim3(256), 0, st, m->d_strad_leaf, ns, m->d_cell_nodes,
                        so.as<int64_t>(), sk.as<uint32_t>(), sv.as<uint32_t>());
+    // the support of each point in slot order, kept with the mesh for the row kernel
+    MPM_HIP(hipMalloc(&m->d_sup_off, size_t(ns + 1) * 8));
+    MPM_HIP(hipMalloc(&m->d_sup_id, size_t(std::max<int64_t>(1, ninc)) * 4));
+    MPM_HIP(hipMalloc(&m->d_sup_src, size_t(std::max<int64_t>(1, ninc)) * 4));
+    MPM_HIP(hipMalloc(&m->d_sup_g, size_t(std::max<int64_t>(1, ninc)) * 4 * 8));
+    MPM_HIP(hipMemcpyAsync(m->d_sup_off, so.as<int64_t>(), size_t(ns + 1) * 8, hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_strad_slots, grid_of(ns), dim3(256), 0, st, m->d_strad_leaf, ns, m->d_cell_nodes,
+                       so.as<int64_t>(), m->d_sup_id, m->d_sup_src);
     uint32_t *ks2 = sk.as<uint32_t>(), *vs2 = sv.as<uint32_t>();
     if ((rc = radix_sort(sk.as<uint32_t>(), sv.as<uint32_t>(), ninc, bits_for(nn), skt.as<uint32_t>(),
                          svt.as<uint32_t>(), sh.as<uint32_t>(), sh.as<uint32_t>() + size_t(nblk2) * 256, st, &ks2,
@@ -597,6 +632,23 @@ int32_t gpu_build_pattern(mpm_mesh* m, const double* dx, const double* dl, hipSt
     hipLaunchKernelGGL(k_run_tables, grid_of(ninc), dim3(256), 0, st, ks2, vs2, rcn.as<int32_t>(), ro.as<int64_t>(),
                        ninc, m->d_snode, m->d_sinc_off, m->d_sinc);
     MPM_HIP(hipGetLastError());
+    // launch order of those rows: narrow rows first (stable), from their widths on the host
+    std::vector<int32_t> node(size_t(m->n_snode));
+    std::vector<int64_t> rp(size_t(3 * m->n_node + 1));
+    MPM_HIP(hipMemcpyAsync(node.data(), m->d_snode, node.size() * 4, hipMemcpyDeviceToHost, st));
+    MPM_HIP(hipMemcpyAsync(rp.data(), m->d_row_ptr, rp.size() * 8, hipMemcpyDeviceToHost, st));
+    MPM_HIP(hipStreamSynchronize(st));
+    std::vector<int32_t> order;
+    order.reserve(node.size());
+    for (int pass = 0; pass < 2; ++pass)
+      for (size_t b = 0; b < node.size(); ++b) {
+        const int64_t a = node[b];
+        const bool narrow = (rp[size_t(3 * a + 1)] - rp[size_t(3 * a)]) / 3 <= kNarrowRow;
+        if (narrow == (pass == 0)) order.push_back(int32_t(b));
+        if (pass == 0 && narrow) ++m->n_snode_narrow;
+      }
+    MPM_HIP(hipMalloc(&m->d_srow, std::max<size_t>(1, order.size()) * 4));
+    MPM_HIP(hipMemcpyAsync(m->d_srow, order.data(), order.size() * 4, hipMemcpyHostToDevice, st));
     MPM_HIP(hipStreamSynchronize(st));
   }
 

@@ -100,6 +100,10 @@ typedef struct {
 int32_t orc_assemble(const orc_mesh* m, const orc_state* s, const double* u, double* f_int, double* K,
                      double* sigma6, double* Fnew9, double* be6, uint8_t* plastic, double* qtrial,
                      int64_t* bad_index);
+/* orc_assemble on nthreads host threads (timing of the oracle on all cores): per-thread f_int and
+ * K added in thread order; sigma6 as orc_assemble (may be NULL). */
+int32_t orc_assemble_threads(const orc_mesh* m, const orc_state* s, const double* u, double* f_int, double* K,
+                             double* sigma6, int32_t nthreads, int64_t* bad_index);
 int32_t orc_external_force(const orc_mesh* m, const orc_state* s, double* f_ext);
 /* Newmark (gamma = 1, beta = 1/2) inertia term: f_iner over 3*n_indep DOFs, (2/dt^2) x the
  * consistent mass added into K (CSR pattern; may be NULL), point acceleration and updated

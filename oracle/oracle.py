@@ -22,7 +22,8 @@ _f64 = np.float64
 
 def build(verbose: bool = False) -> Path:
     """Compile the oracle with gcc (plain C11, FP64, no FMA contraction)."""
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-Wall", "-Wno-unused-function",
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp", "-Wall",
+           "-Wno-unused-function",
            "-o", str(LIB)] + [str(HERE / s) for s in SOURCES] + ["-lm"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -70,6 +71,8 @@ def lib():
         L.orc_material_point.argtypes = [vp, vp, C.c_double, C.c_double, C.c_double, C.c_double, vp, vp, vp, vp, vp]
         L.orc_assemble.restype = C.c_int32
         L.orc_assemble.argtypes = [vp, C.POINTER(_State), vp, vp, vp, vp, vp, vp, vp, vp, i64p]
+        L.orc_assemble_threads.restype = C.c_int32
+        L.orc_assemble_threads.argtypes = [vp, C.POINTER(_State), vp, vp, vp, vp, C.c_int32, i64p]
         L.orc_external_force.restype = C.c_int32
         L.orc_external_force.argtypes = [vp, C.POINTER(_State), vp]
         L.orc_mesh_set_ghost.argtypes = [vp, C.c_int32]
@@ -267,6 +270,23 @@ class OracleMesh:
         if code != 0:
             raise OracleError(code, bad.value)
         return dict(f_int=f, K=K, sigma=sig, Fnew=Fnew, be=be, plastic=pl, q_trial=q)
+
+    def assemble_threads(self, s: dict, u: np.ndarray, nthreads: int, want_K: bool = True) -> dict:
+        """orc_assemble on nthreads host threads (f_int, K, sigma; per-thread sums added in
+        thread order). For timing the oracle on all cores."""
+        c = self.counts()
+        n = self.n_point
+        st = self._state(s)
+        u = np.ascontiguousarray(u, dtype=_f64)
+        f = np.zeros(3 * c["n_node"], _f64)
+        K = np.zeros(c["nnz"], _f64) if want_K else None
+        sig = np.zeros((6, n), _f64)
+        bad = C.c_int64(-1)
+        code = lib().orc_assemble_threads(self.h, C.byref(st), _p(u), _p(f), _p(K), _p(sig), int(nthreads),
+                                          C.byref(bad))
+        if code != 0:
+            raise OracleError(code, bad.value)
+        return dict(f_int=f, K=K, sigma=sig)
 
     def external_force(self, s: dict) -> np.ndarray:
         st = self._state(s)

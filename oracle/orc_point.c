@@ -5,7 +5,11 @@
 #include "orc_internal.h"
 #include <complex.h>
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ---------------------------------------------------------------- GIMP basis
  * S_vp = (1/V_p) sum_K int_{Omega_p cap Omega_K} phi~_vK dx (Section 3.2, GIMP basis),
@@ -214,7 +218,7 @@ int32_t orc_material_point(const double dF9[9], const double bn6[6], double Jn, 
 
   /* consistent spatial tangent a_ijkl = (1/2J) (D:L:B)_ijkl - sigma_il delta_jk with
    * D = dtau/deps (algorithmic, closed form), L = d ln b / d b (spectral), B = d b/d(grad u) */
-  static double D[3][3][3][3], L[3][3][3][3], B[3][3][3][3], DL[3][3][3][3];
+  double D[3][3][3][3], L[3][3][3][3], B[3][3][3][3], DL[3][3][3][3];
   double th[3][3];
   for (int a = 0; a < 3; a++) for (int b = 0; b < 3; b++) th[a][b] = a == b ? 1.0 / P.x[a] : theta_ab(P.x[a], P.x[b]);
   for (int i = 0; i < 3; i++)
@@ -296,57 +300,128 @@ static int64_t csr_find(const orc_mesh* m, int64_t row, int32_t colv) {
 }
 
 /* Updated-Lagrangian weak form (Section 2.1): f_v = sum_p V_p sigma_p grad_x S_vp with
- * V_p = det(dF) V_n, and K = d f_int / d u with the basis frozen over the step. */
+ * V_p = det(dF) V_n, and K = d f_int / d u with the basis frozen over the step. One point's
+ * share, added into f_int and K; the per-point outputs are written when their arrays are given. */
+static int32_t assemble_point(const orc_mesh* m, const orc_state* s, const double* u, int64_t p, orc_kin* k,
+                              double* f_int, double* K, double* sigma6, double* Fnew9, double* be6,
+                              uint8_t* plastic, double* qtrial) {
+  int64_t n = m->np;
+  double a[81];
+  int st = kinematics(m, s, p, u, k);
+  if (st) return st;
+  double bn[6], sig[6], tau[6], be[6], info[3];
+  for (int c = 0; c < 6; c++) bn[c] = s->bn[c * n + p];
+  st = orc_material_point((const double*)k->dF, bn, s->Jn[p], s->E[p], s->nu[p], s->sy[p], sig, tau, K ? a : NULL, be,
+                          info);
+  if (st) return st;
+  if (sigma6) for (int c = 0; c < 6; c++) sigma6[c * n + p] = sig[c];
+  if (be6) for (int c = 0; c < 6; c++) be6[c * n + p] = be[c];
+  if (plastic) plastic[p] = (uint8_t)info[0];
+  if (qtrial) qtrial[p] = info[1];
+  if (Fnew9 && s->Fn) {
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) {
+        double t = 0;
+        for (int mm = 0; mm < 3; mm++) t += k->dF[i][mm] * s->Fn[(3 * mm + j) * n + p];
+        Fnew9[(3 * i + j) * n + p] = t;
+      }
+  }
+  double S3[3][3];
+  sym_from6(sig, S3);
+  double V = k->Jd * s->vol[p];
+  for (int v = 0; v < k->ns; v++)
+    for (int i = 0; i < 3; i++) {
+      double t = 0;
+      for (int j = 0; j < 3; j++) t += S3[i][j] * k->g[3 * v + j];
+      f_int[3 * k->node[v] + i] += V * t;
+    }
+  if (!K) return ORC_OK;
+  for (int va = 0; va < k->ns; va++)
+    for (int vb = 0; vb < k->ns; vb++)
+      for (int i = 0; i < 3; i++)
+        for (int kk = 0; kk < 3; kk++) {
+          double t = 0;
+          for (int j = 0; j < 3; j++)
+            for (int l = 0; l < 3; l++) t += k->g[3 * va + j] * a[((i * 3 + j) * 3 + kk) * 3 + l] * k->g[3 * vb + l];
+          int64_t pos = csr_find(m, 3 * (int64_t)k->node[va] + i, 3 * k->node[vb] + kk);
+          if (pos < 0) return ORC_ESTENCIL;
+          K[pos] += V * t;
+        }
+  return ORC_OK;
+}
+
 int32_t orc_assemble(const orc_mesh* m, const orc_state* s, const double* u, double* f_int, double* K,
                      double* sigma6, double* Fnew9, double* be6, uint8_t* plastic, double* qtrial, int64_t* bad) {
   *bad = -1;
-  int64_t n = m->np;
   memset(f_int, 0, (size_t)(3 * m->nindep) * sizeof(double));
   if (K) memset(K, 0, (size_t)m->nnz * sizeof(double));
   static orc_kin k;
-  double a[81];
-  for (int64_t p = 0; p < n; p++) {
-    int st = kinematics(m, s, p, u, &k);
+  for (int64_t p = 0; p < m->np; p++) {
+    int st = assemble_point(m, s, u, p, &k, f_int, K, sigma6, Fnew9, be6, plastic, qtrial);
     if (st) { *bad = p; return st; }
-    double bn[6], sig[6], tau[6], be[6], info[3];
-    for (int c = 0; c < 6; c++) bn[c] = s->bn[c * n + p];
-    st = orc_material_point((const double*)k.dF, bn, s->Jn[p], s->E[p], s->nu[p], s->sy[p], sig, tau, K ? a : NULL, be, info);
-    if (st) { *bad = p; return st; }
-    if (sigma6) for (int c = 0; c < 6; c++) sigma6[c * n + p] = sig[c];
-    if (be6) for (int c = 0; c < 6; c++) be6[c * n + p] = be[c];
-    if (plastic) plastic[p] = (uint8_t)info[0];
-    if (qtrial) qtrial[p] = info[1];
-    if (Fnew9 && s->Fn) {
-      for (int i = 0; i < 3; i++)
-        for (int j = 0; j < 3; j++) {
-          double t = 0;
-          for (int mm = 0; mm < 3; mm++) t += k.dF[i][mm] * s->Fn[(3 * mm + j) * n + p];
-          Fnew9[(3 * i + j) * n + p] = t;
-        }
-    }
-    double S3[3][3];
-    sym_from6(sig, S3);
-    double V = k.Jd * s->vol[p];
-    for (int v = 0; v < k.ns; v++)
-      for (int i = 0; i < 3; i++) {
-        double t = 0;
-        for (int j = 0; j < 3; j++) t += S3[i][j] * k.g[3 * v + j];
-        f_int[3 * k.node[v] + i] += V * t;
-      }
-    if (!K) continue;
-    for (int va = 0; va < k.ns; va++)
-      for (int vb = 0; vb < k.ns; vb++)
-        for (int i = 0; i < 3; i++)
-          for (int kk = 0; kk < 3; kk++) {
-            double t = 0;
-            for (int j = 0; j < 3; j++)
-              for (int l = 0; l < 3; l++) t += k.g[3 * va + j] * a[((i * 3 + j) * 3 + kk) * 3 + l] * k.g[3 * vb + l];
-            int64_t pos = csr_find(m, 3 * (int64_t)k.node[va] + i, 3 * k.node[vb] + kk);
-            if (pos < 0) { *bad = p; return ORC_ESTENCIL; }
-            K[pos] += V * t;
-          }
   }
   return ORC_OK;
+}
+
+/* The same assembly timed on several host threads (no other use): the points are cut into
+ * nthreads contiguous ranges, each thread adds its points into its own f_int and K, and the
+ * thread copies are added in thread order, so the result depends only on nthreads and equals
+ * orc_assemble's up to the order of the sums. */
+int32_t orc_assemble_threads(const orc_mesh* m, const orc_state* s, const double* u, double* f_int, double* K,
+                             double* sigma6, int32_t nthreads, int64_t* bad) {
+  *bad = -1;
+  if (nthreads < 1) nthreads = 1;
+  const int64_t nf = 3 * m->nindep, nk = K ? m->nnz : 0, n = m->np;
+  double** fp = (double**)calloc((size_t)nthreads, sizeof(double*));
+  double** kp = (double**)calloc((size_t)nthreads, sizeof(double*));
+  int64_t* badt = (int64_t*)malloc((size_t)nthreads * sizeof(int64_t));
+  int32_t* stt = (int32_t*)calloc((size_t)nthreads, sizeof(int32_t));
+  int oom = !fp || !kp || !badt || !stt;
+  for (int t = 0; t < nthreads && !oom; t++) {
+    fp[t] = (double*)calloc((size_t)(nf > 0 ? nf : 1), sizeof(double));
+    kp[t] = (double*)calloc((size_t)(nk > 0 ? nk : 1), sizeof(double));
+    badt[t] = -1;
+    if (!fp[t] || !kp[t]) oom = 1;
+  }
+  int32_t rc = ORC_OK;
+  if (oom) {
+    rc = ORC_EARG;
+  } else {
+#pragma omp parallel num_threads(nthreads)
+    {
+#ifdef _OPENMP
+      const int t = omp_get_thread_num(), nt = omp_get_num_threads();
+#else
+      const int t = 0, nt = 1;
+#endif
+      orc_kin k;
+      for (int tt = t; tt < nthreads; tt += nt) {  /* every range is taken, whatever team size */
+        const int64_t p0 = n * tt / nthreads, p1 = n * (tt + 1) / nthreads;
+        for (int64_t p = p0; p < p1; p++) {
+          int st = assemble_point(m, s, u, p, &k, fp[tt], K ? kp[tt] : NULL, sigma6, NULL, NULL, NULL, NULL);
+          if (st) { stt[tt] = st; badt[tt] = p; break; }
+        }
+      }
+#pragma omp barrier
+#pragma omp for schedule(static)
+      for (int64_t i = 0; i < nf; i++) {
+        double acc = 0;
+        for (int tt = 0; tt < nthreads; tt++) acc += fp[tt][i];
+        f_int[i] = acc;
+      }
+#pragma omp for schedule(static)
+      for (int64_t i = 0; i < nk; i++) {
+        double acc = 0;
+        for (int tt = 0; tt < nthreads; tt++) acc += kp[tt][i];
+        K[i] = acc;
+      }
+    }
+    for (int t = 0; t < nthreads; t++)
+      if (stt[t]) { rc = stt[t]; *bad = badt[t]; break; }
+  }
+  for (int t = 0; t < nthreads && fp && kp; t++) { free(fp[t]); free(kp[t]); }
+  free(fp); free(kp); free(badt); free(stt);
+  return rc;
 }
 
 /* body force term of the weak form: f_ext,v = sum_p S_vp m_p g */

@@ -163,3 +163,21 @@ def test_partial_yield_workload_sigma_y():
     q = trial_q(W.get("c1"))
     assert float(np.percentile(q, 70)) == rec["sigma_y"]
     assert abs(np.mean(q > w.sy) - 0.3) < 1e-4
+
+
+@pytest.mark.parametrize("kind,jit,sy", [("sphere", 0, 40.0), ("box", None, math.inf)])
+def test_threaded_timing_driver(kind, jit, sy):
+    """The all-cores timing mode adds the same per-point shares: one thread reproduces the
+    serial assembly bit for bit, several threads agree to rounding, stress identical."""
+    w, m, ps, s, u = _problem(kind, jit, sy)
+    ref = m.assemble(s, u)
+    one = m.assemble_threads(s, u, 1)
+    assert np.array_equal(one["f_int"], ref["f_int"]) and np.array_equal(one["K"], ref["K"])
+    assert np.array_equal(one["sigma"], ref["sigma"])
+    for t in (3, 8):
+        par = m.assemble_threads(s, u, t)
+        assert np.abs(par["f_int"] - ref["f_int"]).max() <= 1e-14 * np.abs(ref["f_int"]).max()
+        assert np.abs(par["K"] - ref["K"]).max() <= 1e-14 * np.abs(ref["K"]).max()
+        assert np.array_equal(par["sigma"], ref["sigma"])
+        again = m.assemble_threads(s, u, t)
+        assert np.array_equal(again["f_int"], par["f_int"]) and np.array_equal(again["K"], par["K"])

@@ -828,12 +828,14 @@ __device__ __forceinline__ unsigned col_hash(int32_t id, int p) { return (unsign
 
 constexpr int kRowWaves = 4;   // wavefronts per row of k_general_rows
 constexpr int kRowBatch = 16;  // straddling points per batch of one wavefront
-constexpr int kMbStride = 32;  // per point: Mb (27 values), S_a, 2 m / dt^2 (padded for 16-byte reads)
+// per point: Mb (27 values), S_a, 2 m / dt^2; the stride keeps 16-byte alignment and starts
+// consecutive points 4 banks apart, so the lanes of the points of one task group (which read
+// different points' values at once) do not meet in one bank
+constexpr int kMbStride = 34;
 
-// LDS of one wavefront's batch: support offsets, Mb, first task and the point of each task
+// LDS of one wavefront's batch: Mb of its points
 __host__ __device__ constexpr size_t row_batch_lds(int tb) {
-  return size_t(kRowBatch) * 8 + size_t(kRowBatch * kMbStride) * size_t(tb) + size_t(kRowBatch) * 4 +
-         size_t(kRowBatch * kMaxSup);
+  return size_t(kRowBatch * kMbStride) * size_t(tb);
 }
 // LDS bytes of k_general_rows for rows of at most deg block columns, working type of size tb
 __host__ __device__ constexpr size_t general_rows_lds(int deg, int tb) {
@@ -866,11 +868,10 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_general_rows(AsmArgs A, int6
   double* fsum = reinterpret_cast<double*>(gsm + size_t(kRowWaves) * row_batch_lds(sizeof(T)));  // [kRowWaves][3]
   // table entries: node id (high 32 bits) and column (low 32 bits); empty = all ones
   unsigned long long* ctab = reinterpret_cast<unsigned long long*>(fsum + kRowWaves * 4);
-  double* acc = reinterpret_cast<double*>(ctab + tp);    // the row [9 deg], FP64
-  int64_t* poff = reinterpret_cast<int64_t*>(wb);                              // [kRowBatch]
-  T* mbuf = reinterpret_cast<T*>(poff + kRowBatch);                            // [kRowBatch][kMbStride]
-  int32_t* pref = reinterpret_cast<int32_t*>(mbuf + kRowBatch * kMbStride);   // [kRowBatch]
-  uint8_t* taskpt = reinterpret_cast<uint8_t*>(pref + kRowBatch);             // [kRowBatch kMaxSup]
+  // the row in FP64, entry (r, k) of block column c at (3 r + k) deg + c: the lanes of one
+  // addition (one entry, different columns) fall into consecutive banks
+  double* acc = reinterpret_cast<double*>(ctab + tp);
+  T* mbuf = reinterpret_cast<T*>(wb);  // [kRowBatch][kMbStride]
   const bool wantK = A.K != nullptr;
   if (wantK) {
     for (int j = tid; j < 9 * deg; j += 64 * kRowWaves) acc[j] = 0.0;
@@ -911,43 +912,6 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_general_rows(AsmArgs A, int6
   // the wavefront's batches (its own trip count: only wavefront-level synchronisation inside)
   for (int64_t cb = c0 + int64_t(wave) * kRowBatch; cb < c1; cb += kStep) {
     const int nb = int(c1 - cb < kRowBatch ? c1 - cb : kRowBatch);
-    // first task of each point: exclusive prefix of the support sizes over the batch
-    int incl = ns;
-#pragma unroll
-    for (int d = 1; d < kRowBatch; d <<= 1) {
-      const int v = __shfl_up(incl, d, kRowBatch);
-      if (pi >= d) incl += v;
-    }
-    const int ntask = __shfl(incl, kRowBatch - 1);
-    if (pi < nb) {
-      if (part == 0) {
-        poff[pi] = off;
-        pref[pi] = incl - ns;
-      } else if (part == 1) {
-        for (int z = 0; z < ns; ++z) taskpt[incl - ns + z] = uint8_t(pi);
-      }
-    }
-    wave_lds_sync();
-    // the first rounds of (point, slot) tasks: their slot data is loaded now, so that these
-    // loads overlap the loads and arithmetic of Mb below
-    constexpr int kPre = 4;
-    int32_t pid[kPre];
-    double pg[kPre][4];
-    int pq[kPre];
-#pragma unroll
-    for (int u = 0; u < kPre; ++u) {
-      const int tk = lane + 64 * u;
-      pid[u] = -1;
-      pq[u] = 0;
-      for (int c = 0; c < 4; ++c) pg[u][c] = 0.0;
-      if (wantK && tk < ntask) {
-        const int q = taskpt[tk];
-        const int64_t o = poff[q] + (tk - pref[q]);
-        pq[u] = q;
-        pid[u] = A.sup_id[o];
-        for (int c = 0; c < 4; ++c) pg[u][c] = A.sup_g[o * 4 + c];
-      }
-    }
     if (pi < nb) {
       // the record is read in 16-byte pieces: the point's c tau and g_a by each of its four
       // lanes, and the six values of tangent direction dd = 3 j + k (48 bytes) by lane
@@ -986,12 +950,29 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_general_rows(AsmArgs A, int6
                    rec[54 + kSym6[r][2]] * double(ga[2]) + double(Sa) * rec[69 + r];
       }
     }
+    const int64_t toff = off;  // this batch's support of the lane's point
+    const int tns = pi < nb ? ns : 0;
     entry(cb + kStep, t, za, off, ns);  // the next batch of this wavefront
     wave_lds_sync();
-    if (wantK) {
-      auto task = [&](int q, int32_t id, const double* g) {
-        const T sb = T(g[0]);
-        const T gb[3] = {T(g[1]), T(g[2]), T(g[3])};
+    if (wantK && tns > 0) {
+      // the lane's point's slots part, part + 4, ..., started at a per-point offset so that
+      // points with the same support order add to different columns at once; the point's Mb
+      // is read from LDS once
+      const T* Mq = mbuf + pi * kMbStride;
+      T M[29];
+#pragma unroll
+      for (int q = 0; q < 29; ++q) M[q] = Mq[q];
+      const T ms0 = M[28] * M[27];  // inertia: (2 m / dt^2) S_a (times S_b below)
+      const int rot = (5 * pi) % tns;
+      for (int zz = part; zz < tns; zz += 4) {
+        int z = zz + rot;
+        if (z >= tns) z -= tns;
+        const int64_t o = toff + z;
+        const int32_t id = A.sup_id[o];
+        const double2* g = reinterpret_cast<const double2*>(A.sup_g + o * 4);
+        const double2 g01 = g[0], g23 = g[1];
+        const T sb = T(g01.x);
+        const T gb[3] = {T(g01.y), T(g23.x), T(g23.y)};
         int lo = -1;  // block column of the slot's node in row a
         for (unsigned hh = col_hash(id, tp);; hh = (hh + 1) & unsigned(tp - 1)) {
           const unsigned long long en = ctab[hh];
@@ -1003,10 +984,9 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_general_rows(AsmArgs A, int6
         }
         if (lo < 0) {
           raise(A.err, MPM_ESTENCIL, na);
-          return;
+          continue;
         }
-        const T* M = mbuf + q * kMbStride;
-        const T ms = M[28] * M[27] * sb;  // inertia: (2 m / dt^2) S_a S_b on the diagonal
+        const T ms = ms0 * sb;
 #pragma unroll
         for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -1014,18 +994,8 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_general_rows(AsmArgs A, int6
             const int rk = 3 * r + k;
             T val = M[3 * rk] * gb[0] + M[3 * rk + 1] * gb[1] + M[3 * rk + 2] * gb[2];
             if (r == k) val += ms;
-            atomicAdd(acc + r * 3 * deg + 3 * lo + k, double(val));
+            atomicAdd(acc + rk * deg + lo, double(val));
           }
-      };
-#pragma unroll
-      for (int u = 0; u < kPre; ++u)
-        if (pid[u] >= 0) task(pq[u], pid[u], pg[u]);
-      for (int tk = lane + 64 * kPre; tk < ntask; tk += 64) {
-        const int q = taskpt[tk];
-        const int64_t o = poff[q] + (tk - pref[q]);
-        double g[4];
-        for (int c = 0; c < 4; ++c) g[c] = A.sup_g[o * 4 + c];
-        task(q, A.sup_id[o], g);
       }
     }
     wave_lds_sync();  // the batch buffers are rewritten by the wavefront's next batch
@@ -1041,10 +1011,13 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_general_rows(AsmArgs A, int6
     for (int w = 0; w < kRowWaves; ++w) f += fsum[3 * w + tid];
     A.f[3 * na + tid] += f;
   }
-  if (wantK) {
+  if (wantK) {  // CSR order of the node's rows: row r, then block column c, then k
     T* Kout = reinterpret_cast<T*>(A.K);
-    for (int j = tid; j < 9 * deg; j += 64 * kRowWaves)
-      if (acc[j] != 0.0) Kout[r0 + j] += T(acc[j]);
+    for (int j = tid; j < 9 * deg; j += 64 * kRowWaves) {
+      const int r = j / (3 * deg), rem = j - r * 3 * deg, c = rem / 3, k = rem - 3 * c;
+      const double v = acc[(3 * r + k) * deg + c];
+      if (v != 0.0) Kout[r0 + j] += T(v);
+    }
   }
 }
 

@@ -151,8 +151,13 @@ typedef struct {
  * Every construction step runs on the device (refinement, balance, numbering, constraints,
  * point order, overlap classification, CSR pattern, ghost faces); the host only reads counts
  * between the steps and keeps the ghost face records. Besides the pattern and the segment
- * records, the mesh keeps 592 bytes of device memory per point whose domain overlaps several
- * leaves (that point's tangent record, rewritten by every assembly). */
+ * records, the mesh keeps, per point whose domain overlaps several leaves, 592 bytes of device
+ * memory (that point's tangent record, rewritten by every assembly) and 40 bytes per node of
+ * its support (the node, the leaves holding it, and the slot's basis value and spatial
+ * gradient, rewritten by every assembly), plus 4 bytes per (node, such point) incidence.
+ * Errors: MPM_EARG (bad criterion or null argument), MPM_ESTENCIL (lattice or leaf counts
+ * beyond the key widths, a domain over more than one leaf boundary per axis, or more than
+ * 2^26 domains over several leaves), MPM_EOUTSIDE, MPM_ENONFINITE, MPM_EHIP. */
 int32_t octree_build(const mpm_refine_t* crit, const double* x, const double* l, int64_t n, void* stream,
                      mpm_mesh_t** out_mesh);
 int32_t mpm_mesh_info(const mpm_mesh_t* mesh, mpm_mesh_info_t* out);
@@ -197,7 +202,10 @@ int32_t mpm_external_force(const mpm_mesh_t* mesh, const mpm_state_t* s, double*
  *   sigma6 [6][n] FP64 Cauchy stress, may be NULL;
  *   r [n_dof] = f_int - f_ext with DOFs where dirichlet[dof] != 0 zeroed (f_ext, dirichlet
  *   may be NULL = zero / none), and rnorm (device, 1 double) = ||r||_2 in FP64; both may be
- *   NULL; F_new [9][n] = dF F_n and be_new [6][n] updated b_e, may be NULL (commit state).
+ *   NULL; F_new [9][n] = dF F_n and be_new [6][n] the elastic left Cauchy-Green tensor of
+ *   the returned strains, sum_a exp(2 eps_e,a) n_a n_a^T (Section 2.2), may be NULL (commit
+ *   state; both are formed from their increments, F_n + H F_n and I + sum expm1(2 eps_e,a)
+ *   n_a n_a^T, so that MPM_F32K keeps the relative accuracy of the strain).
  * On a mesh built with ghost stabilisation (Section 4, eq. ghost) the penalty
  *   j(u, v) = sum_F (h_F beta_F / kappa) int_F [d_n u] . [d_n v] dA,  kappa = 10,
  * h_F the larger side of the face's two leaves and beta_F the larger of their maxima of the

@@ -40,6 +40,8 @@ struct AsmArgs {
   const int32_t* sup_id;     // node of each slot
   const uint32_t* sup_src;   // leaves of the point holding the slot's node, and its vertex in each
   double* sup_g;             // per slot: S and the spatial gradient (written by k_general_support)
+  const int32_t* tpos;       // per block of those rows above the diagonal: column of the row's node in the
+                             // row of the block's node
   int64_t n, n_strad;
   mpm_state_t s;
   const double* u;
@@ -878,9 +880,12 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_general_rows(AsmArgs A, int6
     for (int j = tid; j < tp; j += 64 * kRowWaves) ctab[j] = ~0ull;
   }
   __syncthreads();
+  // the block column of a itself (the last of the force slots, unused by the forces)
+  int* sja = reinterpret_cast<int*>(fsum + kRowWaves * 4 - 1);
   if (wantK) {
     for (int j = tid; j < deg; j += 64 * kRowWaves) {
       const int32_t id = A.col[r0 + 3 * j] / 3;
+      if (id == na) *sja = j;
       const unsigned long long ent = (static_cast<unsigned long long>(unsigned(id)) << 32) | unsigned(j);
       for (unsigned hh = col_hash(id, tp);; hh = (hh + 1) & unsigned(tp - 1))
         if (atomicCAS(ctab + hh, ~0ull, ent) == ~0ull) break;
@@ -950,14 +955,17 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_general_rows(AsmArgs A, int6
                    rec[54 + kSym6[r][2]] * double(ga[2]) + double(Sa) * rec[69 + r];
       }
     }
-    const int64_t toff = off;  // this batch's support of the lane's point
-    const int tns = pi < nb ? ns : 0;
+    // this batch's support of the lane's point: the slots of nodes b >= a (the support is in
+    // ascending node order and slot za holds a); K is symmetric, so the blocks (a, b) of the
+    // nodes b < a are written by the rows of those nodes (below)
+    const int64_t toff = off + za;
+    const int tns = pi < nb ? ns - za : 0;
     entry(cb + kStep, t, za, off, ns);  // the next batch of this wavefront
     wave_lds_sync();
     if (wantK && tns > 0) {
-      // the lane's point's slots part, part + 4, ..., started at a per-point offset so that
-      // points with the same support order add to different columns at once; the point's Mb
-      // is read from LDS once
+      // the lane's point's upper slots part, part + 4, ..., started at a per-point offset so
+      // that points with the same support order add to different columns at once; the point's
+      // Mb is read from LDS once
       const T* Mq = mbuf + pi * kMbStride;
       T M[29];
 #pragma unroll
@@ -1011,12 +1019,31 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_general_rows(AsmArgs A, int6
     for (int w = 0; w < kRowWaves; ++w) f += fsum[3 * w + tid];
     A.f[3 * na + tid] += f;
   }
-  if (wantK) {  // CSR order of the node's rows: row r, then block column c, then k
+  if (wantK) {
+    // the blocks (a, c) of the columns c from a's own on (columns ascend), in CSR order (row r,
+    // block column c, then k): K(a, c) += the row, and for c above a the same value into
+    // block (c, a), entry (k, r), of the row of c. That block is written by no other
+    // workgroup: the row of c holds only its blocks from c on. An entry no straddling point
+    // reaches keeps the value of the one-leaf gather, symmetric to rounding.
     T* Kout = reinterpret_cast<T*>(A.K);
-    for (int j = tid; j < 9 * deg; j += 64 * kRowWaves) {
-      const int r = j / (3 * deg), rem = j - r * 3 * deg, c = rem / 3, k = rem - 3 * c;
+    const int ja = *sja, nu = deg - ja;
+    const int64_t tb0 = r0 / 9;
+    for (int q = tid; q < 9 * nu; q += 64 * kRowWaves) {
+      const int r = q / (3 * nu), rem = q - r * 3 * nu, cu = rem / 3, k = rem - 3 * cu, c = ja + cu;
       const double v = acc[(3 * r + k) * deg + c];
-      if (v != 0.0) Kout[r0 + j] += T(v);
+      if (v == 0.0) continue;
+      const int64_t e = r0 + int64_t(r) * 3 * deg + 3 * c + k;
+      const T kv = Kout[e] + T(v);
+      Kout[e] = kv;
+      if (cu > 0) {
+        const int64_t nc = A.col[r0 + 3 * c] / 3;
+        const int32_t m = A.tpos[tb0 + c];
+        if (m < 0) {  // the pattern is symmetric: cannot happen
+          raise(A.err, MPM_ESTENCIL, na);
+          continue;
+        }
+        Kout[A.row_ptr[3 * nc + k] + 3 * m + r] = kv;
+      }
     }
   }
 }
@@ -1298,6 +1325,7 @@ static AsmArgs make_args(const mpm_mesh* m, const mpm_state_t* s) {
   A.sup_id = m->d_sup_id;
   A.sup_src = m->d_sup_src;
   A.sup_g = m->d_sup_g;
+  A.tpos = m->d_tpos;
   A.n = m->n_point;
   A.n_strad = m->n_straddle;
   A.s = *s;

@@ -123,12 +123,15 @@ struct mpm_mesh {
   int64_t* d_sinc_off = nullptr;    // n_snode + 1
   int32_t* d_sinc = nullptr;
   // support of each straddling point in slot order (the union of its leaves' slot nodes in
-  // first-seen order): slots d_sup_off[t] .. d_sup_off[t + 1] of the arrays below
+  // ascending node order): slots d_sup_off[t] .. d_sup_off[t + 1] of the arrays below
   int64_t* d_sup_off = nullptr;     // n_straddle + 1
   int32_t* d_sup_id = nullptr;      // node of each slot
   uint32_t* d_sup_src = nullptr;    // per slot: bit q (0..7) = leaf q of the point holds the node,
                                     // bits 8 + 3q .. 10 + 3q = its vertex in that leaf
   double* d_sup_g = nullptr;        // per slot, written by each assembly: S and the spatial gradient
+  // per CSR block (index row_ptr[3 a] / 9 + j) of a row a reached by straddling points whose
+  // column node c is above a: the block column of a in the row of c
+  int32_t* d_tpos = nullptr;
   mpm::DevErr* d_err = nullptr;
   mpm::DevErr* h_err = nullptr;     // pinned host copy of the error word
   hipEvent_t err_ev = nullptr;      // marks the error-word copy (polled, no blocking sync)

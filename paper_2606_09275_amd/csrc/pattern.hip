@@ -46,7 +46,8 @@ __global__ void k_strad_pop(const int32_t* __restrict__ sleaf, int64_t ns, int32
   }
 }
 
-// support of a straddling point: union of the slot nodes of its leaves, first-seen order
+// support of a straddling point: union of the slot nodes of its leaves, in ascending node
+// order (so that the nodes after a given one are a contiguous range of slots)
 __device__ int strad_support(const int32_t* __restrict__ sleaf, int64_t t, const int32_t* __restrict__ cell_nodes,
                              int32_t sup[kMaxPointLeaves * 8]) {
   int ns = 0;
@@ -59,6 +60,12 @@ __device__ int strad_support(const int32_t* __restrict__ sleaf, int64_t t, const
       for (int z = 0; z < ns; ++z) f |= sup[z] == id;
       if (!f) sup[ns++] = id;
     }
+  }
+  for (int z = 1; z < ns; ++z) {  // insertion sort of at most 64 ids
+    const int32_t id = sup[z];
+    int y = z;
+    for (; y > 0 && sup[y - 1] > id; --y) sup[y] = sup[y - 1];
+    sup[y] = id;
   }
   return ns;
 }
@@ -108,6 +115,34 @@ __global__ void k_strad_slots(const int32_t* __restrict__ sleaf, int64_t ns, con
     }
     sup_id[off[t] + z] = sup[z];
     sup_src[off[t] + z] = src;
+  }
+}
+
+// Transposed block positions for the rows reached by straddling points: for block j of row a
+// whose column node c is above a, the block column of a in the row of c (the pattern is
+// symmetric and each row's columns ascend: bisection); -1 if absent, which the row kernel
+// reports. One wavefront per row, lanes over its blocks.
+__global__ void k_tpos(const int32_t* __restrict__ snode, const int64_t* __restrict__ row_ptr,
+                       const int32_t* __restrict__ col, int32_t* __restrict__ tpos) {
+  const int64_t a = snode[blockIdx.x];
+  const int64_t r0 = row_ptr[3 * a];
+  const int deg = int((row_ptr[3 * a + 1] - r0) / 3);
+  for (int j = threadIdx.x; j < deg; j += 64) {
+    const int64_t c = col[r0 + 3 * j] / 3;
+    if (c <= a) continue;
+    const int64_t s0 = row_ptr[3 * c];
+    int lo = 0, hi = int((row_ptr[3 * c + 1] - s0) / 3) - 1, m = -1;
+    while (lo <= hi) {
+      const int mid = (lo + hi) >> 1;
+      const int64_t b = col[s0 + 3 * mid] / 3;
+      if (b == a) {
+        m = mid;
+        break;
+      }
+      if (b < a) lo = mid + 1;
+      else hi = mid - 1;
+    }
+    tpos[r0 / 9 + j] = m;
   }
 }
 
@@ -649,6 +684,11 @@ int32_t gpu_build_pattern(mpm_mesh* m, const double* dx, const double* dl, hipSt
       }
     MPM_HIP(hipMalloc(&m->d_srow, std::max<size_t>(1, order.size()) * 4));
     MPM_HIP(hipMemcpyAsync(m->d_srow, order.data(), order.size() * 4, hipMemcpyHostToDevice, st));
+    MPM_HIP(hipMalloc(&m->d_tpos, size_t(std::max<int64_t>(1, m->nnz / 9)) * 4));
+    if (m->n_snode)
+      hipLaunchKernelGGL(k_tpos, dim3(unsigned(m->n_snode)), dim3(64), 0, st, m->d_snode, m->d_row_ptr, m->d_col,
+                         m->d_tpos);
+    MPM_HIP(hipGetLastError());
     MPM_HIP(hipStreamSynchronize(st));
   }
 

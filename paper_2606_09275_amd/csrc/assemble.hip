@@ -853,6 +853,9 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// marks an entry of the row that no straddling point reached (a NaN no arithmetic produces)
+constexpr long long kUntouched = 0x7ff4d00d0000beefll;
+
 template <typename T>
 __global__ __launch_bounds__(64 * kRowWaves) void k_general_rows(AsmArgs A, int64_t row0) {
   extern __shared__ __align__(16) unsigned char gsm[];
@@ -1021,29 +1024,41 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_general_rows(AsmArgs A, int6
   }
   if (wantK) {
     // the blocks (a, c) of the columns c from a's own on (columns ascend), in CSR order (row r,
-    // block column c, then k): K(a, c) += the row, and for c above a the same value into
-    // block (c, a), entry (k, r), of the row of c. That block is written by no other
-    // workgroup: the row of c holds only its blocks from c on. An entry no straddling point
-    // reaches keeps the value of the one-leaf gather, symmetric to rounding.
+    // block column c, then k): K(a, c) += the row; the new value is kept in the row's LDS (an
+    // entry no straddling point reaches is marked instead: it keeps the value of the one-leaf
+    // gather, symmetric to rounding)
     T* Kout = reinterpret_cast<T*>(A.K);
     const int ja = *sja, nu = deg - ja;
-    const int64_t tb0 = r0 / 9;
     for (int q = tid; q < 9 * nu; q += 64 * kRowWaves) {
       const int r = q / (3 * nu), rem = q - r * 3 * nu, cu = rem / 3, k = rem - 3 * cu, c = ja + cu;
-      const double v = acc[(3 * r + k) * deg + c];
-      if (v == 0.0) continue;
+      double* ap = acc + (3 * r + k) * deg + c;
+      const double v = *ap;
+      if (v == 0.0) {
+        *ap = __longlong_as_double(kUntouched);
+        continue;
+      }
       const int64_t e = r0 + int64_t(r) * 3 * deg + 3 * c + k;
       const T kv = Kout[e] + T(v);
       Kout[e] = kv;
-      if (cu > 0) {
-        const int64_t nc = A.col[r0 + 3 * c] / 3;
-        const int32_t m = A.tpos[tb0 + c];
-        if (m < 0) {  // the pattern is symmetric: cannot happen
-          raise(A.err, MPM_ESTENCIL, na);
-          continue;
-        }
-        Kout[A.row_ptr[3 * nc + k] + 3 * m + r] = kv;
+      *ap = double(kv);
+    }
+    __syncthreads();
+    // for c above a the same values into block (c, a) of the row of c, entry (k, r) at the
+    // block column the mesh keeps; lanes take (c, k, r) with r fastest, so that three lanes
+    // store three consecutive values. That block is written by no other workgroup: the row of
+    // c holds only its blocks from c on.
+    const int64_t tb0 = r0 / 9;
+    for (int q = tid; q < 9 * (nu - 1); q += 64 * kRowWaves) {
+      const int cu = 1 + q / 9, rem = q - 9 * (cu - 1), k = rem / 3, r = rem - 3 * k, c = ja + cu;
+      const double kv = acc[(3 * r + k) * deg + c];
+      if (__double_as_longlong(kv) == kUntouched) continue;
+      const int64_t nc = A.col[r0 + 3 * c] / 3;
+      const int32_t m = A.tpos[tb0 + c];
+      if (m < 0) {  // the pattern is symmetric: cannot happen
+        raise(A.err, MPM_ESTENCIL, na);
+        continue;
       }
+      Kout[A.row_ptr[3 * nc + k] + 3 * m + r] = T(kv);
     }
   }
 }

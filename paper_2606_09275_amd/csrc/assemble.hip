@@ -753,19 +753,20 @@ __global__ __launch_bounds__(64) void k_general_points(AsmArgs A) {
   rec[73] = 0.0;
 }
 
-// Merged support of each straddling point, once per assembly: 8 points per 64-lane
-// workgroup, one lane per (point, leaf). Each lane evaluates its leaf's 8 slot functions at
-// the overlap box (values and reference gradients), maps the gradients to the current
-// configuration with the point's dF^-1 (from its record), and stages them in LDS; then each
-// support slot sums the entries of the leaves that hold its node, in ascending leaf order (a
-// fixed order), and writes (S, grad_x S) to the slot. The row kernel below reads these.
-constexpr int kSupPts = 8;  // points per workgroup of k_general_support
+// Merged support of each straddling point, once per assembly: one lane per (point, leaf),
+// launched per group of straddling points t0 .. t1 whose leaf counts are at most 2^lg, with
+// 2^lg lanes per point. Each lane evaluates its leaf's 8 slot functions at the overlap box
+// (values and reference gradients), maps the gradients to the current configuration with the
+// point's dF^-1 (from its record), and stages them in LDS; then each support slot sums the
+// entries of the leaves that hold its node, in ascending leaf order (a fixed order), and
+// writes (S, grad_x S) to the slot. The row kernel below reads these.
 template <typename T>
-__global__ __launch_bounds__(64) void k_general_support(AsmArgs A) {
-  __shared__ double stg[kSupPts][kMaxPointLeaves][8][4];  // 16 KB
-  const int pp = threadIdx.x >> 3, q = threadIdx.x & 7;
-  const int64_t t = int64_t(blockIdx.x) * kSupPts + pp;
-  const bool ok = t < A.n_strad;
+__global__ __launch_bounds__(64) void k_general_support(AsmArgs A, int64_t t0, int64_t t1, int lg) {
+  __shared__ double stg[64][8][4];  // 16 KB: lane l stages its leaf at row l
+  const int lp = 1 << lg;
+  const int pp = threadIdx.x >> lg, q = threadIdx.x & (lp - 1);
+  const int64_t t = t0 + int64_t(blockIdx.x) * (64 >> lg) + pp;
+  const bool ok = t < t1;
   const int32_t e = ok ? A.strad_leaf[t * kMaxPointLeaves + q] : -1;
   if (e >= 0) {
     const int64_t n = A.n, i = A.strad[t];
@@ -782,23 +783,23 @@ __global__ __launch_bounds__(64) void k_general_support(AsmArgs A) {
       for (int k = 0; k < 3; ++k) Fi[r][k] = T(rec[60 + 3 * r + k]);
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
-      stg[pp][q][v][0] = double(s8[v]);
+      stg[threadIdx.x][v][0] = double(s8[v]);
 #pragma unroll
       for (int k = 0; k < 3; ++k)
-        stg[pp][q][v][1 + k] = double(Fi[0][k] * d8[v][0] + Fi[1][k] * d8[v][1] + Fi[2][k] * d8[v][2]);
+        stg[threadIdx.x][v][1 + k] = double(Fi[0][k] * d8[v][0] + Fi[1][k] * d8[v][1] + Fi[2][k] * d8[v][2]);
     }
   }
   __syncthreads();
   if (!ok) return;
   const int64_t off = A.sup_off[t];
   const int ns = int(A.sup_off[t + 1] - off);
-  for (int z = q; z < ns; z += 8) {
+  for (int z = q; z < ns; z += lp) {
     const uint32_t src = A.sup_src[off + z];
     double g[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int qq = 0; qq < kMaxPointLeaves; ++qq)
+    for (int qq = 0; qq < lp; ++qq)  // the point has at most lp leaves
       if ((src >> qq) & 1u) {
         const int v = int((src >> (8 + 3 * qq)) & 7u);
-        for (int c = 0; c < 4; ++c) g[c] += stg[pp][qq][v][c];
+        for (int c = 0; c < 4; ++c) g[c] += stg[pp * lp + qq][v][c];
       }
     double* o = A.sup_g + (off + z) * 4;
     for (int c = 0; c < 4; ++c) o[c] = g[c];
@@ -1460,9 +1461,14 @@ static int32_t assemble_impl(const mpm_mesh_t* m, const AsmArgs& A, int32_t prec
     const dim3 pgrid(unsigned((m->n_straddle + 63) / 64));
     if (precision == MPM_F64) hipLaunchKernelGGL(k_general_points<double>, pgrid, dim3(64), 0, st, A);
     else hipLaunchKernelGGL(k_general_points<float>, pgrid, dim3(64), 0, st, A);
-    const dim3 sgrid(unsigned((m->n_straddle + kSupPts - 1) / kSupPts));
-    if (precision == MPM_F64) hipLaunchKernelGGL(k_general_support<double>, sgrid, dim3(64), 0, st, A);
-    else hipLaunchKernelGGL(k_general_support<float>, sgrid, dim3(64), 0, st, A);
+    for (int g = 0; g < 3; ++g) {  // groups of at most 2, 4 and 8 leaves per point
+      const int64_t t0 = m->strad_grp[g], t1 = m->strad_grp[g + 1];
+      if (t1 <= t0) continue;
+      const int ppw = 64 >> (g + 1);  // points per workgroup
+      const dim3 sgrid(unsigned((t1 - t0 + ppw - 1) / ppw));
+      if (precision == MPM_F64) hipLaunchKernelGGL(k_general_support<double>, sgrid, dim3(64), 0, st, A, t0, t1, g + 1);
+      else hipLaunchKernelGGL(k_general_support<float>, sgrid, dim3(64), 0, st, A, t0, t1, g + 1);
+    }
     // narrow rows with LDS for kNarrowRow columns, then the rest with LDS for the widest row
     const int64_t nn = m->n_snode_narrow, nw = m->n_snode - nn;
     const int tb = precision == MPM_F64 ? 8 : 4;

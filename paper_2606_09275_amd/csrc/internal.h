@@ -120,6 +120,9 @@ struct mpm_mesh {
   // kernel takes less LDS), then the rest; n_snode_narrow of the first kind
   int32_t* d_srow = nullptr;        // n_snode indices into d_snode
   int64_t n_snode_narrow = 0;
+  // the straddling points are grouped by their number of leaves: 2, 3-4 and 5-8 (each group
+  // in point order); group g holds the indices strad_grp[g] .. strad_grp[g + 1]
+  int64_t strad_grp[4] = {0, 0, 0, 0};
   int64_t* d_sinc_off = nullptr;    // n_snode + 1
   int32_t* d_sinc = nullptr;
   // support of each straddling point in slot order (the union of its leaves' slot nodes in

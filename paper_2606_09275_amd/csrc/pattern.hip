@@ -30,6 +30,27 @@ __global__ void k_compact_index(const int32_t* __restrict__ cnt, const int64_t* 
   if (i < n && cnt[i]) out[off[i]] = i;
 }
 
+// group of a straddling point by its number of leaves (2, 3-4, 5-8) as a sort key
+__global__ void k_strad_group(const int64_t* __restrict__ strad, int64_t ns, const uint8_t* __restrict__ pnleaf,
+                              uint32_t* __restrict__ key, uint32_t* __restrict__ val) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= ns) return;
+  const int nl = pnleaf[strad[t]];
+  key[t] = nl <= 2 ? 0u : (nl <= 4 ? 1u : 2u);
+  val[t] = uint32_t(strad[t]);
+}
+__global__ void k_group_init(int64_t* __restrict__ first) {
+  if (threadIdx.x < 3) first[threadIdx.x] = -1;
+}
+// the grouped order back into the straddler list, and the first index of each group present
+__global__ void k_strad_grouped(const uint32_t* __restrict__ key, const uint32_t* __restrict__ val, int64_t ns,
+                                int64_t* __restrict__ strad, int64_t* __restrict__ first) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= ns) return;
+  strad[t] = int64_t(val[t]);
+  if (t == 0 || key[t] != key[t - 1]) first[key[t]] = t;
+}
+
 // populated leaves: a point whose domain lies in one leaf (pop), or any point (anypop)
 __global__ void k_populated(const int32_t* __restrict__ pleaf, const uint8_t* __restrict__ pnleaf, int64_t n,
                             int32_t* __restrict__ pop) {
@@ -402,6 +423,36 @@ int32_t gpu_build_pattern(mpm_mesh* m, const double* dx, const double* dl, hipSt
       MPM_HIP(hipMalloc(&m->d_grec, size_t(m->n_straddle) * kGenRec * 8));
       hipLaunchKernelGGL(k_compact_index, grid_of(n), dim3(256), 0, st, cnt.as<int32_t>(), off.as<int64_t>(), n,
                          m->d_strad);
+      // grouped by their number of leaves (a stable sort keeps point order inside a group), so
+      // that the wavefronts of the per-point kernels loop over similar numbers of leaves
+      const int64_t ns0 = m->n_straddle;
+      const int64_t nblk = (ns0 + kRsTile - 1) / kRsTile;
+      if (n >= (int64_t(1) << 32)) {
+        set_error(MPM_ESTENCIL, "octree_build: too many points for the straddler grouping");
+        return MPM_ESTENCIL;
+      }
+      DevBuf gk, gv, gkt, gvt, gh, gf;
+      if ((rc = gk.alloc(size_t(ns0) * 4, "octree_build: straddler groups")) ||
+          (rc = gv.alloc(size_t(ns0) * 4, "octree_build: straddler groups")) ||
+          (rc = gkt.alloc(size_t(ns0) * 4, "octree_build: straddler groups")) ||
+          (rc = gvt.alloc(size_t(ns0) * 4, "octree_build: straddler groups")) ||
+          (rc = gh.alloc(size_t(nblk) * 1024 + 1024, "octree_build: straddler groups")) ||
+          (rc = gf.alloc(3 * 8, "octree_build: straddler groups")))
+        return rc;
+      hipLaunchKernelGGL(k_strad_group, grid_of(ns0), dim3(256), 0, st, m->d_strad, ns0, m->d_pnleaf,
+                         gk.as<uint32_t>(), gv.as<uint32_t>());
+      uint32_t *gk2 = gk.as<uint32_t>(), *gv2 = gv.as<uint32_t>();
+      if ((rc = radix_sort(gk.as<uint32_t>(), gv.as<uint32_t>(), ns0, 2, gkt.as<uint32_t>(), gvt.as<uint32_t>(),
+                           gh.as<uint32_t>(), gh.as<uint32_t>() + size_t(nblk) * 256, st, &gk2, &gv2)))
+        return rc;
+      hipLaunchKernelGGL(k_group_init, dim3(1), dim3(64), 0, st, gf.as<int64_t>());
+      hipLaunchKernelGGL(k_strad_grouped, grid_of(ns0), dim3(256), 0, st, gk2, gv2, ns0, m->d_strad,
+                         gf.as<int64_t>());
+      int64_t first[3] = {-1, -1, -1};
+      MPM_HIP(hipMemcpyAsync(first, gf.as<int64_t>(), sizeof(first), hipMemcpyDeviceToHost, st));
+      MPM_HIP(hipStreamSynchronize(st));
+      m->strad_grp[3] = ns0;
+      for (int g = 2; g >= 0; --g) m->strad_grp[g] = first[g] >= 0 ? first[g] : m->strad_grp[g + 1];
       if ((rc = strad_leaves(m, dx, dl, st))) return rc;
     }
   }

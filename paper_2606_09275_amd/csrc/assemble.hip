@@ -675,82 +675,121 @@ __device__ __forceinline__ int sym6(int r, int m) {
   const int sum = r + m;
   return r == m ? r : (sum == 2 ? 5 : 2 + ((sum + 1) >> 1));
 }
+// LDS written by one lane of a wavefront and read by another lane of the same wavefront: the
+// wavefront's LDS operations are performed in order, so only the compiler must not move them
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The wavefront's 64 records are contiguous; they are written through LDS in four rounds
+// (tangent direction rows j = 0, 1, 2: 18 values each; then the last 20 values), so that
+// consecutive lanes store consecutive values of one record instead of 64 records at once.
+constexpr int kRecStage = 21;  // LDS row of one lane's round (20 values, odd stride)
 template <typename T>
 __global__ __launch_bounds__(64) void k_general_points(AsmArgs A) {
-  const int64_t t = int64_t(blockIdx.x) * 64 + threadIdx.x;
-  if (t >= A.n_strad) return;
-  double* rec = A.grec + t * kGenRec;
+  __shared__ double stage[64][kRecStage];
+  const int lane = threadIdx.x;
+  const int64_t t = int64_t(blockIdx.x) * 64 + lane;
+  const bool live = t < A.n_strad;
   const int64_t n = A.n;
-  const int64_t i = A.strad[t];
-  double x[3], l[3];
-  for (int q = 0; q < 3; ++q) {
-    x[q] = A.s.x[q * n + i];
-    l[q] = A.s.l[q * n + i];
-  }
-  const int32_t* lv = A.strad_leaf + t * kMaxPointLeaves;
-  T H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  double du[3] = {0.0, 0.0, 0.0};
-  for (int q = 0; q < kMaxPointLeaves && lv[q] >= 0; ++q) {
-    T s8[8], d8[8][3];
-    leaf_overlap_basis<T>(A.G, lv[q], A.cell_code[lv[q]], x, l, s8, d8);
-    for (int v = 0; v < 8; ++v) {
-      const double* uv = A.u + 3 * int64_t(A.cell_nodes[8 * int64_t(lv[q]) + v]);
-      for (int r = 0; r < 3; ++r) {
-        for (int c = 0; c < 3; ++c) H[r][c] += T(uv[r]) * d8[v][c];
-        du[r] += double(s8[v]) * uv[r];
+  PointMat<T> P;
+  T Fi[3][3];
+  T c = 0;
+  double ma[3] = {0.0, 0.0, 0.0}, c2m = 0.0;
+  bool okp = false;  // the point's record holds its values (else zeros: the call fails)
+  if (live) {
+    const int64_t i = A.strad[t];
+    double x[3], l[3];
+    for (int q = 0; q < 3; ++q) {
+      x[q] = A.s.x[q * n + i];
+      l[q] = A.s.l[q * n + i];
+    }
+    const int32_t* lv = A.strad_leaf + t * kMaxPointLeaves;
+    T H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    double du[3] = {0.0, 0.0, 0.0};
+    for (int q = 0; q < kMaxPointLeaves && lv[q] >= 0; ++q) {
+      T s8[8], d8[8][3];
+      leaf_overlap_basis<T>(A.G, lv[q], A.cell_code[lv[q]], x, l, s8, d8);
+      for (int v = 0; v < 8; ++v) {
+        const double* uv = A.u + 3 * int64_t(A.cell_nodes[8 * int64_t(lv[q]) + v]);
+        for (int r = 0; r < 3; ++r) {
+          for (int cc = 0; cc < 3; ++cc) H[r][cc] += T(uv[r]) * d8[v][cc];
+          du[r] += double(s8[v]) * uv[r];
+        }
+      }
+    }
+    int stc = 0;
+    T F[3][3];
+    for (int r = 0; r < 3; ++r)
+      for (int cc = 0; cc < 3; ++cc) F[r][cc] = H[r][cc] + (r == cc ? T(1) : T(0));
+    const T Jd = inv3(F, Fi);
+    const double Jn = A.s.Jn[i];
+    if (!isfinite(double(Jd)) || !isfinite(Jn)) stc = MPM_ENONFINITE;
+    else if (!(Jd > T(0))) stc = MPM_EDET;
+    else {
+      T B[3][3];
+      load_B<T>(A.s, n, i, B);
+      stc = material<T>(H, B, A.s.E[i], A.s.nu[i], A.s.sy[i], P);
+    }
+    if (stc) {
+      raise(A.err, stc, i);
+    } else {
+      okp = true;
+      write_point<T>(A, i, P, H, double(Jd) * Jn);
+      c = T(A.s.vol[i] / Jn);
+      if (A.vel) {  // Newmark inertia, gamma = 1, beta = 1/2
+        const double c2 = 2.0 / (A.dt * A.dt), mp = A.s.mass[i];
+        for (int r = 0; r < 3; ++r) {
+          const double vr = A.vel[r * n + i];
+          const double ar = c2 * (du[r] - A.dt * vr);
+          if (A.a_new) A.a_new[r * n + i] = ar;
+          if (A.v_new) A.v_new[r * n + i] = vr + A.dt * ar;
+          ma[r] = mp * ar;
+        }
+        c2m = double(T(2.0 * mp / (A.dt * A.dt)));
       }
     }
   }
-  int stc = 0;
-  T F[3][3], Fi[3][3];
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c) F[r][c] = H[r][c] + (r == c ? T(1) : T(0));
-  const T Jd = inv3(F, Fi);
-  const double Jn = A.s.Jn[i];
-  PointMat<T> P;
-  if (!isfinite(double(Jd)) || !isfinite(Jn)) stc = MPM_ENONFINITE;
-  else if (!(Jd > T(0))) stc = MPM_EDET;
-  else {
-    T B[3][3];
-    load_B<T>(A.s, n, i, B);
-    stc = material<T>(H, B, A.s.E[i], A.s.nu[i], A.s.sy[i], P);
-  }
-  if (stc) {  // the call fails; the rows read a zero record
-    raise(A.err, stc, i);
-    for (int q = 0; q < kGenRec; ++q) rec[q] = 0.0;
-    return;
-  }
-  write_point<T>(A, i, P, H, double(Jd) * Jn);
-  const T c = T(A.s.vol[i] / Jn);
-  double ma[3] = {0.0, 0.0, 0.0}, c2m = 0.0;
-  if (A.vel) {  // Newmark inertia, gamma = 1, beta = 1/2
-    const double c2 = 2.0 / (A.dt * A.dt), mp = A.s.mass[i];
-    for (int r = 0; r < 3; ++r) {
-      const double vr = A.vel[r * n + i];
-      const double ar = c2 * (du[r] - A.dt * vr);
-      if (A.a_new) A.a_new[r * n + i] = ar;
-      if (A.v_new) A.v_new[r * n + i] = vr + A.dt * ar;
-      ma[r] = mp * ar;
+  double* rec0 = A.grec + int64_t(blockIdx.x) * 64 * kGenRec;
+  const int64_t left = A.n_strad - int64_t(blockIdx.x) * 64;
+  const int nrec = int(left < 64 ? left : 64);
+  // one round: lane l stages nv values at stage[l][0..nv), then the wavefront stores value v of
+  // record r at rec0[r kGenRec + o + v]
+  auto flush = [&](int o, int nv) {
+    wave_lds_sync();
+    for (int e = lane; e < nrec * nv; e += 64) {
+      const int r = e / nv, v = e - nv * r;
+      rec0[int64_t(r) * kGenRec + o + v] = stage[r][v];
     }
-    c2m = double(T(2.0 * mp / (A.dt * A.dt)));
-  }
+    wave_lds_sync();
+  };
+  // c dtau for the direction e_k (x) N^T e_j, symmetric, at (3 j + k) 6
   for (int j = 0; j < 3; ++j) {
-    const T gt[3] = {P.N[j][0], P.N[j][1], P.N[j][2]};  // N^T e_j
-    for (int k = 0; k < 3; ++k) {
-      T dtk[3][3];
-      dtau_rank1<T>(P, k, gt, T(1), dtk);
-      for (int r = 0; r < 3; ++r)
-        for (int m = r; m < 3; ++m) rec[(3 * j + k) * 6 + kSym6[r][m]] = double(c * dtk[r][m]);
+    if (okp) {
+      const T gt[3] = {P.N[j][0], P.N[j][1], P.N[j][2]};  // N^T e_j
+      for (int k = 0; k < 3; ++k) {
+        T dtk[3][3];
+        dtau_rank1<T>(P, k, gt, T(1), dtk);
+        for (int r = 0; r < 3; ++r)
+          for (int m = r; m < 3; ++m) stage[lane][6 * k + kSym6[r][m]] = double(c * dtk[r][m]);
+      }
+    } else {
+      for (int q = 0; q < 18; ++q) stage[lane][q] = 0.0;
     }
+    flush(18 * j, 18);
   }
+  // c tau (symmetric), dF^-1, the inertia terms
   for (int r = 0; r < 3; ++r)
     for (int j = 0; j < 3; ++j) {
-      if (j >= r) rec[54 + kSym6[r][j]] = double(c * P.tau[r][j]);
-      rec[60 + 3 * r + j] = double(Fi[r][j]);
+      if (j >= r) stage[lane][kSym6[r][j]] = okp ? double(c * P.tau[r][j]) : 0.0;
+      stage[lane][6 + 3 * r + j] = okp ? double(Fi[r][j]) : 0.0;
     }
-  for (int r = 0; r < 3; ++r) rec[69 + r] = ma[r];
-  rec[72] = c2m;
-  rec[73] = 0.0;
+  for (int r = 0; r < 3; ++r) stage[lane][15 + r] = ma[r];
+  stage[lane][18] = c2m;
+  stage[lane][19] = 0.0;
+  flush(54, 20);
 }
 
 // Merged support of each straddling point, once per assembly: one lane per (point, leaf),
@@ -844,14 +883,6 @@ __host__ __device__ constexpr size_t row_batch_lds(int tb) {
 __host__ __device__ constexpr size_t general_rows_lds(int deg, int tb) {
   return size_t(kRowWaves) * row_batch_lds(tb) + size_t(kRowWaves * 4 * 8) + size_t(8) * col_table_size(deg) +
          size_t(9 * 8) * size_t(deg);
-}
-
-// LDS written by one lane of a wavefront and read by another lane of the same wavefront: the
-// wavefront's LDS operations are performed in order, so only the compiler must not move them
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // marks an entry of the row that no straddling point reached (a NaN no arithmetic produces)

@@ -852,15 +852,16 @@ __global__ __launch_bounds__(64) void k_general_support(AsmArgs A, int64_t t0, i
 //   Mb[r][k][j] = (c dtau(j,k) g_a)_r - (c tau)_rj g_a,k
 // from the point's record and the slot of node a in its support (four lanes per point, into
 // the wavefront's part of LDS), and adds the point's force on node a. Then the (point,
-// support slot) pairs of the batch are dealt to the lanes in order: each lane forms the 3x3
-// block sum_j Mb[r][k][j] g_b,j (+ the inertia term on the diagonal) of its slot node b and
-// adds it to that node's column of the row. All loads of a batch are independent of each
-// other, so they overlap; lanes of different points (and wavefronts) can add to one column
-// at once, so the row additions are LDS atomics (the only unordered sums of the assembly:
-// the fast path and the forces are summed in a fixed order). The row and the force are then
-// added to the values the fast path wrote. The column of a node in row a comes from an
-// open-addressing table of the row's columns in LDS (at least half of it empty, so a probe
-// sequence always ends).
+// support slot) pairs of the batch with slot node b >= a are dealt to the lanes in order:
+// each lane forms the 3x3 block sum_j Mb[r][k][j] g_b,j (+ the inertia term on the diagonal)
+// and adds it to that node's column of the row. All loads of a batch are independent of
+// each other, so they overlap; lanes of different points (and wavefronts) can add to one
+// column at once, so the row additions are LDS atomics (the only unordered sums of the
+// assembly: the fast path and the forces are summed in a fixed order). The row and the force
+// are then added to the values the fast path wrote, and each new upper block is also stored,
+// transposed, as block (b, a) of the row of b (K is symmetric). The column of a node in row a
+// comes from an open-addressing table of the row's columns in LDS (at least half of it empty,
+// so a probe sequence always ends).
 __host__ __device__ constexpr int col_table_size(int deg) {
   int p = 2;
   while (p < 2 * deg) p <<= 1;

@@ -996,25 +996,43 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_general_rows(AsmArgs A, int6
     // nodes b < a are written by the rows of those nodes (below)
     const int64_t toff = off + za;
     const int tns = pi < nb ? ns - za : 0;
+    // the lane's point's upper slots part, part + 4, ..., started at a per-point offset so that
+    // points with the same support order add to different columns at once; each slot's node
+    // and (S, grad_x S) are loaded one slot ahead of their use
+    const int rot = tns > 0 ? (5 * pi) % tns : 0;
+    auto slot_at = [&](int zz) {
+      int z = zz + rot;
+      if (z >= tns) z -= tns;
+      return toff + z;
+    };
+    int32_t nid = 0;
+    double2 n01 = {0.0, 0.0}, n23 = {0.0, 0.0};
+    if (wantK && part < tns) {
+      const int64_t o = slot_at(part);
+      nid = A.sup_id[o];
+      const double2* g = reinterpret_cast<const double2*>(A.sup_g + o * 4);
+      n01 = g[0];
+      n23 = g[1];
+    }
     entry(cb + kStep, t, za, off, ns);  // the next batch of this wavefront
     wave_lds_sync();
     if (wantK && tns > 0) {
-      // the lane's point's upper slots part, part + 4, ..., started at a per-point offset so
-      // that points with the same support order add to different columns at once; the point's
-      // Mb is read from LDS once
+      // the point's Mb is read from LDS once
       const T* Mq = mbuf + pi * kMbStride;
       T M[29];
 #pragma unroll
       for (int q = 0; q < 29; ++q) M[q] = Mq[q];
       const T ms0 = M[28] * M[27];  // inertia: (2 m / dt^2) S_a (times S_b below)
-      const int rot = (5 * pi) % tns;
       for (int zz = part; zz < tns; zz += 4) {
-        int z = zz + rot;
-        if (z >= tns) z -= tns;
-        const int64_t o = toff + z;
-        const int32_t id = A.sup_id[o];
-        const double2* g = reinterpret_cast<const double2*>(A.sup_g + o * 4);
-        const double2 g01 = g[0], g23 = g[1];
+        const int32_t id = nid;
+        const double2 g01 = n01, g23 = n23;
+        if (zz + 4 < tns) {
+          const int64_t o = slot_at(zz + 4);
+          nid = A.sup_id[o];
+          const double2* g = reinterpret_cast<const double2*>(A.sup_g + o * 4);
+          n01 = g[0];
+          n23 = g[1];
+        }
         const T sb = T(g01.x);
         const T gb[3] = {T(g01.y), T(g23.x), T(g23.y)};
         int lo = -1;  // block column of the slot's node in row a

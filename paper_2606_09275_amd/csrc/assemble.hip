@@ -30,6 +30,7 @@ struct AsmArgs {
   const int64_t* row_ptr;
   const int32_t* col;
   const int64_t* strad;
+  const int64_t* fidx;       // points whose domain lies in one leaf, in sorted order (null: all points)
   const int32_t* strad_leaf;
   const int32_t* snode;      // rows reached by straddling points
   const int32_t* srow;       // their launch order (indices into snode)
@@ -42,7 +43,7 @@ struct AsmArgs {
   double* sup_g;             // per slot: S and the spatial gradient (written by k_general_support)
   const int32_t* tpos;       // per block of those rows above the diagonal: column of the row's node in the
                              // row of the block's node
-  int64_t n, n_strad;
+  int64_t n, n_strad, n_fast;
   mpm_state_t s;
   const double* u;
   const double* lam;  // adjoint
@@ -259,12 +260,13 @@ void k_assemble_fast(AsmArgs A) {
   double(*redd)[kRow] = reinterpret_cast<double(*)[kRow]>(red_raw);
 
   const int lane = threadIdx.x;
-  const int64_t i = int64_t(blockIdx.x) * 64 + lane;
+  const int64_t j = int64_t(blockIdx.x) * 64 + lane;  // position in the list of one-leaf points
   const int64_t n = A.n;
-  const bool inr = i < n;
+  const bool inr = j < A.n_fast;
+  const int64_t i = inr ? (A.fidx ? A.fidx[j] : j) : 0;  // the point (sorted order)
   const int32_t leaf = inr ? A.pleaf[i] : -1;
   bool act = inr && A.pnleaf[i] == 1;
-  wave_segments(leaf, inr, n, seg_start, &seg_cnt);
+  wave_segments(leaf, inr, A.n_fast, seg_start, &seg_cnt);
 
   // ---------------- per-point arithmetic
   T S[8], dS[8][3], g[8][3];
@@ -1121,12 +1123,13 @@ __global__ __launch_bounds__(64) void k_external_fast(AsmArgs A) {
   __shared__ int32_t seg_start[65];
   __shared__ int32_t seg_cnt;
   const int lane = threadIdx.x;
-  const int64_t i = int64_t(blockIdx.x) * 64 + lane;
+  const int64_t j = int64_t(blockIdx.x) * 64 + lane;  // position in the list of one-leaf points
   const int64_t n = A.n;
-  const bool inr = i < n;
+  const bool inr = j < A.n_fast;
+  const int64_t i = inr ? (A.fidx ? A.fidx[j] : j) : 0;
   const int32_t leaf = inr ? A.pleaf[i] : -1;
   const bool act = inr && A.pnleaf[i] == 1;
-  wave_segments(leaf, inr, n, seg_start, &seg_cnt);
+  wave_segments(leaf, inr, A.n_fast, seg_start, &seg_cnt);
   double S[8], dS[8][3], mass = 0.0;
   if (act) {
     double x[3], l[3];
@@ -1319,9 +1322,10 @@ __device__ __forceinline__ void adjoint_point(const AsmArgs& A, int64_t i, const
 
 template <typename T>
 __global__ __launch_bounds__(64) void k_adjoint_fast(AsmArgs A) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  const int64_t n = A.n;
-  if (i >= n || A.pnleaf[i] != 1) return;
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= A.n_fast) return;
+  const int64_t i = A.fidx ? A.fidx[j] : j, n = A.n;
+  if (A.pnleaf[i] != 1) return;
   double x[3], l[3];
   for (int a = 0; a < 3; ++a) {
     x[a] = A.s.x[a * n + i];
@@ -1394,6 +1398,8 @@ static AsmArgs make_args(const mpm_mesh* m, const mpm_state_t* s) {
   A.tpos = m->d_tpos;
   A.n = m->n_point;
   A.n_strad = m->n_straddle;
+  A.fidx = m->d_fidx;
+  A.n_fast = m->n_fast;
   A.s = *s;
   A.err = m->d_err;
   return A;
@@ -1418,10 +1424,8 @@ extern "C" int32_t mpm_external_force(const mpm_mesh_t* m, const mpm_state_t* s,
   AsmArgs A = make_args(m, s);
   A.f = f_ext;
   A.K = nullptr;
-  if (m->n_point) {
-    hipLaunchKernelGGL(k_external_fast, dim3(unsigned((m->n_point + 63) / 64)), dim3(64), 0, st, A);
-    launch_rec_reduce<double>(m, st, false, nullptr);
-  }
+  if (m->n_fast) hipLaunchKernelGGL(k_external_fast, dim3(unsigned((m->n_fast + 63) / 64)), dim3(64), 0, st, A);
+  if (m->n_point) launch_rec_reduce<double>(m, st, false, nullptr);
   // every f_ext entry is written by the gather (zero where no point contributes)
   launch_gather<double>(m, st, A);
   if (m->n_snode) hipLaunchKernelGGL(k_external_rows, dim3(unsigned(m->n_snode)), dim3(64), 0, st, A);
@@ -1484,8 +1488,8 @@ static int32_t assemble_impl(const mpm_mesh_t* m, const AsmArgs& A, int32_t prec
   mpm_mesh* mm = const_cast<mpm_mesh*>(m);
   const bool timed = mm->timing && n;
   if (timed) MPM_HIP(hipEventRecord(mm->ev[0], st));
-  if (n) {
-    const dim3 grid(unsigned((n + 63) / 64));
+  if (m->n_fast) {  // the points whose domain lies in one leaf
+    const dim3 grid(unsigned((m->n_fast + 63) / 64));
     if (A.vel) {
       if (precision == MPM_F64) hipLaunchKernelGGL((k_assemble_fast<double, true>), grid, dim3(64), 0, st, A);
       else hipLaunchKernelGGL((k_assemble_fast<float, true>), grid, dim3(64), 0, st, A);
@@ -1583,8 +1587,8 @@ extern "C" int32_t mpm_assemble_adjoint(const mpm_mesh_t* m, const mpm_state_t* 
   mpm_mesh* mm = const_cast<mpm_mesh*>(m);
   const bool timed = mm->timing && n;
   if (timed) MPM_HIP(hipEventRecord(mm->ev[2], st));
-  if (n) {
-    const dim3 grid(unsigned((n + 63) / 64));
+  if (m->n_fast) {  // the points whose domain lies in one leaf
+    const dim3 grid(unsigned((m->n_fast + 63) / 64));
     if (precision == MPM_F64) hipLaunchKernelGGL(k_adjoint_fast<double>, grid, dim3(64), 0, st, A);
     else hipLaunchKernelGGL(k_adjoint_fast<float>, grid, dim3(64), 0, st, A);
   }

@@ -16,13 +16,17 @@ namespace mpm {
 // k_leaf_beta_strad (E > 0, so the integer order of the IEEE bit patterns is the order of the
 // values there).
 __global__ __launch_bounds__(64) void k_seg_beta(const double* __restrict__ E, const int32_t* __restrict__ pleaf,
-                                                 const uint8_t* __restrict__ pnleaf, int64_t n,
-                                                 const int32_t* __restrict__ wave_seg, double* __restrict__ segmax) {
-  const int64_t i = int64_t(blockIdx.x) * 64 + threadIdx.x;
+                                                 const uint8_t* __restrict__ pnleaf, const int64_t* __restrict__ fidx,
+                                                 int64_t nf, const int32_t* __restrict__ wave_seg,
+                                                 double* __restrict__ segmax) {
+  // lane j of the list of points whose domain lies in one leaf (the segments' order)
+  const int64_t j = int64_t(blockIdx.x) * 64 + threadIdx.x;
   const int lane = threadIdx.x;
   int32_t leaf = -1;
   double v = 0.0;
-  if (i < n) {
+  const bool inr = j < nf;
+  if (inr) {
+    const int64_t i = fidx ? fidx[j] : j;
     leaf = pleaf[i];
     if (pnleaf[i] == 1 && E[i] > 0.0) v = E[i];
   }
@@ -33,7 +37,7 @@ __global__ __launch_bounds__(64) void k_seg_beta(const double* __restrict__ E, c
     if (lane + off < 64 && ol == leaf) v = fmax(v, ov);
   }
   const int32_t prev = __shfl_up(leaf, 1);
-  const bool head = i < n && (lane == 0 || prev != leaf);
+  const bool head = inr && (lane == 0 || prev != leaf);
   const uint64_t hm = __ballot(head);
   if (head) segmax[wave_seg[blockIdx.x] + __popcll(hm & ((1ull << lane) - 1ull))] = v;
 }
@@ -171,9 +175,9 @@ __global__ __launch_bounds__(64) void k_ghost_gather(const int64_t* __restrict__
 int32_t ghost_apply(const mpm_mesh* m, const mpm_state_t* s, const double* u, int32_t precision, void* K, double* f,
                     hipStream_t st) {
   if (!m->n_gface) return MPM_OK;
-  if (m->n_point)
+  if (m->n_fast)
     hipLaunchKernelGGL(k_seg_beta, dim3(unsigned(m->n_wave)), dim3(64), 0, st, s->E, m->d_pleaf, m->d_pnleaf,
-                       m->n_point, m->d_wave_seg, m->d_gsegmax);
+                       m->d_fidx, m->n_fast, m->d_wave_seg, m->d_gsegmax);
   hipLaunchKernelGGL(k_leaf_beta, dim3(unsigned((m->n_leaf + 255) / 256)), dim3(256), 0, st, m->d_gsegmax,
                      m->d_leaf_seg0, m->d_leaf_nseg, m->n_leaf, m->d_gbeta);
   if (m->n_straddle)

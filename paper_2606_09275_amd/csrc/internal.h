@@ -123,6 +123,10 @@ struct mpm_mesh {
   // the straddling points are grouped by their number of leaves: 2, 3-4 and 5-8 (each group
   // in point order); group g holds the indices strad_grp[g] .. strad_grp[g + 1]
   int64_t strad_grp[4] = {0, 0, 0, 0};
+  // the points whose domain lies in one leaf, in sorted order (n_fast of them): the fast path's
+  // wavefronts and segments run over this list; null when every point is such a point
+  int64_t* d_fidx = nullptr;
+  int64_t n_fast = 0;
   int64_t* d_sinc_off = nullptr;    // n_snode + 1
   int32_t* d_sinc = nullptr;
   // support of each straddling point in slot order (the union of its leaves' slot nodes in

@@ -29,6 +29,16 @@ __global__ void k_compact_index(const int32_t* __restrict__ cnt, const int64_t* 
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n && cnt[i]) out[off[i]] = i;
 }
+// the points whose domain lies in one leaf (flags), and their leaves in list order
+__global__ void k_fast_flags(const uint8_t* __restrict__ pnleaf, int64_t n, int32_t* __restrict__ cnt) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) cnt[i] = pnleaf[i] == 1 ? 1 : 0;
+}
+__global__ void k_fast_leaf(const int64_t* __restrict__ fidx, int64_t nf, const int32_t* __restrict__ pleaf,
+                            int32_t* __restrict__ fleaf) {
+  const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j < nf) fleaf[j] = pleaf[fidx[j]];
+}
 
 // group of a straddling point by its number of leaves (2, 3-4, 5-8) as a sort key
 __global__ void k_strad_group(const int64_t* __restrict__ strad, int64_t ns, const uint8_t* __restrict__ pnleaf,
@@ -535,8 +545,32 @@ int32_t gpu_build_pattern(mpm_mesh* m, const double* dx, const double* dl, hipSt
                      m->d_col);
   MPM_HIP(hipGetLastError());
 
-  // segments of the sorted points
-  m->n_wave = (n + 63) / 64;
+  // segments of the points whose domain lies in one leaf: maximal runs of one leaf inside each
+  // 64-point wavefront of their list (the sorted points themselves when no domain straddles)
+  m->n_fast = n - ns;
+  const int64_t nfast = m->n_fast;
+  const int32_t* lf = m->d_pleaf;
+  DevBuf fcnt, foff, fleaf;
+  if (ns && nfast) {
+    if ((rc = fcnt.alloc(size_t(n) * 4, "octree_build: one-leaf points")) ||
+        (rc = foff.alloc(size_t(n + 1) * 8, "octree_build: one-leaf points")) ||
+        (rc = fleaf.alloc(size_t(nfast) * 4, "octree_build: one-leaf points")))
+      return rc;
+    MPM_HIP(hipMalloc(&m->d_fidx, size_t(nfast) * 8));
+    hipLaunchKernelGGL(k_fast_flags, grid_of(n), dim3(256), 0, st, m->d_pnleaf, n, fcnt.as<int32_t>());
+    if ((rc = scan_counts(fcnt.as<int32_t>(), n, foff.as<int64_t>(), st))) return rc;
+    int64_t cnt1 = 0;
+    if ((rc = read64(foff.as<int64_t>() + n, &cnt1))) return rc;
+    if (cnt1 != nfast) {  // every point overlaps at least one leaf once classified
+      set_error(MPM_EARG, "octree_build: point overlap counts do not add up");
+      return MPM_EARG;
+    }
+    hipLaunchKernelGGL(k_compact_index, grid_of(n), dim3(256), 0, st, fcnt.as<int32_t>(), foff.as<int64_t>(), n,
+                       m->d_fidx);
+    hipLaunchKernelGGL(k_fast_leaf, grid_of(nfast), dim3(256), 0, st, m->d_fidx, nfast, m->d_pleaf, fleaf.as<int32_t>());
+    lf = fleaf.as<int32_t>();
+  }
+  m->n_wave = (nfast + 63) / 64;
   DevBuf segc, segoff;
   MPM_HIP(hipMalloc(&m->d_wave_seg, size_t(m->n_wave + 1) * 4));
   MPM_HIP(hipMalloc(&m->d_leaf_seg0, size_t(std::max<int64_t>(1, nl)) * 4));
@@ -544,16 +578,16 @@ int32_t gpu_build_pattern(mpm_mesh* m, const double* dx, const double* dl, hipSt
   hipLaunchKernelGGL(k_fill32, grid_of(nl), dim3(256), 0, st, m->d_leaf_seg0, nl, 0);
   hipLaunchKernelGGL(k_fill32, grid_of(nl), dim3(256), 0, st, m->d_leaf_nseg, nl, 0);
   int64_t nseg = 0;
-  if (n) {
-    if ((rc = segc.alloc(size_t(n) * 4, "octree_build: segment flags")) ||
-        (rc = segoff.alloc(size_t(n + 1) * 8, "octree_build: segment offsets")))
+  if (nfast) {
+    if ((rc = segc.alloc(size_t(nfast) * 4, "octree_build: segment flags")) ||
+        (rc = segoff.alloc(size_t(nfast + 1) * 8, "octree_build: segment offsets")))
       return rc;
-    hipLaunchKernelGGL(k_seg_flags, grid_of(n), dim3(256), 0, st, m->d_pleaf, n, segc.as<int32_t>());
-    if ((rc = scan_counts(segc.as<int32_t>(), n, segoff.as<int64_t>(), st))) return rc;
-    if ((rc = read64(segoff.as<int64_t>() + n, &nseg))) return rc;
-    hipLaunchKernelGGL(k_seg_first, grid_of(n), dim3(256), 0, st, m->d_pleaf, n, segoff.as<int64_t>(), m->n_wave,
+    hipLaunchKernelGGL(k_seg_flags, grid_of(nfast), dim3(256), 0, st, lf, nfast, segc.as<int32_t>());
+    if ((rc = scan_counts(segc.as<int32_t>(), nfast, segoff.as<int64_t>(), st))) return rc;
+    if ((rc = read64(segoff.as<int64_t>() + nfast, &nseg))) return rc;
+    hipLaunchKernelGGL(k_seg_first, grid_of(nfast), dim3(256), 0, st, lf, nfast, segoff.as<int64_t>(), m->n_wave,
                        m->d_wave_seg, m->d_leaf_seg0);
-    hipLaunchKernelGGL(k_seg_count, grid_of(n), dim3(256), 0, st, m->d_pleaf, n, segoff.as<int64_t>(),
+    hipLaunchKernelGGL(k_seg_count, grid_of(nfast), dim3(256), 0, st, lf, nfast, segoff.as<int64_t>(),
                        m->d_leaf_seg0, m->d_leaf_nseg);
   } else {
     MPM_HIP(hipMemsetAsync(m->d_wave_seg, 0, 4, st));

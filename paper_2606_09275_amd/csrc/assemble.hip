@@ -1487,6 +1487,30 @@ static int32_t assemble_impl(const mpm_mesh_t* m, const AsmArgs& A, int32_t prec
   const int64_t n = m->n_point;
   mpm_mesh* mm = const_cast<mpm_mesh*>(m);
   const bool timed = mm->timing && n;
+  if (m->n_snode && general_rows_lds(int(m->max_deg), 8) > size_t(160) * 1024) {
+    set_error(MPM_ESTENCIL, "assembly: a row couples more nodes than the general-path row kernel holds in LDS");
+    return MPM_ESTENCIL;
+  }
+  // points whose domain overlaps several leaves: their update and tangent records, then their
+  // merged supports, on the mesh's second stream beside the fast path (they write only their
+  // own points' outputs and the mesh's per-point records)
+  if (m->n_snode) {
+    MPM_HIP(hipEventRecord(m->fork_ev, st));
+    MPM_HIP(hipStreamWaitEvent(m->side, m->fork_ev, 0));
+    const dim3 pgrid(unsigned((m->n_straddle + 63) / 64));
+    if (precision == MPM_F64) hipLaunchKernelGGL(k_general_points<double>, pgrid, dim3(64), 0, m->side, A);
+    else hipLaunchKernelGGL(k_general_points<float>, pgrid, dim3(64), 0, m->side, A);
+    for (int g = 0; g < 3; ++g) {  // groups of at most 2, 4 and 8 leaves per point
+      const int64_t t0 = m->strad_grp[g], t1 = m->strad_grp[g + 1];
+      if (t1 <= t0) continue;
+      const int ppw = 64 >> (g + 1);  // points per workgroup
+      const dim3 sgrid(unsigned((t1 - t0 + ppw - 1) / ppw));
+      if (precision == MPM_F64)
+        hipLaunchKernelGGL(k_general_support<double>, sgrid, dim3(64), 0, m->side, A, t0, t1, g + 1);
+      else hipLaunchKernelGGL(k_general_support<float>, sgrid, dim3(64), 0, m->side, A, t0, t1, g + 1);
+    }
+    MPM_HIP(hipEventRecord(m->join_ev, m->side));
+  }
   if (timed) MPM_HIP(hipEventRecord(mm->ev[0], st));
   if (m->n_fast) {  // the points whose domain lies in one leaf
     const dim3 grid(unsigned((m->n_fast + 63) / 64));
@@ -1507,22 +1531,8 @@ static int32_t assemble_impl(const mpm_mesh_t* m, const AsmArgs& A, int32_t prec
   if (precision == MPM_F64) launch_gather<double>(m, st, A);
   else launch_gather<float>(m, st, A);
   if (timed) MPM_HIP(hipEventRecord(mm->ev[4], st));
-  if (m->n_snode && general_rows_lds(int(m->max_deg), 8) > size_t(160) * 1024) {
-    set_error(MPM_ESTENCIL, "assembly: a row couples more nodes than the general-path row kernel holds in LDS");
-    return MPM_ESTENCIL;
-  }
   if (m->n_snode) {  // rows reached by points whose domain overlaps several leaves
-    const dim3 pgrid(unsigned((m->n_straddle + 63) / 64));
-    if (precision == MPM_F64) hipLaunchKernelGGL(k_general_points<double>, pgrid, dim3(64), 0, st, A);
-    else hipLaunchKernelGGL(k_general_points<float>, pgrid, dim3(64), 0, st, A);
-    for (int g = 0; g < 3; ++g) {  // groups of at most 2, 4 and 8 leaves per point
-      const int64_t t0 = m->strad_grp[g], t1 = m->strad_grp[g + 1];
-      if (t1 <= t0) continue;
-      const int ppw = 64 >> (g + 1);  // points per workgroup
-      const dim3 sgrid(unsigned((t1 - t0 + ppw - 1) / ppw));
-      if (precision == MPM_F64) hipLaunchKernelGGL(k_general_support<double>, sgrid, dim3(64), 0, st, A, t0, t1, g + 1);
-      else hipLaunchKernelGGL(k_general_support<float>, sgrid, dim3(64), 0, st, A, t0, t1, g + 1);
-    }
+    MPM_HIP(hipStreamWaitEvent(st, m->join_ev, 0));  // their records and supports, and the gather
     // narrow rows with LDS for kNarrowRow columns, then the rest with LDS for the widest row
     const int64_t nn = m->n_snode_narrow, nw = m->n_snode - nn;
     const int tb = precision == MPM_F64 ? 8 : 4;
@@ -1586,6 +1596,15 @@ extern "C" int32_t mpm_assemble_adjoint(const mpm_mesh_t* m, const mpm_state_t* 
   const int64_t n = m->n_point;
   mpm_mesh* mm = const_cast<mpm_mesh*>(m);
   const bool timed = mm->timing && n;
+  // points whose domain overlaps several leaves on the mesh's second stream, beside the others
+  if (m->n_straddle) {
+    MPM_HIP(hipEventRecord(m->fork_ev, st));
+    MPM_HIP(hipStreamWaitEvent(m->side, m->fork_ev, 0));
+    const dim3 grid(unsigned((m->n_straddle + 63) / 64));
+    if (precision == MPM_F64) hipLaunchKernelGGL(k_adjoint_general<double>, grid, dim3(64), 0, m->side, A);
+    else hipLaunchKernelGGL(k_adjoint_general<float>, grid, dim3(64), 0, m->side, A);
+    MPM_HIP(hipEventRecord(m->join_ev, m->side));
+  }
   if (timed) MPM_HIP(hipEventRecord(mm->ev[2], st));
   if (m->n_fast) {  // the points whose domain lies in one leaf
     const dim3 grid(unsigned((m->n_fast + 63) / 64));
@@ -1593,11 +1612,7 @@ extern "C" int32_t mpm_assemble_adjoint(const mpm_mesh_t* m, const mpm_state_t* 
     else hipLaunchKernelGGL(k_adjoint_fast<float>, grid, dim3(64), 0, st, A);
   }
   if (timed) MPM_HIP(hipEventRecord(mm->ev[3], st));
-  if (m->n_straddle) {
-    const dim3 grid(unsigned((m->n_straddle + 63) / 64));
-    if (precision == MPM_F64) hipLaunchKernelGGL(k_adjoint_general<double>, grid, dim3(64), 0, st, A);
-    else hipLaunchKernelGGL(k_adjoint_general<float>, grid, dim3(64), 0, st, A);
-  }
+  if (m->n_straddle) MPM_HIP(hipStreamWaitEvent(st, m->join_ev, 0));
   MPM_HIP(hipGetLastError());
   const int32_t rc = read_error(mm, st, "mpm_assemble_adjoint");
   if (timed) {

@@ -127,6 +127,11 @@ struct mpm_mesh {
   // wavefronts and segments run over this list; null when every point is such a point
   int64_t* d_fidx = nullptr;
   int64_t n_fast = 0;
+  // a second stream (default priority) on which the straddling points' kernels run beside the
+  // fast path, and the events that fork it from and join it to the caller's stream; created
+  // with the mesh when some domain straddles
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   int64_t* d_sinc_off = nullptr;    // n_snode + 1
   int32_t* d_sinc = nullptr;
   // support of each straddling point in slot order (the union of its leaves' slot nodes in

@@ -552,6 +552,12 @@ extern "C" void mpm_mesh_free(mpm_mesh_t* m) {
   if (m->h_cg) (void)hipHostFree(m->h_cg);
   if (m->h_word) (void)hipHostFree(m->h_word);
   if (m->cg_ev) (void)hipEventDestroy(m->cg_ev);
+  if (m->side) {
+    (void)hipStreamSynchronize(m->side);
+    (void)hipStreamDestroy(m->side);
+  }
+  if (m->fork_ev) (void)hipEventDestroy(m->fork_ev);
+  if (m->join_ev) (void)hipEventDestroy(m->join_ev);
   delete m;
 }
 

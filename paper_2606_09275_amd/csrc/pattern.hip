@@ -463,6 +463,9 @@ int32_t gpu_build_pattern(mpm_mesh* m, const double* dx, const double* dl, hipSt
       MPM_HIP(hipStreamSynchronize(st));
       m->strad_grp[3] = ns0;
       for (int g = 2; g >= 0; --g) m->strad_grp[g] = first[g] >= 0 ? first[g] : m->strad_grp[g + 1];
+      MPM_HIP(hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking));
+      MPM_HIP(hipEventCreateWithFlags(&m->fork_ev, hipEventDisableTiming));
+      MPM_HIP(hipEventCreateWithFlags(&m->join_ev, hipEventDisableTiming));
       if ((rc = strad_leaves(m, dx, dl, st))) return rc;
     }
   }

@@ -20,7 +20,11 @@
  *   - "device" pointers are HIP device memory (e.g. torch tensors on the GPU); they stay
  *     owned by the caller unless stated. All device work is ordered on the caller's
  *     hipStream_t `stream` (NULL = default stream). A mesh handle must not be used
- *     concurrently from two streams.
+ *     concurrently from two streams. On a mesh where some point domains overlap several
+ *     leaves, the assembly and adjoint calls also run the kernels of those points on a
+ *     second stream that the mesh owns (default priority), forked from `stream` by an event at
+ *     the start of the call and joined to it by another before the call's work that needs
+ *     them: seen from `stream` (and by graph capture) the call stays ordered.
  *   - No exception crosses this interface. The library is not re-entrant for one handle.
  */
 #ifndef MPM_GIMP_H
@@ -346,8 +350,9 @@ int32_t mpm_split_apply(const mpm_mesh_t* mesh, int64_t n, const uint8_t* split,
 
 /* Kernel timing for measurement tools. enable = 1: from now on HIP events bracket the fused
  * assembly kernel (single-leaf points), the row-gather kernel that writes f_int and K, and
- * the adjoint kernel on the caller's stream, and their elapsed times accumulate in the handle
- * (read at the synchronisation that ends each call); enable = 0: stop; enable = -1: only read.
+ * the adjoint kernel (single-leaf points) on the caller's stream, and their elapsed times
+ * accumulate in the handle (read at the synchronisation that ends each call; kernels on the
+ * mesh's second stream may run inside these spans); enable = 0: stop; enable = -1: only read.
  * ms_out (host, 6 doubles, may be NULL): [0] assembly-kernel ms summed, [1] its launches,
  * [2] adjoint-kernel ms, [3] adjoint launches, [4] gather-kernel ms, [5] gather launches;
  * reading resets the sums. */

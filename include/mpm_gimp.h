@@ -158,10 +158,13 @@ typedef struct {
  * records, the mesh keeps, per point whose domain overlaps several leaves, 592 bytes of device
  * memory (that point's tangent record, rewritten by every assembly) and 40 bytes per node of
  * its support (the node, the leaves holding it, and the slot's basis value and spatial
- * gradient, rewritten by every assembly), plus 4 bytes per (node, such point) incidence.
- * Errors: MPM_EARG (bad criterion or null argument), MPM_ESTENCIL (lattice or leaf counts
- * beyond the key widths, a domain over more than one leaf boundary per axis, or more than
- * 2^26 domains over several leaves), MPM_EOUTSIDE, MPM_ENONFINITE, MPM_EHIP. */
+ * gradient, rewritten by every assembly), plus 4 bytes per (node, such point) incidence, 4
+ * bytes per CSR block of the node rows those points reach, 8 bytes per point whose domain
+ * lies in one leaf (their list), and a second stream with two events.
+ * Errors: MPM_EARG (bad criterion or null argument, 2^32 points or more when some domains
+ * straddle), MPM_ESTENCIL (lattice or leaf counts beyond the key widths, a domain over more
+ * than one leaf boundary per axis, or more than 2^26 domains over several leaves),
+ * MPM_EOUTSIDE, MPM_ENONFINITE, MPM_EHIP. */
 int32_t octree_build(const mpm_refine_t* crit, const double* x, const double* l, int64_t n, void* stream,
                      mpm_mesh_t** out_mesh);
 int32_t mpm_mesh_info(const mpm_mesh_t* mesh, mpm_mesh_info_t* out);

@@ -437,9 +437,9 @@ int32_t gpu_build_pattern(mpm_mesh* m, const double* dx, const double* dl, hipSt
       // that the wavefronts of the per-point kernels loop over similar numbers of leaves
       const int64_t ns0 = m->n_straddle;
       const int64_t nblk = (ns0 + kRsTile - 1) / kRsTile;
-      if (n >= (int64_t(1) << 32)) {
-        set_error(MPM_ESTENCIL, "octree_build: too many points for the straddler grouping");
-        return MPM_ESTENCIL;
+      if (n >= (int64_t(1) << 32)) {  // the grouping sorts 32-bit point indices
+        set_error(MPM_EARG, "octree_build: 2^32 points or more with domains over several leaves");
+        return MPM_EARG;
       }
       DevBuf gk, gv, gkt, gvt, gh, gf;
       if ((rc = gk.alloc(size_t(ns0) * 4, "octree_build: straddler groups")) ||

@@ -24,7 +24,7 @@
  *     leaves, the assembly and adjoint calls also run the kernels of those points on a
  *     second stream that the mesh owns (default priority), forked from `stream` by an event at
  *     the start of the call and joined to it by another before the call's work that needs
- *     them: seen from `stream` (and by graph capture) the call stays ordered.
+ *     them: seen from `stream` the call stays ordered.
  *   - No exception crosses this interface. The library is not re-entrant for one handle.
  */
 #ifndef MPM_GIMP_H

@@ -338,6 +338,60 @@ def test_c2_jittered_sampled_rows_and_stress():
         es = rel_err(to_np(out["sigma"])[:, inv[idx]], ref["sigma"])
         log(f"[parity] c2 jittered {prec}: sampled f={ef:.2e} K rows={ek:.2e} sigma={es:.2e} ({idx.size} points)")
         assert ef <= tol and ek <= tol and es <= tol
+        # K is symmetric: 20 000 seeded entries anywhere in the matrix against their transposes
+        # (the general path writes the blocks below the diagonal of its rows as transposes)
+        es_sym = _sampled_asymmetry(rp, col, K, 20000)
+        log(f"[parity] c2 jittered {prec}: max |K_ij - K_ji| / max |K| over 20000 entries = {es_sym:.2e}")
+        assert es_sym <= (1e-13 if prec == "f64" else 1e-6)
+
+
+def _sampled_asymmetry(rp, col, K, n):
+    rng = np.random.default_rng(17)
+    e = rng.integers(0, K.size, n)
+    rows = np.searchsorted(rp, e, side="right") - 1
+    worst = 0.0
+    for ent, i in zip(e, rows):
+        j = int(col[ent])
+        a0, a1 = rp[j], rp[j + 1]
+        k = a0 + np.searchsorted(col[a0:a1], i)
+        assert k < a1 and col[k] == i, "the pattern is symmetric"
+        worst = max(worst, abs(K[ent] - K[k]))
+    return worst / np.abs(K).max()
+
+
+def test_c2_jittered_adjoint_64_points():
+    """Adjoint of straddling points at full size: dL/d(E, nu, sigma_y, V_n) of 64 seeded points
+    whose domains overlap several leaves (32 over two leaves, 32 over more) against the oracle
+    on those points alone (a point's gradient depends only on its own support)."""
+    from paper_2606_09275_amd.mesh import Mesh
+    w = W.get("c2")
+    o = OracleMesh(w.crit())
+    lv = o.leaves()
+    nodes = o.nodes()
+    ps = W.jitter_points(w, W.make_points(w, lv[:, :3], lv[:, 3]), 0)
+    st = W.make_state(w, ps)
+    u = W.make_u(w, nodes)
+    lam = W.make_lambda(w, nodes)
+    m = Mesh(w.crit(), torch.from_numpy(ps.x).cuda(), torch.from_numpy(ps.l).cuda())
+    a = m.arrays()
+    perm, nleaf = to_np(a["perm"]), to_np(a["point_nleaf"])
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(perm.size)
+    nl = nleaf[inv]  # leaves per point, original order
+    rng = np.random.default_rng(21)
+    pts = np.concatenate([rng.choice(np.nonzero(nl == 2)[0], 32, replace=False),
+                          rng.choice(np.nonzero(nl > 2)[0], 32, replace=False)])
+    sub = OracleMesh(w.crit())
+    sub.set_points(ps.x[:, pts], ps.l[:, pts])
+    ss = {k: (v[..., pts] if isinstance(v, np.ndarray) else v) for k, v in st.items()}
+    ref = sub.adjoint(ss, u, lam)
+    s_dev = m.sorted_state(st)
+    for prec, tol in (("f64", TOL64), ("f32k", 2e-4)):
+        g = m.adjoint(s_dev, torch.from_numpy(u).cuda(), torch.from_numpy(lam).cuda(), prec)
+        torch.cuda.synchronize()
+        errs = {k: rel_err(to_np(g[k])[inv[pts]], ref[k]) for k in ("dE", "dnu", "dsy", "dV")}
+        log(f"[parity] c2 jittered adjoint {prec} 64 points: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+        assert all(v <= tol for v in errs.values()), errs
 
 
 def test_c2_body_force_total(c2):

@@ -847,9 +847,9 @@ __global__ __launch_bounds__(64) void k_general_support(AsmArgs A, int64_t t0, i
   }
 }
 
-// The rows those points reach: one workgroup of four wavefronts per node a, which share the
+// The rows those points reach: one workgroup of W wavefronts per node a, which share the
 // row's accumulator; each wavefront takes batches of 16 of the node's straddling points (batch
-// b of the node goes to wavefront b mod 4). For K_ab = V grad_x S_a . a . grad_x S_b a batch
+// b of the node goes to wavefront b mod W). For K_ab = V grad_x S_a . a . grad_x S_b a batch
 // first forms, for each of its points, the 27 values
 //   Mb[r][k][j] = (c dtau(j,k) g_a)_r - (c tau)_rj g_a,k
 // from the point's record and the slot of node a in its support (four lanes per point, into
@@ -871,7 +871,10 @@ __host__ __device__ constexpr int col_table_size(int deg) {
 }
 __device__ __forceinline__ unsigned col_hash(int32_t id, int p) { return (unsigned(id) * 2654435761u) & unsigned(p - 1); }
 
-constexpr int kRowWaves = 4;   // wavefronts per row of k_general_rows
+// wavefronts per row of k_general_rows: rows of at most kNarrowRow columns take two (more rows
+// in flight per CU; two beat one, four and eight), wider rows four (their LDS admits fewer
+// workgroups per CU)
+constexpr int kRowWavesNarrow = 2, kRowWavesWide = 4;
 constexpr int kRowBatch = 16;  // straddling points per batch of one wavefront
 // per point: Mb (27 values), S_a, 2 m / dt^2; the stride keeps 16-byte alignment and starts
 // consecutive points 4 banks apart, so the lanes of the points of one task group (which read
@@ -882,17 +885,17 @@ constexpr int kMbStride = 34;
 __host__ __device__ constexpr size_t row_batch_lds(int tb) {
   return size_t(kRowBatch * kMbStride) * size_t(tb);
 }
-// LDS bytes of k_general_rows for rows of at most deg block columns, working type of size tb
-__host__ __device__ constexpr size_t general_rows_lds(int deg, int tb) {
-  return size_t(kRowWaves) * row_batch_lds(tb) + size_t(kRowWaves * 4 * 8) + size_t(8) * col_table_size(deg) +
-         size_t(9 * 8) * size_t(deg);
+// LDS bytes of k_general_rows with w wavefronts for rows of at most deg block columns, working
+// type of size tb
+__host__ __device__ constexpr size_t general_rows_lds(int deg, int tb, int w) {
+  return size_t(w) * row_batch_lds(tb) + size_t(w * 4 * 8) + size_t(8) * col_table_size(deg) + size_t(9 * 8) * size_t(deg);
 }
 
 // marks an entry of the row that no straddling point reached (a NaN no arithmetic produces)
 constexpr long long kUntouched = 0x7ff4d00d0000beefll;
 
-template <typename T>
-__global__ __launch_bounds__(64 * kRowWaves) void k_general_rows(AsmArgs A, int64_t row0) {
+template <typename T, int W>
+__global__ __launch_bounds__(64 * W) void k_general_rows(AsmArgs A, int64_t row0) {
   extern __shared__ __align__(16) unsigned char gsm[];
   // the row's entry in the straddler tables; each XCD takes one contiguous range of rows, so
   // that rows sharing straddling points read them through one L2
@@ -905,23 +908,23 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_general_rows(AsmArgs A, int6
   // LDS: the wavefronts' batch buffers (fixed size, first, so their alignment is known), the
   // wavefronts' forces, the column table and the row
   unsigned char* wb = gsm + size_t(wave) * row_batch_lds(sizeof(T));
-  double* fsum = reinterpret_cast<double*>(gsm + size_t(kRowWaves) * row_batch_lds(sizeof(T)));  // [kRowWaves][3]
+  double* fsum = reinterpret_cast<double*>(gsm + size_t(W) * row_batch_lds(sizeof(T)));  // [W][3]
   // table entries: node id (high 32 bits) and column (low 32 bits); empty = all ones
-  unsigned long long* ctab = reinterpret_cast<unsigned long long*>(fsum + kRowWaves * 4);
+  unsigned long long* ctab = reinterpret_cast<unsigned long long*>(fsum + W * 4);
   // the row in FP64, entry (r, k) of block column c at (3 r + k) deg + c: the lanes of one
   // addition (one entry, different columns) fall into consecutive banks
   double* acc = reinterpret_cast<double*>(ctab + tp);
   T* mbuf = reinterpret_cast<T*>(wb);  // [kRowBatch][kMbStride]
   const bool wantK = A.K != nullptr;
   if (wantK) {
-    for (int j = tid; j < 9 * deg; j += 64 * kRowWaves) acc[j] = 0.0;
-    for (int j = tid; j < tp; j += 64 * kRowWaves) ctab[j] = ~0ull;
+    for (int j = tid; j < 9 * deg; j += 64 * W) acc[j] = 0.0;
+    for (int j = tid; j < tp; j += 64 * W) ctab[j] = ~0ull;
   }
   __syncthreads();
   // the block column of a itself (the last of the force slots, unused by the forces)
-  int* sja = reinterpret_cast<int*>(fsum + kRowWaves * 4 - 1);
+  int* sja = reinterpret_cast<int*>(fsum + W * 4 - 1);
   if (wantK) {
-    for (int j = tid; j < deg; j += 64 * kRowWaves) {
+    for (int j = tid; j < deg; j += 64 * W) {
       const int32_t id = A.col[r0 + 3 * j] / 3;
       if (id == na) *sja = j;
       const unsigned long long ent = (static_cast<unsigned long long>(unsigned(id)) << 32) | unsigned(j);
@@ -932,7 +935,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_general_rows(AsmArgs A, int6
   __syncthreads();
   double fa[3] = {0.0, 0.0, 0.0};
   const int64_t c0 = A.sinc_off[rb], c1 = A.sinc_off[rb + 1];
-  constexpr int64_t kStep = int64_t(kRowWaves) * kRowBatch;
+  constexpr int64_t kStep = int64_t(W) * kRowBatch;
   // lanes pi, pi + 16, pi + 32, pi + 48 hold the batch's point pi: the point, the slot of node
   // a in its support, its support slots; the next batch's are loaded while this one runs
   const int pi = lane & (kRowBatch - 1), part = lane >> 4;
@@ -1072,7 +1075,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_general_rows(AsmArgs A, int6
   __syncthreads();
   if (tid < 3) {
     double f = 0.0;
-    for (int w = 0; w < kRowWaves; ++w) f += fsum[3 * w + tid];
+    for (int w = 0; w < W; ++w) f += fsum[3 * w + tid];
     A.f[3 * na + tid] += f;
   }
   if (wantK) {
@@ -1082,7 +1085,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_general_rows(AsmArgs A, int6
     // gather, symmetric to rounding)
     T* Kout = reinterpret_cast<T*>(A.K);
     const int ja = *sja, nu = deg - ja;
-    for (int q = tid; q < 9 * nu; q += 64 * kRowWaves) {
+    for (int q = tid; q < 9 * nu; q += 64 * W) {
       const int r = q / (3 * nu), rem = q - r * 3 * nu, cu = rem / 3, k = rem - 3 * cu, c = ja + cu;
       double* ap = acc + (3 * r + k) * deg + c;
       const double v = *ap;
@@ -1101,7 +1104,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void k_general_rows(AsmArgs A, int6
     // store three consecutive values. That block is written by no other workgroup: the row of
     // c holds only its blocks from c on.
     const int64_t tb0 = r0 / 9;
-    for (int q = tid; q < 9 * (nu - 1); q += 64 * kRowWaves) {
+    for (int q = tid; q < 9 * (nu - 1); q += 64 * W) {
       const int cu = 1 + q / 9, rem = q - 9 * (cu - 1), k = rem / 3, r = rem - 3 * k, c = ja + cu;
       const double kv = acc[(3 * r + k) * deg + c];
       if (__double_as_longlong(kv) == kUntouched) continue;
@@ -1487,7 +1490,7 @@ static int32_t assemble_impl(const mpm_mesh_t* m, const AsmArgs& A, int32_t prec
   const int64_t n = m->n_point;
   mpm_mesh* mm = const_cast<mpm_mesh*>(m);
   const bool timed = mm->timing && n;
-  if (m->n_snode && general_rows_lds(int(m->max_deg), 8) > size_t(160) * 1024) {
+  if (m->n_snode && general_rows_lds(int(m->max_deg), 8, kRowWavesWide) > size_t(160) * 1024) {
     set_error(MPM_ESTENCIL, "assembly: a row couples more nodes than the general-path row kernel holds in LDS");
     return MPM_ESTENCIL;
   }
@@ -1537,16 +1540,17 @@ static int32_t assemble_impl(const mpm_mesh_t* m, const AsmArgs& A, int32_t prec
     const int64_t nn = m->n_snode_narrow, nw = m->n_snode - nn;
     const int tb = precision == MPM_F64 ? 8 : 4;
     const int dn = std::min<int>(kNarrowRow, int(m->max_deg));
+    constexpr int wn = kRowWavesNarrow, ww = kRowWavesWide;
     if (precision == MPM_F64) {
-      if (nn) hipLaunchKernelGGL(k_general_rows<double>, dim3(unsigned(nn)), dim3(64 * kRowWaves),
-                                 general_rows_lds(dn, tb), st, A, int64_t(0));
-      if (nw) hipLaunchKernelGGL(k_general_rows<double>, dim3(unsigned(nw)), dim3(64 * kRowWaves),
-                                 general_rows_lds(int(m->max_deg), tb), st, A, nn);
+      if (nn) hipLaunchKernelGGL((k_general_rows<double, wn>), dim3(unsigned(nn)), dim3(64 * wn),
+                                 general_rows_lds(dn, tb, wn), st, A, int64_t(0));
+      if (nw) hipLaunchKernelGGL((k_general_rows<double, ww>), dim3(unsigned(nw)), dim3(64 * ww),
+                                 general_rows_lds(int(m->max_deg), tb, ww), st, A, nn);
     } else {
-      if (nn) hipLaunchKernelGGL(k_general_rows<float>, dim3(unsigned(nn)), dim3(64 * kRowWaves),
-                                 general_rows_lds(dn, tb), st, A, int64_t(0));
-      if (nw) hipLaunchKernelGGL(k_general_rows<float>, dim3(unsigned(nw)), dim3(64 * kRowWaves),
-                                 general_rows_lds(int(m->max_deg), tb), st, A, nn);
+      if (nn) hipLaunchKernelGGL((k_general_rows<float, wn>), dim3(unsigned(nn)), dim3(64 * wn),
+                                 general_rows_lds(dn, tb, wn), st, A, int64_t(0));
+      if (nw) hipLaunchKernelGGL((k_general_rows<float, ww>), dim3(unsigned(nw)), dim3(64 * ww),
+                                 general_rows_lds(int(m->max_deg), tb, ww), st, A, nn);
     }
   }
   // ghost penalty (Section 4): after every point term, before the residual

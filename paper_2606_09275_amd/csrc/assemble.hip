@@ -18,6 +18,7 @@ struct AsmArgs {
   const int32_t* pleaf;
   const uint8_t* pnleaf;
   const int32_t* wave_seg;
+  const int32_t* gorder;     // the row gather's node order (null: ascending)
   const int32_t* leaf_seg0;
   const int32_t* leaf_nseg;
   const int32_t* con_off;
@@ -544,11 +545,12 @@ __device__ __forceinline__ int64_t xcd_block(int64_t w, int64_t n) {
 // issued without branches (indices past the end repeat the last one and are not added), so
 // that they are all in flight together.
 template <typename T, bool WANTK, bool MASS>
-__global__ __launch_bounds__(64) void k_gather(AsmArgs A, int64_t n_node) {
+__global__ __launch_bounds__(64) void k_gather(AsmArgs A, int64_t row0) {
   extern __shared__ __align__(16) unsigned char gsm[];
   T* acc = reinterpret_cast<T*>(gsm);
   constexpr int kBatch = 4;  // contributions in flight per step: 52 registers, eight wavefronts per SIMD
-  const int64_t nd = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t q = row0 + xcd_block(blockIdx.x, gridDim.x);
+  const int64_t nd = A.gorder ? A.gorder[q] : q;
   const int lane = threadIdx.x;
   const int64_t base = A.row_ptr[3 * nd];
   const int deg = int((A.row_ptr[3 * nd + 1] - base) / 3);
@@ -642,18 +644,25 @@ __global__ __launch_bounds__(64) void k_gather(AsmArgs A, int64_t n_node) {
   if (lane < 3) A.f[3 * nd + lane] = fsum;
 }
 
+// nodes [row0, row0 + count) of the gather order, LDS for rows of at most deg block columns
+template <typename T>
+static void gather_part(hipStream_t st, const AsmArgs& A, int64_t row0, int64_t count, int64_t deg) {
+  if (count <= 0) return;
+  const dim3 grid(static_cast<unsigned>(count));
+  const size_t lds = size_t(9) * size_t(deg) * sizeof(T);
+  if (A.K && A.segM) hipLaunchKernelGGL((k_gather<T, true, true>), grid, dim3(64), lds, st, A, row0);
+  else if (A.K) hipLaunchKernelGGL((k_gather<T, true, false>), grid, dim3(64), lds, st, A, row0);
+  else hipLaunchKernelGGL((k_gather<T, false, false>), grid, dim3(64), 0, st, A, row0);
+}
 template <typename T>
 static void launch_gather(const mpm_mesh* m, hipStream_t st, const AsmArgs& A) {
   if (!m->n_node) return;
-  const dim3 grid(unsigned(m->n_node));
-  if (A.K && A.segM)
-    hipLaunchKernelGGL((k_gather<T, true, true>), grid, dim3(64), size_t(9) * m->max_deg * sizeof(T), st, A,
-                       m->n_node);
-  else if (A.K)
-    hipLaunchKernelGGL((k_gather<T, true, false>), grid, dim3(64), size_t(9) * m->max_deg * sizeof(T), st, A,
-                       m->n_node);
-  else
-    hipLaunchKernelGGL((k_gather<T, false, false>), grid, dim3(64), 0, st, A, m->n_node);
+  if (!m->d_gorder) {  // every row narrow: one launch in node order
+    gather_part<T>(st, A, 0, m->n_node, m->max_deg);
+    return;
+  }
+  gather_part<T>(st, A, 0, m->n_gnarrow, std::min<int64_t>(kGatherNarrow, m->max_deg));
+  gather_part<T>(st, A, m->n_gnarrow, m->n_node - m->n_gnarrow, m->max_deg);
 }
 
 // ------------------------------------------------------------------ general path
@@ -1377,6 +1386,7 @@ static AsmArgs make_args(const mpm_mesh* m, const mpm_state_t* s) {
   A.pleaf = m->d_pleaf;
   A.pnleaf = m->d_pnleaf;
   A.wave_seg = m->d_wave_seg;
+  A.gorder = m->d_gorder;
   A.leaf_seg0 = m->d_leaf_seg0;
   A.leaf_nseg = m->d_leaf_nseg;
   A.con_off = m->d_con_off;

@@ -55,6 +55,7 @@ __host__ __device__ inline uint64_t compact3(uint64_t v) {
 constexpr int kMaxPointLeaves = 8; // leaves a point domain may overlap (one boundary per axis)
 constexpr int kGenRec = 74;        // doubles per straddling point: the general path's tangent record
 constexpr int kNarrowRow = 128;    // rows of at most this many block columns run with less LDS
+constexpr int kGatherNarrow = 64;  // the row gather's split: rows of at most this many block columns
 
 // per-leaf constraint code: bits 0..7 hanging vertices, bits 8..10 child index in the parent
 __host__ __device__ inline int code_hmask(int32_t code) { return code & 0xff; }
@@ -120,6 +121,11 @@ struct mpm_mesh {
   // kernel takes less LDS), then the rest; n_snode_narrow of the first kind
   int32_t* d_srow = nullptr;        // n_snode indices into d_snode
   int64_t n_snode_narrow = 0;
+  // when some row has more than kGatherNarrow block columns: the nodes in the row gather's launch
+  // order, those of at most kGatherNarrow columns first (their launch takes less LDS), each part
+  // ascending; n_gnarrow of the first kind (null when every row is narrow)
+  int32_t* d_gorder = nullptr;
+  int64_t n_gnarrow = 0;
   // the straddling points are grouped by their number of leaves: 2, 3-4 and 5-8 (each group
   // in point order); group g holds the indices strad_grp[g] .. strad_grp[g + 1]
   int64_t strad_grp[4] = {0, 0, 0, 0};

@@ -541,7 +541,7 @@ extern "C" void mpm_mesh_free(mpm_mesh_t* m) {
                   m->d_hang_ijk, m->d_hang_sup, m->d_hang_w, m->d_hang_owner, m->d_perm, m->d_pleaf, m->d_pnleaf,
                   m->d_row_ptr, m->d_col, m->d_wave_seg, m->d_leaf_seg0, m->d_leaf_nseg, m->d_con_off, m->d_con_seg, m->d_con_bp, m->d_bpos,
                   m->d_segK, m->d_segF, m->d_segM, m->d_red1, m->d_red2, m->d_strad, m->d_strad_leaf, m->d_grec, m->d_err,
-                  m->d_partial, m->d_scratch, m->d_stage, m->d_cellmap, m->d_cg, m->d_gm, m->d_split, m->d_snode, m->d_srow, m->d_sinc_off, m->d_sinc, m->d_sup_off, m->d_sup_id, m->d_sup_src, m->d_sup_g, m->d_tpos, m->d_fidx, m->d_gf_leaf, m->d_gf_nodes,
+                  m->d_partial, m->d_scratch, m->d_stage, m->d_cellmap, m->d_cg, m->d_gm, m->d_split, m->d_snode, m->d_srow, m->d_sinc_off, m->d_sinc, m->d_sup_off, m->d_sup_id, m->d_sup_src, m->d_sup_g, m->d_tpos, m->d_fidx, m->d_gorder, m->d_gf_leaf, m->d_gf_nodes,
                   m->d_gf_G, m->d_gf_h, m->d_gf_sc, m->d_gf_bpos, m->d_gnode, m->d_gcon_off, m->d_gcon, m->d_gbeta, m->d_gsegmax};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);

@@ -694,6 +694,26 @@ int32_t gpu_build_pattern(mpm_mesh* m, const double* dx, const double* dl, hipSt
     set_error(MPM_ESTENCIL, "octree_build: node row too wide or too many leaves for the gather");
     return MPM_ESTENCIL;
   }
+  // the row gather's launch order when some rows are wide (the LDS of a launch is sized for
+  // its widest row): narrow rows first, from their widths on the host
+  if (m->max_deg > kGatherNarrow && nn) {
+    std::vector<int64_t> rp(size_t(3 * nn + 1));
+    MPM_HIP(hipMemcpyAsync(rp.data(), m->d_row_ptr, rp.size() * 8, hipMemcpyDeviceToHost, st));
+    MPM_HIP(hipStreamSynchronize(st));
+    std::vector<int32_t> order;
+    order.reserve(size_t(nn));
+    m->n_gnarrow = 0;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int64_t a = 0; a < nn; ++a) {
+        const bool narrow = (rp[size_t(3 * a + 1)] - rp[size_t(3 * a)]) / 3 <= kGatherNarrow;
+        if (narrow != (pass == 0)) continue;
+        order.push_back(int32_t(a));
+        if (narrow) ++m->n_gnarrow;
+      }
+    MPM_HIP(hipMalloc(&m->d_gorder, order.size() * 4));
+    MPM_HIP(hipMemcpyAsync(m->d_gorder, order.data(), order.size() * 4, hipMemcpyHostToDevice, st));
+    MPM_HIP(hipStreamSynchronize(st));
+  }
 
   // ghost couplings: block column of every face node pair in the first node's row
   if (nf) {
